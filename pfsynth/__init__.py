@@ -1,0 +1,130 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the benchmark.
+
+This module only draws inputs: greyscale videos of a disk moving over a flat
+background with Gaussian pixel noise, shaped like the paper's tracking workload
+(arXiv:2308.00763, Sec. 5, verification paragraph: a circular object moving in
+the plane, one foreground and one background intensity, added Gaussian noise,
+bouncing specularly off a wall).  It holds none of the particle filter's
+arithmetic and is imported by both the oracle-side tests and the GPU side.
+
+Conventions: x is the column, y is the row; frames are (H, W) uint8, row-major.
+The object at frame t is drawn at an integer centre; a pixel (i, j) is
+foreground when (j - cx)^2 + (i - cy)^2 < r^2.  Noise N(0, sigma^2) is added,
+rounded half up and clipped to [0, 255].
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class Video:
+    frames: np.ndarray      # (T, H, W) uint8
+    centres: np.ndarray     # (T, 2) float64, ground-truth (x, y) per frame
+    radius: int
+    noise_sigma: float
+
+
+def _reflect(p: int, v: int, lo: int, hi: int):
+    """Advance p by v inside [lo, hi], reflecting specularly off both walls."""
+    p = p + v
+    while p < lo or p > hi:
+        if p < lo:
+            p = 2 * lo - p
+            v = -v
+        if p > hi:
+            p = 2 * hi - p
+            v = -v
+    return p, v
+
+
+def trajectory(T: int, start, velocity, width: int, height: int, radius: int,
+               bounce: bool = False) -> np.ndarray:
+    """Integer object centres for frames 0..T-1 (constant velocity, optional bounce)."""
+    cx, cy = int(start[0]), int(start[1])
+    vx, vy = int(velocity[0]), int(velocity[1])
+    out = np.zeros((T, 2), dtype=np.float64)
+    for t in range(T):
+        out[t] = (cx, cy)
+        if bounce:
+            cx, vx = _reflect(cx, vx, radius, width - 1 - radius)
+            cy, vy = _reflect(cy, vy, radius, height - 1 - radius)
+        else:
+            cx, cy = cx + vx, cy + vy
+    return out
+
+
+def render(width: int, height: int, centres: np.ndarray, radius: int, noise_sigma: float,
+           seed: int, fg: int = 228, bg: int = 100) -> np.ndarray:
+    """Draw the frames for the given centres with PCG64(seed) noise."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    T = centres.shape[0]
+    video = np.empty((T, height, width), dtype=np.uint8)
+    r2 = radius * radius
+    for t in range(T):
+        cx, cy = int(centres[t, 0]), int(centres[t, 1])
+        img = np.full((height, width), float(bg), dtype=np.float32)
+        y0, y1 = max(cy - radius, 0), min(cy + radius, height - 1)
+        x0, x1 = max(cx - radius, 0), min(cx + radius, width - 1)
+        if y0 <= y1 and x0 <= x1:
+            jj, ii = np.meshgrid(np.arange(x0, x1 + 1), np.arange(y0, y1 + 1))
+            inside = (jj - cx) ** 2 + (ii - cy) ** 2 < r2
+            sub = img[y0:y1 + 1, x0:x1 + 1]
+            sub[inside] = float(fg)
+        if noise_sigma > 0:
+            img += rng.standard_normal((height, width), dtype=np.float32) * np.float32(noise_sigma)
+        video[t] = np.clip(np.floor(img + np.float32(0.5)), 0, 255).astype(np.uint8)
+    return video
+
+
+def moving_disk(width: int, height: int, T: int, radius: int, start, velocity,
+                noise_sigma: float, seed: int, bounce: bool = False,
+                fg: int = 228, bg: int = 100) -> Video:
+    centres = trajectory(T, start, velocity, width, height, radius, bounce)
+    frames = render(width, height, centres, radius, noise_sigma, seed, fg, bg)
+    return Video(frames, centres, radius, float(noise_sigma))
+
+
+# ---------------------------------------------------------------------------
+# Named workloads.  Sizes follow the paper's tracking workload scaled to the
+# configurations this library is measured on.
+
+@dataclass
+class Workload:
+    name: str
+    width: int
+    height: int
+    frames: int
+    radius: int
+    noise_sigma: float
+    n_particles: int
+    start: tuple
+    velocity: tuple
+    filter_seed: int
+    video_seed: int
+    drift: tuple = (1.0, -2.0)
+    sigma: tuple = (5.0, 2.0)
+
+
+WORKLOADS = {
+    # single filter, 128x128, 10 frames, r=5, N=1000 (parity case)
+    "disk128_n1000": Workload("disk128_n1000", 128, 128, 10, 5, 2.0, 1000,
+                              (64, 64), (1, -2), 0, 1),
+    # precision sweep: 1024x1024, 100 frames, r=5, N=2^20
+    "disk1024_n1m": Workload("disk1024_n1m", 1024, 1024, 100, 5, 2.0, 1 << 20,
+                             (512, 512), (1, -2), 0, 2),
+    # large-N stress: 512x512, 50 frames, r=8, noise sigma 8, N=2^24
+    "disk512_r8_n16m": Workload("disk512_r8_n16m", 512, 512, 50, 8, 8.0, 1 << 24,
+                                (256, 256), (1, -2), 0, 3),
+    # the paper's accuracy video: 512x512, 100 frames, bouncing off y = 0
+    "bounce512_n128": Workload("bounce512_n128", 512, 512, 100, 5, 2.0, 128,
+                               (256, 200), (1, -4), 0, 7),
+}
+
+
+def workload_video(w: Workload, frames: int | None = None, bounce: bool = False) -> Video:
+    T = w.frames if frames is None else frames
+    return moving_disk(w.width, w.height, T, w.radius, w.start, w.velocity, w.noise_sigma,
+                       w.video_seed, bounce=bounce)
