@@ -1,0 +1,187 @@
+/*
+ * pf.h -- C ABI of libpf, a particle filter for tracking an object in a
+ * greyscale video, with its per-frame step written in HIP for AMD gfx950.
+ *
+ * The method is the bootstrap sampling-importance-resampling (SIR) particle
+ * filter of Schieffer et al., "Boosting the Performance of Object Tracking with
+ * a Half-Precision Particle Filter on GPU" (arXiv:2308.00763):
+ *   Sec. 2   -- the three stages per time step (propagate, weight, resample);
+ *   Sec. 4   -- Eq. (1)-(2) transition model, Eq. (3)-(4) log-likelihood over
+ *               the pixels around a particle, the maximum, Eq. (5) weights,
+ *               normalisation into a cumulative distribution, systematic
+ *               resampling, and the precision variants (double, single, half);
+ *   Sec. 5   -- the workload: a disk moving over a flat background with
+ *               Gaussian noise.
+ *
+ * Conventions shared by every call:
+ *   - Coordinates are in pixels; x is the column, y is the row.  A particle at
+ *     (x, y) looks at pixel (floor(x + 1/2), floor(y + 1/2)).
+ *   - Frames are H x W uint8 in device memory, row-major, `row_pitch` bytes
+ *     between rows (row_pitch >= W).
+ *   - The library never allocates device memory.  The caller allocates the
+ *     workspace (pf_workspace_bytes) and owns it; a filter handle must not
+ *     outlive its workspace.
+ *   - All device work of a filter is ordered on the HIP stream given at
+ *     pf_init; calls return before that work finishes unless stated.
+ *   - Every function returns PF_OK (0) or a pf_status code; the text of the
+ *     last error on the calling thread is available from pf_last_error().
+ *     No C++ exception crosses this interface.
+ */
+#ifndef PF_H
+#define PF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PF_ABI_VERSION 1
+
+typedef enum pf_status {
+    PF_OK = 0,
+    PF_ERR_INVALID_ARG = 1, /* a parameter or pointer is out of its documented range */
+    PF_ERR_WORKSPACE = 2,   /* the workspace is smaller than pf_workspace_bytes() */
+    PF_ERR_HIP = 3,         /* a HIP runtime call failed; the handle is poisoned */
+    PF_ERR_STATE = 4        /* the handle is poisoned by an earlier PF_ERR_HIP */
+} pf_status;
+
+/* Arithmetic precision of the step (paper Sec. 4, implementation paragraph:
+ * one filter templated over double, float and half).
+ *   PF_F64  -- positions, log-likelihoods, weights and the cumulative
+ *              distribution in double; the baseline.
+ *   PF_F32  -- positions in float (offsets from an integer origin), weights,
+ *              normaliser and distribution in float; the distribution's
+ *              carried tile offsets in compensated (two-float) arithmetic.
+ *   PF_F16  -- positions in half (offsets from an integer origin), propagated
+ *              with packed half arithmetic, two particles per 32-bit register;
+ *              normaliser, distribution and estimate as in PF_F32.
+ *   PF_BF16 -- positions in bfloat16 (offsets from an integer origin),
+ *              propagated in float and rounded once to bfloat16; the rest as
+ *              in PF_F32. */
+typedef enum pf_dtype { PF_F64 = 0, PF_F32 = 1, PF_F16 = 2, PF_BF16 = 3 } pf_dtype;
+
+/* Normalisation of the log-likelihood, Eq. (3): the sum over the N_d disk
+ * pixels is divided by kappa * N_d (PF_LIK_MEAN, the paper's reading) or by
+ * kappa alone (PF_LIK_SUM). */
+typedef enum pf_lik_norm { PF_LIK_MEAN = 0, PF_LIK_SUM = 1 } pf_lik_norm;
+
+/* Keep the per-particle diagnostics of the last step (weights before
+ * resampling, ancestors, disk sums) so that pf_export / pf_export_step can
+ * return them.  Costs extra workspace and memory traffic; off by default. */
+#define PF_FLAG_DIAGNOSTICS 1u
+
+typedef struct pf_params {
+    uint32_t struct_size;  /* must be sizeof(pf_params) */
+    int32_t dtype;         /* pf_dtype */
+    int64_t n_particles;   /* N, 1 <= N <= 2^28 */
+    int32_t width;         /* W, frame columns, > 2 * disk_radius */
+    int32_t height;        /* H, frame rows, > 2 * disk_radius */
+    int32_t disk_radius;   /* r, 1 <= r <= 32; pixels with dx^2 + dy^2 < r^2 */
+    int32_t fg;            /* foreground intensity (paper: 228), 0..255 */
+    int32_t bg;            /* background intensity (paper: 100), 0..255 */
+    int32_t lik_norm;      /* pf_lik_norm */
+    double kappa;          /* likelihood scale (paper: 50), > 0 */
+    double x0, y0;         /* initial object position; every particle starts here */
+    double drift_x;        /* mean displacement per frame, Eq. (1): 1.0 */
+    double drift_y;        /* Eq. (2); -2.0 for an object moving toward y = 0 */
+    double sigma_x;        /* transition standard deviation, Eq. (1): 5.0 */
+    double sigma_y;        /* Eq. (2): 2.0 */
+    uint64_t seed;         /* key of the counter-based random streams */
+    uint32_t stream_id;    /* filter id inside the random-stream counter */
+    uint32_t flags;        /* PF_FLAG_* */
+} pf_params;
+
+typedef struct pf_filter pf_filter;
+
+/* Device bytes a filter with these parameters needs.  Pure function: touches
+ * no device.  Errors: PF_ERR_INVALID_ARG for out-of-range parameters or a
+ * NULL pointer. */
+int pf_workspace_bytes(const pf_params* p, size_t* out_bytes);
+
+/* Initialisation (paper Sec. 4, Fig. 1: the filter starts after an
+ * initialization phase): all N particles at (x0, y0) with weight 1/N, step
+ * counter t = 0.  `d_workspace` is device memory of at least
+ * pf_workspace_bytes() bytes, 256-byte aligned, owned by the caller;
+ * `hip_stream` is a hipStream_t (NULL for the default stream).  On success
+ * *out receives a host handle (freed by pf_destroy).
+ * Errors: PF_ERR_INVALID_ARG, PF_ERR_WORKSPACE, PF_ERR_HIP. */
+int pf_init(const pf_params* p, void* d_workspace, size_t workspace_bytes, void* hip_stream,
+            pf_filter** out);
+
+/* One SIR step on one frame (paper Sec. 2 three stages; Sec. 4 six kernels):
+ * t <- t + 1; every particle k draws two normals from random stream
+ * (k, t, stream_id) and moves by (drift + sigma * z) (Eq. (1)-(2)); its
+ * log-likelihood is the disk sum of Eq. (3) over `d_frame`; weights are
+ * exp(L - max L) (Eq. (5), previous weights are all 1/N after resampling);
+ * the weighted mean position before resampling becomes the estimate; the
+ * normalised cumulative weights are resampled systematically with the offset
+ * drawn from stream (0, t, stream_id, purpose 1) (Sec. 4, resampling
+ * paragraph).  Asynchronous on the filter's stream; `d_frame` must stay valid
+ * until the step has run.  Errors: PF_ERR_INVALID_ARG (NULL frame, pitch < W),
+ * PF_ERR_HIP (the handle is then poisoned), PF_ERR_STATE. */
+int pf_step(pf_filter* h, const uint8_t* d_frame, int64_t row_pitch);
+
+/* The estimate of the latest step (x, y in pixels), or (x0, y0) before the
+ * first step.  Waits for the filter's stream.  Errors: PF_ERR_STATE,
+ * PF_ERR_HIP, PF_ERR_INVALID_ARG (NULL out). */
+int pf_estimate(pf_filter* h, double out_xy[2]);
+
+/* Stream-ordered copy of the latest estimate into device memory
+ * (`d_out_xy`: 2 doubles, device pointer); does not wait. */
+int pf_estimate_async(pf_filter* h, double* d_out_xy);
+
+/* Copy the filter's state to host memory (waits for the stream).  Each
+ * pointer may be NULL to skip it; arrays hold N elements.
+ *   x, y    -- particle positions after the latest resampling (the next
+ *              step's ancestors), in absolute pixels;
+ *   w_norm  -- normalised weights of the latest step before resampling, in
+ *              particle order of that step (needs PF_FLAG_DIAGNOSTICS);
+ *   anc     -- ancestor of every slot of the latest resampling
+ *              (needs PF_FLAG_DIAGNOSTICS);
+ *   t       -- steps taken.
+ * Errors: PF_ERR_INVALID_ARG (diagnostics requested without the flag, or no
+ * step taken yet for w_norm/anc), PF_ERR_STATE, PF_ERR_HIP. */
+int pf_export(pf_filter* h, double* x, double* y, double* w_norm, int32_t* anc, uint32_t* t);
+
+/* The propagated positions and disk sums of the latest step, before
+ * resampling, in absolute pixels (needs PF_FLAG_DIAGNOSTICS for disk_sum; the
+ * positions are always available after a step).  disk_sum[k] is the integer
+ * sum over the disk of (I - bg)^2 - (I - fg)^2.  Any pointer may be NULL. */
+int pf_export_step(pf_filter* h, double* x_prop, double* y_prop, int32_t* disk_sum);
+
+/* Replace the particle positions (host arrays of N doubles, absolute pixels)
+ * and the step counter; weights become 1/N.  Used for checkpoint/resume and
+ * teacher-forced comparisons.  Reduced-precision modes round each position
+ * to the mode's storage precision.  Stream-ordered; waits for the copy. */
+int pf_import(pf_filter* h, const double* x, const double* y, uint32_t t);
+
+/* Free the host handle (not the workspace).  NULL is accepted. */
+int pf_destroy(pf_filter* h);
+
+/* Text of the last error on the calling thread; valid until the next libpf
+ * call on that thread.  Never NULL. */
+const char* pf_last_error(void);
+
+/* Per-pass timing with HIP events on the filter's stream.  pf_profile_start
+ * creates the events for up to `max_steps` steps (host-side objects, no device
+ * memory) and records them around every kernel of the following pf_step
+ * calls; pf_profile_read waits for the stream and returns the summed
+ * durations in milliseconds: out_ms[0] = pass A (propagate, likelihood, tile
+ * maximum, weights, tile prefix sums), out_ms[1] = combine (global maximum,
+ * normaliser, carried offsets, estimate, resampling offset), out_ms[2] = pass C
+ * (systematic-resampling scatter), and the number of steps recorded; it then
+ * stops recording and frees the events.  Errors: PF_ERR_INVALID_ARG,
+ * PF_ERR_HIP. */
+int pf_profile_start(pf_filter* h, uint32_t max_steps);
+int pf_profile_read(pf_filter* h, double out_ms[3], uint32_t* steps);
+
+/* PF_ABI_VERSION of the loaded library. */
+int pf_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PF_H */

@@ -1,0 +1,240 @@
+"""Python binding of libpf: a reduced-precision SIR particle filter for object
+tracking in greyscale video, with its per-frame step in HIP for AMD gfx950.
+
+This module only marshals arguments to the C ABI declared in ``include/pf.h``
+(same function names); every step of the filter runs in the library's HIP
+kernels.  PyTorch supplies device memory (the workspace, frames) and streams.
+If the library has not been built, importing works but every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpf.so")
+
+PF_OK = 0
+PF_ERR_INVALID_ARG = 1
+PF_ERR_WORKSPACE = 2
+PF_ERR_HIP = 3
+PF_ERR_STATE = 4
+
+PF_F64, PF_F32, PF_F16, PF_BF16 = 0, 1, 2, 3
+DTYPES = {"f64": PF_F64, "f32": PF_F32, "f16": PF_F16, "bf16": PF_BF16}
+PF_LIK_MEAN, PF_LIK_SUM = 0, 1
+PF_FLAG_DIAGNOSTICS = 1
+
+# Every function the C header declares (checked against include/pf.h by the tests).
+EXPORTS = ("pf_workspace_bytes", "pf_init", "pf_step", "pf_estimate", "pf_estimate_async",
+           "pf_export", "pf_export_step", "pf_import", "pf_destroy", "pf_last_error",
+           "pf_abi_version", "pf_profile_start", "pf_profile_read")
+
+
+class PfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libpf error {code}: {msg}")
+        self.code = code
+
+
+class pf_params(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("dtype", ctypes.c_int32),
+        ("n_particles", ctypes.c_int64),
+        ("width", ctypes.c_int32),
+        ("height", ctypes.c_int32),
+        ("disk_radius", ctypes.c_int32),
+        ("fg", ctypes.c_int32),
+        ("bg", ctypes.c_int32),
+        ("lik_norm", ctypes.c_int32),
+        ("kappa", ctypes.c_double),
+        ("x0", ctypes.c_double),
+        ("y0", ctypes.c_double),
+        ("drift_x", ctypes.c_double),
+        ("drift_y", ctypes.c_double),
+        ("sigma_x", ctypes.c_double),
+        ("sigma_y", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("stream_id", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libpf (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libpf.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        vp = ctypes.c_void_p
+        L.pf_workspace_bytes.argtypes = [P(pf_params), P(ctypes.c_size_t)]
+        L.pf_init.argtypes = [P(pf_params), vp, ctypes.c_size_t, vp, P(vp)]
+        L.pf_step.argtypes = [vp, vp, ctypes.c_int64]
+        L.pf_estimate.argtypes = [vp, P(ctypes.c_double)]
+        L.pf_estimate_async.argtypes = [vp, vp]
+        L.pf_export.argtypes = [vp, vp, vp, vp, vp, P(ctypes.c_uint32)]
+        L.pf_export_step.argtypes = [vp, vp, vp, vp]
+        L.pf_import.argtypes = [vp, vp, vp, ctypes.c_uint32]
+        L.pf_destroy.argtypes = [vp]
+        L.pf_last_error.argtypes = []
+        L.pf_last_error.restype = ctypes.c_char_p
+        L.pf_abi_version.argtypes = []
+        L.pf_profile_start.argtypes = [vp, ctypes.c_uint32]
+        L.pf_profile_read.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_uint32)]
+        for name in EXPORTS:
+            if name != "pf_last_error":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != PF_OK:
+        raise PfError(rc, lib().pf_last_error().decode())
+
+
+def make_params(n, width, height, dtype="f64", radius=5, x0=0.0, y0=0.0, drift=(1.0, -2.0),
+                sigma=(5.0, 2.0), seed=0, stream_id=0, fg=228, bg=100, kappa=50.0,
+                lik_norm=PF_LIK_MEAN, diagnostics=False) -> pf_params:
+    dt = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+    return pf_params(ctypes.sizeof(pf_params), dt, int(n), int(width), int(height), int(radius),
+                     int(fg), int(bg), int(lik_norm), float(kappa), float(x0), float(y0),
+                     float(drift[0]), float(drift[1]), float(sigma[0]), float(sigma[1]),
+                     int(seed) & (2**64 - 1), int(stream_id), PF_FLAG_DIAGNOSTICS if diagnostics else 0)
+
+
+# ---------------------------------------------------------------------------
+# C-ABI functions under their C names (argument marshalling only).
+
+def pf_workspace_bytes(p: pf_params) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().pf_workspace_bytes(ctypes.byref(p), ctypes.byref(out)))
+    return out.value
+
+
+def pf_init(p: pf_params, d_workspace: int, workspace_bytes: int, hip_stream: int):
+    h = ctypes.c_void_p()
+    _check(lib().pf_init(ctypes.byref(p), ctypes.c_void_p(d_workspace), workspace_bytes,
+                         ctypes.c_void_p(hip_stream), ctypes.byref(h)))
+    return h
+
+
+def pf_step(h, d_frame: int, row_pitch: int):
+    _check(lib().pf_step(h, ctypes.c_void_p(d_frame), int(row_pitch)))
+
+
+def pf_estimate(h):
+    out = (ctypes.c_double * 2)()
+    _check(lib().pf_estimate(h, out))
+    return float(out[0]), float(out[1])
+
+
+def pf_estimate_async(h, d_out: int):
+    _check(lib().pf_estimate_async(h, ctypes.c_void_p(d_out)))
+
+
+def _np_ptr(a):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def pf_export(h, n: int, diagnostics: bool = False):
+    x = np.zeros(n)
+    y = np.zeros(n)
+    w = np.zeros(n) if diagnostics else None
+    anc = np.zeros(n, dtype=np.int32) if diagnostics else None
+    t = ctypes.c_uint32()
+    _check(lib().pf_export(h, _np_ptr(x), _np_ptr(y), _np_ptr(w), _np_ptr(anc), ctypes.byref(t)))
+    return dict(x=x, y=y, w=w, anc=anc, t=t.value)
+
+
+def pf_export_step(h, n: int, diagnostics: bool = False):
+    x = np.zeros(n)
+    y = np.zeros(n)
+    s = np.zeros(n, dtype=np.int32) if diagnostics else None
+    _check(lib().pf_export_step(h, _np_ptr(x), _np_ptr(y), _np_ptr(s)))
+    return dict(x_prop=x, y_prop=y, disk_sum=s)
+
+
+def pf_import(h, x, y, t: int):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    _check(lib().pf_import(h, _np_ptr(x), _np_ptr(y), int(t)))
+
+
+def pf_destroy(h):
+    _check(lib().pf_destroy(h))
+
+
+def pf_last_error() -> str:
+    return lib().pf_last_error().decode()
+
+
+def pf_abi_version() -> int:
+    return lib().pf_abi_version()
+
+
+def pf_profile_start(h, max_steps: int):
+    _check(lib().pf_profile_start(h, int(max_steps)))
+
+
+def pf_profile_read(h):
+    """(pass A ms, combine ms, pass C ms, steps) summed over the recorded steps."""
+    out = (ctypes.c_double * 3)()
+    steps = ctypes.c_uint32()
+    _check(lib().pf_profile_read(h, out, ctypes.byref(steps)))
+    return float(out[0]), float(out[1]), float(out[2]), steps.value
+
+
+# ---------------------------------------------------------------------------
+# Convenience wrapper: workspace and stream from PyTorch.
+
+class Filter:
+    """One particle filter with a torch-allocated workspace on `device`."""
+
+    def __init__(self, params: pf_params, device="cuda:0", stream=None):
+        import torch
+        self.params = params
+        self.n = params.n_particles
+        self.diagnostics = bool(params.flags & PF_FLAG_DIAGNOSTICS)
+        self.device = torch.device(device)
+        nbytes = pf_workspace_bytes(params)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.handle = pf_init(params, self.workspace.data_ptr(), nbytes, self.stream.cuda_stream)
+
+    def step(self, frame):
+        """frame: (H, W) uint8 CUDA tensor (row pitch from its stride)."""
+        assert frame.dtype.itemsize == 1 and frame.dim() == 2 and frame.stride(1) == 1
+        assert frame.is_cuda
+        pf_step(self.handle, frame.data_ptr(), frame.stride(0))
+
+    def estimate(self):
+        return pf_estimate(self.handle)
+
+    def export(self):
+        return pf_export(self.handle, self.n, self.diagnostics)
+
+    def export_step(self):
+        return pf_export_step(self.handle, self.n, self.diagnostics)
+
+    def load(self, x, y, t):
+        pf_import(self.handle, x, y, t)
+
+    def close(self):
+        if self.handle is not None:
+            pf_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,136 @@
+// Internal layout shared by the kernels and the C-ABI host code of libpf.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/pf.h"
+
+namespace pf {
+
+constexpr int kBlock = 256;        // threads per workgroup of every pass
+constexpr int kWaves = kBlock / 64;
+constexpr int kMaxTile = 1024;     // largest particles-per-workgroup tile
+constexpr int kScatterItems = 2048; // merge-path items (particles + slots) per workgroup
+constexpr int kPrefPitch = 130;    // LDS row-prefix table: u16 entries per window row (65 dwords)
+constexpr int kPrefRows = 64;      // LDS row-prefix table: window rows
+constexpr int kWinMaxW = 128;      // widest frame window staged in LDS
+constexpr int kMaxRadius = 32;
+
+// Particles per thread and tile size per precision mode.
+__host__ __device__ constexpr int ppt_of(int /*dtype*/) { return 4; }
+__host__ __device__ constexpr int tile_of(int dtype) { return kBlock * ppt_of(dtype); }
+__host__ __device__ constexpr int elt_of(int dtype) { return dtype == PF_F64 ? 8 : dtype == PF_F32 ? 4 : 2; }
+
+// Per-filter scalars in device memory (first 256 bytes of the workspace).
+struct DevBlock {
+    uint32_t pad0[2];
+    int32_t ci_x, ci_y;   // reduced modes: origin cell of the stored positions
+    int32_t cn_x, cn_y;   // reduced modes: origin cell of the next propagation
+    double est_x, est_y;  // estimate of the latest step
+    // double mode: normaliser and maximum log-likelihood of the latest step
+    double Z, M, u0;
+    // reduced modes: the same in float / two-float form
+    float Zf, u0_hi, u0_lo, R_hi, R_lo;  // R = N / Z
+    int32_t Smax;
+    uint32_t pad1[2];
+};
+static_assert(sizeof(DevBlock) <= 256, "DevBlock must fit in 256 bytes");
+
+// Per-tile record written by the first pass: tile maximum and sums relative
+// to it.
+struct TileRec64 {
+    double m, s, sx, sy;
+};
+struct TileRec32 {
+    int32_t smax;
+    float s, sx, sy;
+};
+// Per-tile table written by the combine: cumulative weight before the tile
+// (two-float in reduced modes; entry ntiles holds the total), the factor
+// exp(m_t - M), and E = the end slot of the tile's last particle.
+struct TileTab64 {
+    double off, f;
+    int64_t E;
+};
+struct TileTab32 {
+    float off_hi, off_lo, f;
+    int32_t E;
+};
+
+// Workspace layout; offsets in bytes from the workspace base.
+struct Layout {
+    int64_t n, n_pad;
+    int tile, ntiles;
+    size_t blk, rec, tab, sx, sy, px, py, q, dg_s, dg_w, dg_anc, total;
+};
+
+inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+inline Layout make_layout(const pf_params& p)
+{
+    Layout L{};
+    L.n = p.n_particles;
+    L.tile = tile_of(p.dtype);
+    L.ntiles = (int)((L.n + L.tile - 1) / L.tile);
+    L.n_pad = (int64_t)L.ntiles * L.tile;
+    const size_t elt = (size_t)elt_of(p.dtype);
+    const size_t rec = p.dtype == PF_F64 ? sizeof(TileRec64) : sizeof(TileRec32);
+    const size_t tab = p.dtype == PF_F64 ? sizeof(TileTab64) : sizeof(TileTab32);
+    const size_t qel = p.dtype == PF_F64 ? 8 : 4;
+    size_t o = 0;
+    L.blk = o; o += 256;
+    L.rec = o; o = align256(o + rec * (size_t)L.ntiles);
+    L.tab = o; o = align256(o + tab * (size_t)(L.ntiles + 1));
+    L.sx = o; o = align256(o + elt * (size_t)L.n_pad);
+    L.sy = o; o = align256(o + elt * (size_t)L.n_pad);
+    L.px = o; o = align256(o + elt * (size_t)L.n_pad);
+    L.py = o; o = align256(o + elt * (size_t)L.n_pad);
+    L.q = o; o = align256(o + qel * (size_t)L.n_pad);
+    if (p.flags & PF_FLAG_DIAGNOSTICS) {
+        L.dg_s = o; o = align256(o + 4 * (size_t)L.n_pad);
+        L.dg_w = o; o = align256(o + 8 * (size_t)L.n_pad);
+        L.dg_anc = o; o = align256(o + 4 * (size_t)L.n_pad);
+    } else {
+        L.dg_s = L.dg_w = L.dg_anc = 0;
+    }
+    L.total = o;
+    return L;
+}
+
+// Arguments of the passes (passed by value).
+struct StepArgs {
+    const uint8_t* frame;
+    int64_t pitch;
+    int32_t W, H, r, nd;
+    int64_t n;
+    int32_t ntiles;
+    uint32_t t, stream_id, key0, key1;
+    int32_t fg, bg;
+    double drift_x, drift_y, sigma_x, sigma_y;
+    double denom;       // kappa * N_d (MEAN) or kappa (SUM)
+    float beta;         // log2(e) / denom, reduced modes
+    DevBlock* blk;
+    void* rec;
+    void* tab;
+    void* sx;
+    void* sy;
+    void* px;
+    void* py;
+    void* q;
+    int32_t* dg_s;      // diagnostics (may be null)
+    double* dg_w;
+    int32_t* dg_anc;
+};
+
+// Host-side launchers (kernels.hip).  launch_step = launch_pass_a,
+// launch_combine, launch_pass_c on the same stream.
+hipError_t launch_step(int dtype, const StepArgs& a, hipStream_t s);
+hipError_t launch_pass_a(int dtype, const StepArgs& a, hipStream_t s);
+hipError_t launch_combine(int dtype, const StepArgs& a, hipStream_t s);
+hipError_t launch_pass_c(int dtype, const StepArgs& a, hipStream_t s);
+hipError_t launch_fill(int dtype, const StepArgs& a, double vx, double vy, hipStream_t s);
+hipError_t launch_diag_weights(int dtype, const StepArgs& a, hipStream_t s);
+
+}  // namespace pf

@@ -1,0 +1,74 @@
+"""CPU checks of the C-ABI library: it loads, exports every function the
+header declares, sizes workspaces and rejects bad parameters (no device call)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2308_00763_amd as pf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pf.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(pf_[a-z_]+)\s*\(", src, re.M)))
+
+
+def test_header_declares_the_binding_names():
+    assert _declared() == sorted(pf.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(pf.LIB_PATH)
+    for name in _declared():
+        assert hasattr(L, name), name
+    assert pf.pf_abi_version() == 1
+
+
+def test_params_struct_matches_header_size():
+    # 4 + 4 + 8 + 6*4 + 8 + 6*8 + 8 + 4 + 4 = 112 bytes on x86-64
+    assert ctypes.sizeof(pf.pf_params) == 112
+
+
+def test_workspace_sizes():
+    p64 = pf.make_params(1 << 20, 1024, 1024, "f64")
+    p16 = pf.make_params(1 << 20, 1024, 1024, "f16")
+    b64, b16 = pf.pf_workspace_bytes(p64), pf.pf_workspace_bytes(p16)
+    # state (2 planes) + propagated (2 planes) + prefix (1)
+    assert b64 >= (1 << 20) * (4 * 8 + 8)
+    assert b16 >= (1 << 20) * (4 * 2 + 4)
+    assert b16 < b64 / 2.5
+    pd = pf.make_params(1 << 20, 1024, 1024, "f16", diagnostics=True)
+    assert pf.pf_workspace_bytes(pd) >= b16 + (1 << 20) * 16
+
+
+@pytest.mark.parametrize("field,value", [
+    ("n_particles", 0), ("n_particles", (1 << 28) + 1), ("disk_radius", 0), ("disk_radius", 33),
+    ("width", 10), ("dtype", 7), ("fg", 300), ("lik_norm", 5), ("kappa", 0.0),
+    ("sigma_x", -1.0), ("x0", float("nan")), ("flags", 8), ("struct_size", 12)])
+def test_bad_params_are_rejected(field, value):
+    p = pf.make_params(1000, 128, 128)
+    setattr(p, field, value)
+    with pytest.raises(pf.PfError) as ei:
+        pf.pf_workspace_bytes(p)
+    assert ei.value.code == pf.PF_ERR_INVALID_ARG
+    assert len(pf.pf_last_error()) > 0
+
+
+def test_null_pointers_are_rejected_without_a_device():
+    L = pf.lib()
+    p = pf.make_params(1000, 128, 128)
+    assert L.pf_workspace_bytes(ctypes.byref(p), None) == pf.PF_ERR_INVALID_ARG
+    out = ctypes.c_void_p()
+    assert L.pf_init(ctypes.byref(p), None, 0, None, ctypes.byref(out)) == pf.PF_ERR_INVALID_ARG
+    assert L.pf_step(None, None, 0) == pf.PF_ERR_INVALID_ARG
+    assert L.pf_estimate(None, None) == pf.PF_ERR_INVALID_ARG
+    assert L.pf_destroy(None) == pf.PF_OK
+    # a workspace pointer that is too small is refused before any device work
+    assert L.pf_init(ctypes.byref(p), ctypes.c_void_p(256), 16, None,
+                     ctypes.byref(out)) == pf.PF_ERR_WORKSPACE
+    assert L.pf_init(ctypes.byref(p), ctypes.c_void_p(257), 1 << 30, None,
+                     ctypes.byref(out)) == pf.PF_ERR_INVALID_ARG
