@@ -30,11 +30,49 @@ sys.path.insert(0, ROOT)
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9   # lane-operation issue slots per second
 PEAK_HBM = 8.0e12                      # bytes per second
 
-# Algorithmic work of pass A per particle-update, in VALU lane-operation issue
-# slots (a quarter-rate instruction costs 4), counted from the method's minimal
-# instruction sequence per precision mode; the derivation is in the design doc.
-PASS_A_SLOTS = {"f64": 330, "f32": 190, "f16": 186, "bf16": 192}
+# Algorithmic work of pass A per particle-update, in full-rate VALU
+# instruction slots (a wave64 instruction issued every 4 cycles per SIMD is
+# one slot per lane; measured on this GPU: transcendentals cost 2, 64-bit
+# products and double operations 1.25), counted from the minimal instruction
+# sequence of the method for radius 5: Philox4x32-10 65, uniforms 6,
+# Box-Muller 12, propagation 3-5, pixel rounding 8, disk sum over the row
+# prefixes 18 + 1, weight 5, maximum / prefix sum / estimate 4.  The double
+# mode replaces the float uniforms, Box-Muller, propagation, rounding, weight
+# and the likelihood division by their double versions.
+PASS_A_SLOTS = {"f64": 277, "f32": 123, "f16": 122, "bf16": 124}
 STATE_BYTES = {"f64": 32, "f32": 16, "f16": 8, "bf16": 8}
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "pass_a_f16_disk1024_n1m_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2308_00763_amd", "csrc", f)
+                  for f in ("kernels.hip", "philox.hpp", "wave.hpp", "pf_internal.hpp")]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, dtype):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources (else None)."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    vals = {}
+    with open(TRAFFIC_SUMMARY) as f:
+        for line in f:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    if vals.get("kernel") != kernel or vals.get("dtype") != dtype:
+        return None
+    fetch = float(vals["fetch_kib_per_dispatch"]) * 1024 * float(vals["fetch_scale"])
+    write = float(vals["write_kib_per_dispatch"]) * 1024 * float(vals["write_scale"])
+    return fetch + write
 
 
 def log(msg):
@@ -42,26 +80,39 @@ def log(msg):
 
 
 def run_mode(pf, torch, frames_dev, centres, w, dtype, steps, warmup, profile):
+    """Time `steps` SIR steps after `warmup` (a fresh filter each call).
+
+    The timed loop calls the C ABI directly with precomputed frame pointers,
+    so the host adds as little as possible between launches.  With profile=True
+    the same loop also records HIP events around every kernel (on the filter's
+    stream); event records between kernels lengthen the step, so the headline
+    time comes from a run without them."""
+    import ctypes
     T = frames_dev.shape[0]
     assert warmup + steps <= T - 1, "the timed steps must fit in one pass over the video"
     x0, y0 = centres[0]
     p = pf.make_params(w.n_particles, w.width, w.height, dtype, radius=w.radius, x0=x0, y0=y0,
                        drift=w.drift, sigma=w.sigma, seed=w.filter_seed)
     f = pf.Filter(p)
-    t = 1
-    for _ in range(warmup):
-        f.step(frames_dev[t])
-        t += 1
+    lib = pf.lib()
+    pitch = int(frames_dev.stride(1))
+    base = int(frames_dev.data_ptr())
+    fstride = int(frames_dev.stride(0))
+    ptrs = [ctypes.c_void_p(base + t * fstride) for t in range(T)]
+    step = lib.pf_step
+    h = f.handle
+    for t in range(1, warmup + 1):
+        if step(h, ptrs[t], pitch):
+            raise pf.PfError(-1, pf.pf_last_error())
     if profile:
-        pf.pf_profile_start(f.handle, steps)
+        pf.pf_profile_start(h, steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        f.step(frames_dev[t])
-        t += 1
+    for t in range(warmup + 1, warmup + steps + 1):
+        step(h, ptrs[t], pitch)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = pf.pf_profile_read(f.handle) if profile else None
+    prof = pf.pf_profile_read(h) if profile else None
     f.close()
     return (t1 - t0), prof
 
@@ -113,6 +164,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-track", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (five times), "
+                         "to scale hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the filter step is single-GPU "
@@ -127,6 +181,15 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        nbytes = args.calibrate_copy << 20
+        src = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0").fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": nbytes, "copies": 5}), flush=True)
+        return
     w = pfsynth.WORKLOADS[args.workload]
     log(f"[bench] generating {w.name}: {w.frames} frames {w.width}x{w.height}")
     vid = pfsynth.workload_video(w)
@@ -136,12 +199,16 @@ def main():
     res = {}
     for dt in modes:
         log(f"[bench] timing {dt}: warmup {args.warmup}, steps {args.steps}")
-        secs, prof = run_mode(pf, torch, frames_dev, vid.centres, w, dt, args.steps, args.warmup,
-                              profile=True)
+        secs, _ = run_mode(pf, torch, frames_dev, vid.centres, w, dt, args.steps, args.warmup,
+                           profile=False)
+        # the same steps again, with HIP events around every kernel
+        psecs, prof = run_mode(pf, torch, frames_dev, vid.centres, w, dt, args.steps, args.warmup,
+                               profile=True)
         a_ms, m_ms, c_ms, n = prof
         res[dt] = dict(seconds=secs, ms_per_step=1e3 * secs / args.steps,
                        updates_per_s=w.n_particles * args.steps / secs,
-                       pass_a_us=1e3 * a_ms / n, combine_us=1e3 * m_ms / n, pass_c_us=1e3 * c_ms / n)
+                       pass_a_us=1e3 * a_ms / n, combine_us=1e3 * m_ms / n, pass_c_us=1e3 * c_ms / n,
+                       ms_per_step_with_events=1e3 * psecs / args.steps)
         log(f"[bench] {dt}: {res[dt]}")
 
     if not args.no_track and "f64" in modes:
@@ -161,8 +228,10 @@ def main():
     if dom == "pass_a":
         achieved = PASS_A_SLOTS[head] * w.n_particles / a_s
         roof = dict(bound="alu", kernel="pass_a", achieved=achieved / 1e12, peak=PEAK_LANE_OPS / 1e12,
-                    unit="Tlane-op/s", frac=achieved / PEAK_LANE_OPS, traffic=None,
-                    kernel_us=r["pass_a_us"])
+                    unit="Tlane-op/s", frac=achieved / PEAK_LANE_OPS,
+                    traffic=measured_traffic("pass_a", head) if w.name == "disk1024_n1m" else None,
+                    kernel_us=r["pass_a_us"],
+                    work_per_update=PASS_A_SLOTS[head], work_unit="VALU lane slots")
     else:
         c_s = r["pass_c_us"] * 1e-6
         byts = STATE_BYTES[head] * w.n_particles / 2  # pass C's share: read + write of positions

@@ -145,13 +145,13 @@ struct ModeT<PF_F64> {
     struct Prop {
         double dx, dy, sx, sy;
     };
-    static __device__ __forceinline__ void load(const void* p, int64_t k0, Val* v)
+    static __device__ __forceinline__ void load(const void* p, int k0, Val* v)
     {
         const double2* q = reinterpret_cast<const double2*>(static_cast<const double*>(p) + k0);
         const double2 a = q[0], b = q[1];
         v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
     }
-    static __device__ __forceinline__ void store(void* p, int64_t k0, const Val* v)
+    static __device__ __forceinline__ void store(void* p, int k0, const Val* v)
     {
         double2* q = reinterpret_cast<double2*>(static_cast<double*>(p) + k0);
         q[0] = make_double2(v[0], v[1]);
@@ -160,7 +160,7 @@ struct ModeT<PF_F64> {
     // x <- x + (d + sigma z), each operation rounded (library built without
     // contraction), as Eq. (1)-(2) are written.
     static __device__ __forceinline__ void propagate(Val* x, Val* y, const Prop& pr, const StepArgs& a,
-                                                     int64_t k0)
+                                                     int k0)
     {
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
@@ -187,17 +187,17 @@ struct ModeT<PF_F32> {
     struct Prop {
         float dx, dy, sx, sy;
     };
-    static __device__ __forceinline__ void load(const void* p, int64_t k0, Val* v)
+    static __device__ __forceinline__ void load(const void* p, int k0, Val* v)
     {
         const float4 a = *reinterpret_cast<const float4*>(static_cast<const float*>(p) + k0);
         v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
     }
-    static __device__ __forceinline__ void store(void* p, int64_t k0, const Val* v)
+    static __device__ __forceinline__ void store(void* p, int k0, const Val* v)
     {
         *reinterpret_cast<float4*>(static_cast<float*>(p) + k0) = make_float4(v[0], v[1], v[2], v[3]);
     }
     static __device__ __forceinline__ void propagate(Val* x, Val* y, const Prop& pr, const StepArgs& a,
-                                                     int64_t k0)
+                                                     int k0)
     {
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
@@ -224,20 +224,20 @@ struct ModeT<PF_F16> {
     struct Prop {
         half2_t dx, dy, sx, sy;
     };
-    static __device__ __forceinline__ void load(const void* p, int64_t k0, Val* v)
+    static __device__ __forceinline__ void load(const void* p, int k0, Val* v)
     {
         const uint2 a = *reinterpret_cast<const uint2*>(static_cast<const _Float16*>(p) + k0);
         const half2_t h0 = __builtin_bit_cast(half2_t, a.x), h1 = __builtin_bit_cast(half2_t, a.y);
         v[0] = h0.x; v[1] = h0.y; v[2] = h1.x; v[3] = h1.y;
     }
-    static __device__ __forceinline__ void store(void* p, int64_t k0, const Val* v)
+    static __device__ __forceinline__ void store(void* p, int k0, const Val* v)
     {
         const half2_t h0 = {v[0], v[1]}, h1 = {v[2], v[3]};
         *reinterpret_cast<uint2*>(static_cast<_Float16*>(p) + k0) =
             make_uint2(__builtin_bit_cast(uint32_t, h0), __builtin_bit_cast(uint32_t, h1));
     }
     static __device__ __forceinline__ void propagate(Val* x, Val* y, const Prop& pr, const StepArgs& a,
-                                                     int64_t k0)
+                                                     int k0)
     {
 #pragma unroll
         for (int i = 0; i < PPT; i += 2) {
@@ -275,7 +275,7 @@ struct ModeT<PF_BF16> {
     struct Prop {
         float dx, dy, sx, sy;
     };
-    static __device__ __forceinline__ void load(const void* p, int64_t k0, Val* v)
+    static __device__ __forceinline__ void load(const void* p, int k0, Val* v)
     {
         const uint2 a = *reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(p) + k0);
         v[0] = __uint_as_float(a.x << 16);
@@ -288,12 +288,12 @@ struct ModeT<PF_BF16> {
         const __bf16 a = (__bf16)lo, b = (__bf16)hi;
         return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
     }
-    static __device__ __forceinline__ void store(void* p, int64_t k0, const Val* v)
+    static __device__ __forceinline__ void store(void* p, int k0, const Val* v)
     {
         *reinterpret_cast<uint2*>(static_cast<uint16_t*>(p) + k0) = make_uint2(pack(v[0], v[1]), pack(v[2], v[3]));
     }
     static __device__ __forceinline__ void propagate(Val* x, Val* y, const Prop& pr, const StepArgs& a,
-                                                     int64_t k0)
+                                                     int k0)
     {
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
@@ -344,13 +344,14 @@ __global__ __launch_bounds__(kBlock) void pass_a_kernel(StepArgs a)
 {
     using M = ModeT<DT>;
     constexpr int PPT = M::PPT;
-    constexpr int TILE = kBlock * PPT;
+    static_assert(kBlock * PPT == kTile, "tile size");
     __shared__ PassALds lds;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
     const int tile = blockIdx.x;
-    const int64_t k0 = (int64_t)tile * TILE + (int64_t)tid * PPT;
+    const int k0 = tile * kTile + tid * PPT;
+    const int n = (int)a.n;
     const int r = RC > 0 ? RC : a.r;
 
     // Origins (reduced modes): stored offsets are relative to ci, the
@@ -381,7 +382,7 @@ __global__ __launch_bounds__(kBlock) void pass_a_kernel(StepArgs a)
     int b0 = INT32_MAX, b1 = INT32_MAX, b2 = INT32_MAX, b3 = INT32_MAX;  // min x, min y, -max x, -max y
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
-        valid[i] = (k0 + i) < a.n;
+        valid[i] = k0 + i < n;
         cx[i] = M::cell(x[i], cnx, lox, hix);
         cy[i] = M::cell(y[i], cny, loy, hiy);
         if (valid[i]) {
@@ -516,8 +517,7 @@ __global__ __launch_bounds__(kBlock) void pass_a_kernel(StepArgs a)
         for (int w = 1; w < wv; ++w) off = off + red[0][w];
     }
     const Acc incl = wv > 0 ? off + sw : sw;
-    Acc excl = shfl_up(incl, 1);
-    if (lane == 0) excl = off;
+    const Acc excl = wave_shift_up1(incl, off);
     Acc q[PPT];
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
@@ -554,309 +554,411 @@ __global__ __launch_bounds__(kBlock) void pass_a_kernel(StepArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// End slot of a cumulative weight P: #{j in [0, N) : (j + u0)/N <= P / Z}.
+// End slots.  A particle with normalised cumulative weight C = P / Z ends the
+// strata (j + u0) / N <= C, i.e. its end slot is floor(N P / Z - u0) + 1
+// (clamped to [0, N]).  With R = N / Z and P = off_t + f_t q inside tile t,
+// the slot coordinate is the affine y = (R off_t - u0) + (R f_t) q, capped at
+// y_max = R off_{t+1} - u0, whose end slot is the tile's end slot E_t (the
+// combine evaluates exactly that expression), so tiles join without gaps.
+// The reduced modes evaluate y in two-float arithmetic (about 44 bits); the
+// double mode in double (the slot coordinate of N <= 2^28 strata then carries
+// an error far below the 1e-12 resolution of the distribution).
 
-template <int DT>
-struct SlotMap;
-
-template <>
-struct SlotMap<PF_F64> {
-    int64_t n;
-    double Z, u0, nd;
-    // Every comparison is evaluated exactly as (j + u0) / N <= C with
-    // C = P / Z, so the result agrees with a direct search of the strata; the
-    // floor only gives the starting guess.
-    __device__ int64_t operator()(double P) const
-    {
-        const double C = P / Z;
-        double g = floor(nd * C - u0);
-        g = fmin(fmax(g, -1.0), (double)(n - 1));
-        int64_t j = (int64_t)g;
-        while (j + 1 <= n - 1 && ((double)(j + 1) + u0) / nd <= C) ++j;
-        while (j >= 0 && ((double)j + u0) / nd > C) --j;
-        return j + 1;
-    }
-};
-
-template <>
-struct SlotMap<PF_F32> {
-    int64_t n;
-    ff R, mu0;  // R = N / Z, mu0 = -u0
-    // floor(N P / Z - u0) + 1 in two-float arithmetic (about 44 bits).
-    __device__ int64_t operator()(ff P) const
-    {
-        const ff Y = ff_add(ff_mul(R, P), mu0);
-        int64_t g = ff_floor(Y) + 1;
-        return g < 0 ? 0 : (g > n ? n : g);
-    }
-};
-
-// Per-particle end slot e_i from the stored tile-local prefix q_i and the
-// tile table; e of a tile's last particle is the tile's stored end slot and
-// e_{N-1} = N, so consecutive tiles join exactly.
-template <int DT>
-struct EndSlot;
-
-template <>
-struct EndSlot<PF_F64> {
-    const double* q;
-    const TileTab64* tab;
-    int64_t n;
-    int tile;
-    SlotMap<PF_F64> sm;
-    __device__ EndSlot(const StepArgs& a)
-        : q(static_cast<const double*>(a.q)), tab(static_cast<const TileTab64*>(a.tab)), n(a.n),
-          tile(tile_of(PF_F64))
-    {
-        sm.n = a.n; sm.Z = a.blk->Z; sm.u0 = a.blk->u0; sm.nd = (double)a.n;
-    }
-    __device__ int64_t tile_end(int t) const { return tab[t].E; }
-    __device__ int64_t operator()(int64_t i) const
-    {
-        if (i >= n - 1) return n;
-        const int t = (int)(i / tile);
-        if (i % tile == tile - 1) return tab[t].E;
-        double P = tab[t].off + tab[t].f * q[i];
-        const double Pn = tab[t + 1].off;
-        P = P < Pn ? P : Pn;
-        return sm(P);
-    }
-};
-
-template <>
-struct EndSlot<PF_F32> {
-    const float* q;
-    const TileTab32* tab;
-    int64_t n;
-    int tile;
-    SlotMap<PF_F32> sm;
-    __device__ EndSlot(const StepArgs& a, int tile_size)
-        : q(static_cast<const float*>(a.q)), tab(static_cast<const TileTab32*>(a.tab)), n(a.n), tile(tile_size)
-    {
-        sm.n = a.n;
-        sm.R = ff{a.blk->R_hi, a.blk->R_lo};
-        sm.mu0 = ff{-a.blk->u0_hi, -a.blk->u0_lo};
-    }
-    __device__ int64_t tile_end(int t) const { return tab[t].E; }
-    __device__ int64_t operator()(int64_t i) const
-    {
-        if (i >= n - 1) return n;
-        const int t = (int)(i / tile);
-        if (i % tile == tile - 1) return tab[t].E;
-        const TileTab32 tb = tab[t];
-        const TileTab32 tn = tab[t + 1];
-        ff P = ff_add(ff{tb.off_hi, tb.off_lo}, two_prod(tb.f, q[i]));
-        P = ff_min(P, ff{tn.off_hi, tn.off_lo});
-        return sm(P);
-    }
-};
-
-template <int DT>
-__device__ __forceinline__ auto make_end_slot(const StepArgs& a)
+__device__ __forceinline__ int slot_end_of(double y, int n)
 {
-    if constexpr (DT == PF_F64) return EndSlot<PF_F64>(a);
-    else return EndSlot<PF_F32>(a, tile_of(DT));
+    const double g = floor(y) + 1.0;
+    return g <= 0.0 ? 0 : (g >= (double)n ? n : (int)g);
 }
 
-// ---------------------------------------------------------------------------
-// Combine: one workgroup turns the tile records into the tile table.
-
-constexpr int kCombChunk = 8 * kBlock;  // tiles per round, 8 per thread
+__device__ __forceinline__ int slot_end_of(ff y, int n)
+{
+    const int64_t g = ff_floor(y) + 1;
+    return g <= 0 ? 0 : (g >= n ? n : (int)g);
+}
 
 template <int DT>
-__global__ __launch_bounds__(kBlock) void combine_kernel(StepArgs a)
+struct TileSlots;
+
+template <>
+struct TileSlots<PF_F64> {
+    double base, scale, ymax;
+    int E, Eprev, B;
+    __device__ TileSlots(const StepArgs& a, int t)
+    {
+        const TileTab64* tab = static_cast<const TileTab64*>(a.tab);
+        const double R = a.blk->R, u0 = a.blk->u0;
+        base = R * tab[t].off - u0;
+        scale = R * tab[t].f;
+        ymax = R * tab[t + 1].off - u0;
+        E = tab[t].E;
+        B = tab[t].B;
+        Eprev = t > 0 ? tab[t - 1].E : 0;
+    }
+    __device__ int operator()(const void* q, int i, int n) const
+    {
+        double y = __builtin_fma(scale, static_cast<const double*>(q)[i], base);
+        y = y < ymax ? y : ymax;
+        return slot_end_of(y, n);
+    }
+};
+
+template <>
+struct TileSlots<PF_F32> {
+    ff base, scale, ymax;
+    int E, Eprev, B;
+    __device__ TileSlots(const StepArgs& a, int t)
+    {
+        const TileTab32* tab = static_cast<const TileTab32*>(a.tab);
+        const ff R{a.blk->R_hi, a.blk->R_lo}, mu0{-a.blk->u0_hi, -a.blk->u0_lo};
+        base = ff_add(ff_mul(R, ff{tab[t].off_hi, tab[t].off_lo}), mu0);
+        scale = ff_mul_f(R, tab[t].f);
+        ymax = ff_add(ff_mul(R, ff{tab[t + 1].off_hi, tab[t + 1].off_lo}), mu0);
+        E = tab[t].E;
+        B = tab[t].B;
+        Eprev = t > 0 ? tab[t - 1].E : 0;
+    }
+    __device__ int operator()(const void* q, int i, int n) const
+    {
+        ff y = ff_add(base, ff_mul_f(scale, static_cast<const float*>(q)[i]));
+        y = ff_min(y, ymax);
+        return slot_end_of(y, n);
+    }
+};
+
+template <int DT>
+using TileSlotsT = TileSlots<DT == PF_F64 ? PF_F64 : PF_F32>;
+
+// ---------------------------------------------------------------------------
+// Combine: one workgroup of 1024 threads turns the tile records into the tile
+// table.  Every thread owns KPER consecutive tiles per round; the carried
+// offsets come from a two-level scan (per wave, then over the wave totals)
+// whose total is the normaliser Z; the estimate sums ride on the same
+// exchange.  Offsets are made monotone by prefix maxima and by clamping each
+// value to the next wave's offset.
+
+constexpr int kCombThreads = 1024;
+constexpr int kCombWaves = kCombThreads / 64;
+
+// Two-float DPP moves and scans.
+template <int CTRL, int RM = 0xF>
+__device__ __forceinline__ ff dpp_ff(ff v, float fill_hi)
 {
-    using Acc = typename std::conditional<DT == PF_F64, double, float>::type;
-    __shared__ double red_d[3][kWaves];
-    __shared__ float red_f[2][kWaves];
-    __shared__ ff red_ff[kWaves];
-    __shared__ int red_i[kWaves];
+    return ff{dpp_f<CTRL, RM>(v.hi, fill_hi), dpp_f<CTRL, RM>(v.lo, 0.f)};
+}
+
+__device__ __forceinline__ ff wave_incl_sum_ff(ff v)
+{
+    v = ff_add(dpp_ff<0x111>(v, 0.f), v);
+    v = ff_add(dpp_ff<0x112>(v, 0.f), v);
+    v = ff_add(dpp_ff<0x114>(v, 0.f), v);
+    v = ff_add(dpp_ff<0x118>(v, 0.f), v);
+    v = ff_add(dpp_ff<0x142, 0xA>(v, 0.f), v);
+    v = ff_add(dpp_ff<0x143, 0xC>(v, 0.f), v);
+    return v;
+}
+
+__device__ __forceinline__ ff wave_incl_max_ff(ff v)
+{
+    const float ninf = -INFINITY;
+    v = ff_max(dpp_ff<0x111>(v, ninf), v);
+    v = ff_max(dpp_ff<0x112>(v, ninf), v);
+    v = ff_max(dpp_ff<0x114>(v, ninf), v);
+    v = ff_max(dpp_ff<0x118>(v, ninf), v);
+    v = ff_max(dpp_ff<0x142, 0xA>(v, ninf), v);
+    v = ff_max(dpp_ff<0x143, 0xC>(v, ninf), v);
+    return v;
+}
+
+// Accumulator arithmetic of the combine: double in FP64 mode, two-float in
+// the reduced modes.
+template <int DT>
+struct CombAcc;
+
+template <>
+struct CombAcc<PF_F64> {
+    using T = double;
+    static __device__ T zero() { return 0.0; }
+    static __device__ T add(T a, T b) { return a + b; }
+    static __device__ T min_(T a, T b) { return a < b ? a : b; }
+    static __device__ T max_(T a, T b) { return a > b ? a : b; }
+    static __device__ T scan(T v) { return wave_incl_max(wave_incl_sum(v, 0), 0); }
+    static __device__ T last(T v) { return lane63(v); }
+    static __device__ T up1(T v, T fill) { return wave_shift_up1(v, fill); }
+};
+
+template <>
+struct CombAcc<PF_F32> {
+    using T = ff;
+    static __device__ T zero() { return ff{0.f, 0.f}; }
+    static __device__ T add(T a, T b) { return ff_add(a, b); }
+    static __device__ T min_(T a, T b) { return ff_min(a, b); }
+    static __device__ T max_(T a, T b) { return ff_max(a, b); }
+    static __device__ T scan(T v) { return wave_incl_max_ff(wave_incl_sum_ff(v)); }
+    static __device__ T last(T v) { return ff{lane63(v.hi), lane63(v.lo)}; }
+    static __device__ T up1(T v, T fill) { return ff{wave_shift_up1(v.hi, fill.hi), wave_shift_up1(v.lo, fill.lo)}; }
+};
+
+template <int DT, int KPER>
+__global__ __launch_bounds__(kCombThreads) void combine_kernel(StepArgs a)
+{
+    constexpr bool F64 = DT == PF_F64;
+    using A = CombAcc<F64 ? PF_F64 : PF_F32>;
+    using T = typename A::T;
+    using Rec = typename std::conditional<F64, TileRec64, TileRec32>::type;
+    using Tab = typename std::conditional<F64, TileTab64, TileTab32>::type;
+    using Fv = typename std::conditional<F64, double, float>::type;
+    using Mx = typename std::conditional<F64, double, int>::type;
+    constexpr int CHUNK = KPER * kCombThreads;
+
+    __shared__ Mx red_m[kCombWaves];
+    __shared__ T red_s[kCombWaves];
+    __shared__ T wave_off[kCombWaves + 1];
+    __shared__ Fv red_x[kCombWaves], red_y[kCombWaves];
+
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int nt = a.ntiles;
-    const int tile = tile_of(DT);
+    const int n = (int)a.n;
     DevBlock* b = a.blk;
-    const u32x4 wu = philox4x32_10(0u, a.t, a.stream_id, 1u, a.key0, a.key1);
+    const Rec* rec = static_cast<const Rec*>(a.rec);
+    Tab* tab = static_cast<Tab*>(a.tab);
 
-    if constexpr (DT == PF_F64) {
-        const TileRec64* rec = static_cast<const TileRec64*>(a.rec);
-        TileTab64* tab = static_cast<TileTab64*>(a.tab);
-        // global maximum (strided, eight loads in flight per thread)
-        double m = -INFINITY;
-        for (int base = 0; base < nt; base += kCombChunk) {
+    // global maximum of the tile maxima
+    Mx m = F64 ? (Mx)-INFINITY : (Mx)INT32_MIN;
+    for (int base = 0; base < nt; base += CHUNK) {
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int t = base + k * kBlock + tid;
-                if (t < nt) m = fmax(m, rec[t].m);
+        for (int k = 0; k < KPER; ++k) {
+            const int t = base + tid * KPER + k;
+            if (t < nt) {
+                Mx mt;
+                if constexpr (F64) mt = rec[t].m; else mt = rec[t].smax;
+                m = mt > m ? mt : m;
             }
         }
-        const double Mx = block_max<kWaves>(m, red_d[0]);
-        SlotMap<PF_F64> sm;
-        sm.n = a.n;
-        sm.u0 = uniform53(wu.v0, wu.v1);
-        sm.nd = (double)a.n;
-        // inclusive offsets, chunk by chunk: 8 consecutive tiles per thread
-        double carry = 0.0, sx = 0.0, sy = 0.0;
-        // The normaliser is needed for the end slots: a first sweep sums the
-        // tiles in the same order as the offsets below, so Z equals the last
-        // offset bit for bit.
-        for (int pass = 0; pass < 2; ++pass) {
-            carry = 0.0;
-            for (int base = 0; base < nt; base += kCombChunk) {
-                const int t0 = base + tid * 8;
-                double f[8], v[8];
-                double loc = 0.0;
+    }
+    m = wave_max(m);
+    if (lane == 0) red_m[wv] = m;
+    __syncthreads();
+    Mx gm = red_m[0];
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const int t = t0 + k;
-                    f[k] = 0.0;
-                    v[k] = 0.0;
-                    if (t < nt) {
-                        const TileRec64 rr = rec[t];
-                        f[k] = exp(rr.m - Mx);
-                        v[k] = f[k] * rr.s;
-                        if (pass == 1) {
-                            sx = sx + f[k] * rr.sx;
-                            sy = sy + f[k] * rr.sy;
-                        }
-                    }
-                    loc = loc + v[k];
-                }
-                double sw = wave_incl_sum(loc, lane);
-                sw = wave_incl_max(sw, lane);
-                __syncthreads();
-                if (lane == 63) red_d[0][wv] = sw;
-                __syncthreads();
-                double off = carry;
-                for (int w = 0; w < wv; ++w) off = off + red_d[0][w];
-                const double incl = off + sw;
-                double excl = shfl_up(incl, 1);
-                if (lane == 0) excl = off;
-                if (pass == 1) {
-                    double run = 0.0;
+    for (int w = 1; w < kCombWaves; ++w) gm = red_m[w] > gm ? red_m[w] : gm;
+
+    const u32x4 wu = philox4x32_10(0u, a.t, a.stream_id, 1u, a.key0, a.key1);
+    T carry = A::zero();
+    Fv ex = 0, ey = 0;
+    // Pass 1 of 2 over the rounds computes the offsets and the normaliser;
+    // the end slots need the normaliser, so they are written in pass 2 from
+    // the offsets kept in the table (one round when nt <= CHUNK: registers).
+    constexpr bool KEEP = KPER <= 4;  // keep offsets in registers for the end slots
+    T o_keep[KEEP ? KPER : 1];
+    for (int base = 0; base < nt; base += CHUNK) {
+        Fv f[KPER];
+        T v[KPER];
+        T loc = A::zero();
 #pragma unroll
-                    for (int k = 0; k < 8; ++k) {
-                        const int t = t0 + k;
-                        run = run + v[k];
-                        double o = excl + run;
-                        o = o < incl ? o : incl;
-                        if (t < nt) {
-                            tab[t].f = f[k];
-                            tab[t + 1].off = o;
-                            tab[t].E = t == nt - 1 ? a.n : sm(o);
-                        }
-                    }
+        for (int k = 0; k < KPER; ++k) {
+            const int t = base + tid * KPER + k;
+            f[k] = 0;
+            v[k] = A::zero();
+            if (t < nt) {
+                const Rec rr = rec[t];
+                if constexpr (F64) {
+                    f[k] = exp(rr.m - gm);
+                    v[k] = f[k] * rr.s;
+                } else {
+                    f[k] = __builtin_amdgcn_exp2f((float)(rr.smax - gm) * a.beta);
+                    v[k] = two_prod(f[k], rr.s);
                 }
-                // carry = the chunk's last inclusive value
-                double c = carry;
-                for (int w = 0; w < kWaves; ++w) c = c + red_d[0][w];
-                carry = c;
+                ex = ex + f[k] * rr.sx;
+                ey = ey + f[k] * rr.sy;
             }
-            if (pass == 0) sm.Z = carry;
+            loc = A::add(loc, v[k]);
         }
-        sx = block_sum<kWaves>(sx, red_d[1]);
-        sy = block_sum<kWaves>(sy, red_d[2]);
-        if (tid == 0) {
-            tab[0].off = 0.0;
-            b->M = Mx;
-            b->Z = sm.Z;
-            b->u0 = sm.u0;
-            b->est_x = sx / sm.Z;
-            b->est_y = sy / sm.Z;
+        // level 1: monotone inclusive scan inside the wave
+        const T sw = A::scan(loc);
+        if (lane == 63) red_s[wv] = sw;
+        __syncthreads();
+        // level 2: wave 0 scans the wave totals
+        if (wv == 0) {
+            T tv = lane < kCombWaves ? red_s[lane] : A::zero();
+            tv = A::scan(tv);
+            if (lane < kCombWaves) wave_off[lane + 1] = A::add(carry, tv);
+            if (lane == 0) wave_off[0] = carry;
         }
+        __syncthreads();
+        const T off = wave_off[wv], off_next = wave_off[wv + 1];
+        const T incl = A::min_(A::add(off, sw), off_next);
+        const T excl = A::up1(incl, off);
+        T run = A::zero(), prev = excl;
+#pragma unroll
+        for (int k = 0; k < KPER; ++k) {
+            const int t = base + tid * KPER + k;
+            run = A::add(run, v[k]);
+            T o = A::min_(A::add(excl, run), incl);
+            o = A::max_(o, prev);
+            prev = o;
+            if constexpr (KEEP) o_keep[k] = o;
+            if (t < nt) {
+                tab[t].f = f[k];
+                if constexpr (F64) tab[t + 1].off = o;
+                else { tab[t + 1].off_hi = o.hi; tab[t + 1].off_lo = o.lo; }
+            }
+        }
+        carry = wave_off[kCombWaves];
+        __syncthreads();
+    }
+    const T Z = carry;
+    ex = wave_sum(ex);
+    ey = wave_sum(ey);
+    if (lane == 0) { red_x[wv] = ex; red_y[wv] = ey; }
+    __syncthreads();
+    Fv sx = red_x[0], sy = red_y[0];
+#pragma unroll
+    for (int w = 1; w < kCombWaves; ++w) { sx = sx + red_x[w]; sy = sy + red_y[w]; }
+
+    // end slots of every tile: y = R off_{t+1} - u0 (the expression pass C
+    // caps its tiles with)
+    using Y = typename std::conditional<F64, double, ff>::type;
+    Y Rr, mu0;
+    double u0d = 0.0;
+    ff u0f{0.f, 0.f};
+    if constexpr (F64) {
+        u0d = uniform53(wu.v0, wu.v1);
+        Rr = (double)n / Z;
+        mu0 = -u0d;
     } else {
-        const TileRec32* rec = static_cast<const TileRec32*>(a.rec);
-        TileTab32* tab = static_cast<TileTab32*>(a.tab);
-        int smx = INT32_MIN;
-        for (int base = 0; base < nt; base += kCombChunk) {
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int t = base + k * kBlock + tid;
-                if (t < nt) smx = max(smx, rec[t].smax);
-            }
-        }
-        const int Smax = block_max<kWaves>(smx, red_i);
-        SlotMap<PF_F32> sm;
-        sm.n = a.n;
         const uint64_t bits = ((uint64_t)wu.v0 << 21) | (uint64_t)(wu.v1 >> 11);
-        const ff u0 = fast_two_sum((float)(uint32_t)(bits >> 29) * 0x1.0p-24f,
-                                   (float)(uint32_t)(bits & 0x1FFFFFFFu) * 0x1.0p-53f);
-        sm.mu0 = ff{-u0.hi, -u0.lo};
-        ff carry{0.f, 0.f};
-        float sx = 0.f, sy = 0.f;
-        for (int pass = 0; pass < 2; ++pass) {
-            carry = ff{0.f, 0.f};
-            for (int base = 0; base < nt; base += kCombChunk) {
-                const int t0 = base + tid * 8;
-                float f[8], sv[8];
-                ff loc{0.f, 0.f};
+        u0f = fast_two_sum((float)(uint32_t)(bits >> 29) * 0x1.0p-24f,
+                           (float)(uint32_t)(bits & 0x1FFFFFFFu) * 0x1.0p-53f);
+        mu0 = ff{-u0f.hi, -u0f.lo};
+        const ff Nff = fast_two_sum((float)n, (float)(n - (int)(float)n));
+        Rr = ff_div(Nff, Z);
+    }
+    auto end_of = [&](T o) -> int {
+        if constexpr (F64) return slot_end_of(Rr * o + mu0, n);
+        else return slot_end_of(ff_add(ff_mul(Rr, o), mu0), n);
+    };
+    const bool one_round = KEEP && nt <= CHUNK;
+    int Ek[KPER];
+    for (int base = 0; base < nt; base += CHUNK) {
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const int t = t0 + k;
-                    f[k] = 0.f;
-                    sv[k] = 0.f;
-                    if (t < nt) {
-                        const TileRec32 rr = rec[t];
-                        f[k] = __builtin_amdgcn_exp2f((float)(rr.smax - Smax) * a.beta);
-                        sv[k] = rr.s;
-                        if (pass == 1) {
-                            sx = sx + f[k] * rr.sx;
-                            sy = sy + f[k] * rr.sy;
-                        }
-                    }
-                    loc = ff_add(loc, two_prod(f[k], sv[k]));
-                }
-                // monotone inclusive scan of two-float totals over the wave
-                ff s = loc;
-#pragma unroll
-                for (int d = 1; d < 64; d <<= 1) {
-                    const ff o{shfl_up(s.hi, d), shfl_up(s.lo, d)};
-                    if (lane >= d) s = ff_add(o, s);
-                }
-#pragma unroll
-                for (int d = 1; d < 64; d <<= 1) {
-                    const ff o{shfl_up(s.hi, d), shfl_up(s.lo, d)};
-                    if (lane >= d) s = ff_max(o, s);
-                }
-                __syncthreads();
-                if (lane == 63) red_ff[wv] = s;
-                __syncthreads();
-                ff off = carry;
-                for (int w = 0; w < wv; ++w) off = ff_add(off, red_ff[w]);
-                const ff incl = ff_add(off, s);
-                ff excl{shfl_up(incl.hi, 1), shfl_up(incl.lo, 1)};
-                if (lane == 0) excl = off;
-                if (pass == 1) {
-                    ff run{0.f, 0.f}, prev = excl;
-#pragma unroll
-                    for (int k = 0; k < 8; ++k) {
-                        const int t = t0 + k;
-                        run = ff_add(run, two_prod(f[k], sv[k]));
-                        ff o = ff_min(ff_add(excl, run), incl);
-                        o = ff_max(o, prev);
-                        prev = o;
-                        if (t < nt) {
-                            tab[t].f = f[k];
-                            tab[t + 1].off_hi = o.hi;
-                            tab[t + 1].off_lo = o.lo;
-                            tab[t].E = t == nt - 1 ? (int32_t)a.n : (int32_t)sm(o);
-                        }
-                    }
-                }
-                ff c = carry;
-                for (int w = 0; w < kWaves; ++w) c = ff_add(c, red_ff[w]);
-                carry = c;
-            }
-            if (pass == 0) {
-                const ff Nff = fast_two_sum((float)a.n, (float)(a.n - (int64_t)(float)a.n));
-                sm.R = ff_div(Nff, carry);
+        for (int k = 0; k < KPER; ++k) {
+            const int t = base + tid * KPER + k;
+            Ek[k] = 0;
+            if (t < nt) {
+                T o;
+                if (one_round) o = o_keep[KEEP ? k : 0];
+                else if constexpr (F64) o = tab[t + 1].off;
+                else o = ff{tab[t + 1].off_hi, tab[t + 1].off_lo};
+                Ek[k] = t == nt - 1 ? n : end_of(o);
+                tab[t].E = Ek[k];
             }
         }
-        sx = block_sum<kWaves>(sx, red_f[0]);
-        sy = block_sum<kWaves>(sy, red_f[1]);
-        if (tid == 0) {
+    }
+
+    // Pass-C work split: tile t takes P_t = ceil((T_t + s_t) / D) workgroups
+    // (none when it has no slots), numbered from B_t = P_0 + ... + P_{t-1};
+    // the workgroup -> tile map is the prefix maximum of the tile starts.  The
+    // map is built in LDS when it fits, else in global memory.
+    constexpr int kMapLds = 8192;
+    __shared__ int map_lds[kMapLds];
+    __shared__ int e_last[kCombThreads];
+    __shared__ int red_p[kCombWaves];
+    __shared__ int woff_p[kCombWaves + 1];
+    const bool map_in_lds = a.max_wg + 1 <= kMapLds;
+    int* map = map_in_lds ? map_lds : a.wgmap;
+    for (int w = tid; w <= a.max_wg; w += kCombThreads) map[w] = -1;
+    int carry_b = 0, e_carry = 0;
+    for (int base = 0; base < nt; base += CHUNK) {
+        if (!one_round) {
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < KPER; ++k) {
+                const int t = base + tid * KPER + k;
+                Ek[k] = t < nt ? tab[t].E : 0;
+            }
+        }
+        // end slot of the tile before this thread's first tile
+        const int tl = base + tid * KPER + KPER - 1;
+        e_last[tid] = tl < nt ? Ek[KPER - 1] : n;
+        __syncthreads();
+        int e_before = tid > 0 ? e_last[tid - 1] : e_carry;
+        int P[KPER];
+        int locp = 0;
+#pragma unroll
+        for (int k = 0; k < KPER; ++k) {
+            const int t = base + tid * KPER + k;
+            P[k] = 0;
+            if (t < nt) {
+                const int slots = Ek[k] - e_before;
+                const int tt = min(kTile, n - t * kTile);
+                P[k] = slots > 0 ? (tt + slots + kScatterItems - 1) / kScatterItems : 0;
+                e_before = Ek[k];
+            }
+            locp += P[k];
+        }
+        e_carry = e_last[kCombThreads - 1];
+        const int sp = wave_incl_scan<OpAdd>(locp);
+        if (lane == 63) red_p[wv] = sp;
+        __syncthreads();
+        if (wv == 0) {
+            int tv = lane < kCombWaves ? red_p[lane] : 0;
+            tv = wave_incl_scan<OpAdd>(tv);
+            if (lane < kCombWaves) woff_p[lane + 1] = carry_b + tv;
+            if (lane == 0) woff_p[0] = carry_b;
+        }
+        __syncthreads();
+        int run = woff_p[wv] + sp - locp;
+#pragma unroll
+        for (int k = 0; k < KPER; ++k) {
+            const int t = base + tid * KPER + k;
+            if (t < nt) {
+                tab[t].B = run;
+                if (P[k] > 0) map[run] = t;
+            }
+            run += P[k];
+        }
+        carry_b = woff_p[kCombWaves];
+    }
+    const int n_wg = carry_b;
+    __syncthreads();
+    // prefix maximum of the map: contiguous chunks per thread, then a scan of
+    // the chunk maxima; the result goes to the global map
+    {
+        const int per = (n_wg + kCombThreads - 1) / kCombThreads;
+        const int w0 = min(tid * per, n_wg), w1 = min(w0 + per, n_wg);
+        int mx = -1;
+        for (int w = w0; w < w1; ++w) mx = max(mx, map[w]);
+        const int sm2 = wave_incl_scan<OpMax>(mx);
+        if (lane == 63) red_p[wv] = sm2;
+        __syncthreads();
+        if (wv == 0) {
+            int tv = lane < kCombWaves ? red_p[lane] : -1;
+            tv = wave_incl_scan<OpMax>(tv);
+            if (lane < kCombWaves) woff_p[lane + 1] = tv;
+            if (lane == 0) woff_p[0] = -1;
+        }
+        __syncthreads();
+        int cur = max(woff_p[wv], wave_shift_up1(sm2, -1));
+        for (int w = w0; w < w1; ++w) {
+            cur = max(cur, map[w]);
+            a.wgmap[w] = cur;
+        }
+    }
+
+    if (tid == 0) {
+        b->n_wg = n_wg;
+        if constexpr (F64) {
+            tab[0].off = 0.0;
+            b->M = gm;
+            b->Z = Z;
+            b->u0 = u0d;
+            b->R = Rr;
+            b->est_x = sx / Z;
+            b->est_y = sy / Z;
+        } else {
             tab[0].off_hi = 0.f;
             tab[0].off_lo = 0.f;
-            const float Zf = carry.hi + carry.lo;
+            const float Zf = Z.hi + Z.lo;
             const int cnx = b->cn_x, cny = b->cn_y;
             const float ox = (float)cnx + sx / Zf;
             const float oy = (float)cny + sy / Zf;
@@ -864,11 +966,11 @@ __global__ __launch_bounds__(kBlock) void combine_kernel(StepArgs a)
             b->est_x = (double)ox;
             b->est_y = (double)oy;
             b->Zf = Zf;
-            b->Smax = Smax;
-            b->R_hi = sm.R.hi;
-            b->R_lo = sm.R.lo;
-            b->u0_hi = u0.hi;
-            b->u0_lo = u0.lo;
+            b->Smax = gm;
+            b->R_hi = Rr.hi;
+            b->R_lo = Rr.lo;
+            b->u0_hi = u0f.hi;
+            b->u0_lo = u0f.lo;
             // the stored positions become relative to this step's origin; the
             // next propagation is centred on the predicted position
             b->ci_x = cnx;
@@ -879,101 +981,83 @@ __global__ __launch_bounds__(kBlock) void combine_kernel(StepArgs a)
             b->cn_y = offset_cell(py_, 0, -2000000, 2000000);
         }
     }
-    (void)tile;
 }
 
 // ---------------------------------------------------------------------------
-// Pass C: merge-path scatter.
+// Pass C: merge-path scatter, one tile per workgroup.
 //
-// g(i) = e_i + i is strictly increasing; the merge-path split of diagonal d
-// (particles among the first d merged items, a particle going before slot j
-// when e_i <= j) is the first i with g(i) >= d.  It is found in two levels by
-// one wave: over tiles with G_t = g(last particle of tile t) = E_t + last,
-// then inside the tile; each level is a 64-ary search (every lane tests one
-// candidate, a ballot picks the first true one), so a split costs a few
-// memory round trips instead of a binary search's ~20.
-
-template <typename Pred>
-__device__ __forceinline__ int64_t wave_first_true(int64_t lo, int64_t hi, int lane, const Pred& pred)
-{
-    // first k in [lo, hi] with pred(k); pred(hi) is taken as true
-    while (lo < hi) {
-        const int64_t n = hi - lo;
-        if (n <= 64) {
-            const bool p = lane < n ? pred(lo + lane) : false;
-            const uint64_t m = __ballot(p);
-            return m ? lo + __builtin_ctzll(m) : hi;
-        }
-        const int64_t step = (n + 63) / 64;
-        const int64_t k = lo + (int64_t)(lane + 1) * step - 1;
-        const bool p = k < hi ? pred(k) : true;
-        const uint64_t m = __ballot(p);
-        if (!m) return hi;
-        const int f = __builtin_ctzll(m);
-        const int64_t kf = lo + (int64_t)(f + 1) * step - 1;
-        const int64_t nhi = kf < hi ? kf : hi;
-        lo = f == 0 ? lo : lo + (int64_t)f * step;
-        hi = nhi;
-    }
-    return lo;
-}
-
-template <typename E>
-__device__ int64_t merge_split_wave(const E& e, int64_t d, int64_t n, int tile, int ntiles, int lane)
-{
-    if (d >= 2 * n) return n;
-    auto last_of = [&](int64_t t) { const int64_t l = (t + 1) * (int64_t)tile - 1; return l < n - 1 ? l : n - 1; };
-    const int64_t t = wave_first_true(0, ntiles - 1, lane, [&](int64_t tt) {
-        return e.tile_end((int)tt) + last_of(tt) >= d;
-    });
-    return wave_first_true(t * (int64_t)tile, last_of(t), lane, [&](int64_t i) { return e(i) + i >= d; });
-}
+// The slots of tile t are [E_{t-1}, E_t); inside the tile, particle k owns
+// the local slots [e_{k-1}, e_k) (local end slots e_k = e_i - E_{t-1}).  The
+// tile's particles and slots form two sorted sequences whose merge (a
+// particle going before local slot j when e_k <= j) is cut into pieces of
+// kScatterItems items, one per workgroup: with g(k) = e_k + k strictly
+// increasing, the cut at diagonal d is the first k with g(k) >= d.  Each
+// workgroup computes the end slots of its whole tile into LDS (one pass over
+// the tile's cumulative weights), finds its two cuts there, and writes the
+// ancestors' propagated positions to its slots.
 
 template <int DT>
 __global__ __launch_bounds__(kBlock) void pass_c_kernel(StepArgs a)
 {
     using Store = typename ModeT<DT>::Store;
     constexpr int D = kScatterItems;
-    __shared__ int64_t sp[2];
-    __shared__ int32_t s_e[D + 1];
-    __shared__ Store s_x[D + 1];
-    __shared__ Store s_y[D + 1];
+    constexpr int IPT = D / kBlock;  // merge items per thread
+    __shared__ int32_t s_e[kTile];
+    __shared__ Store s_x[kTile];
+    __shared__ Store s_y[kTile];
 
-    const int64_t n = a.n;
-    const auto e = make_end_slot<DT>(a);
-    const int64_t d0 = (int64_t)blockIdx.x * D;
-    const int64_t d1 = d0 + D < 2 * n ? d0 + D : 2 * n;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    if (wv < 2) {
-        const int64_t i = merge_split_wave(e, wv == 0 ? d0 : d1, n, tile_of(DT), a.ntiles, lane);
-        if (lane == 0) sp[wv] = i;
-    }
-    __syncthreads();
-    const int64_t i0 = sp[0], i1 = sp[1];
-    const int64_t j0 = d0 - i0, j1 = d1 - i1;
-    const int64_t iend = i1 < n - 1 ? i1 : n - 1;
-    const int ni = (int)(iend - i0 + 1);
+    const int w = blockIdx.x;
+    if (w >= a.blk->n_wg) return;
+    const int n = (int)a.n;
+    const int t = a.wgmap[w];
+    const TileSlotsT<DT> ts(a, t);
+    const int part = w - ts.B;
+    const int slots = ts.E - ts.Eprev;
+    const int first = t * kTile;
+    const int tt = min(kTile, n - first);
+    const int total = tt + slots;
+    const int d0 = part * D;
+    const int d1 = min(d0 + D, total);
+    const int tid = threadIdx.x;
+
     const Store* px = static_cast<const Store*>(a.px);
     const Store* py = static_cast<const Store*>(a.py);
-    for (int k = tid; k < ni; k += kBlock) {
-        s_e[k] = (int32_t)e(i0 + k);
-        s_x[k] = px[i0 + k];
-        s_y[k] = py[i0 + k];
+#pragma unroll
+    for (int r = 0; r < kTile / kBlock; ++r) {
+        const int k = tid + r * kBlock;
+        if (k < tt) {
+            const int e = k == tt - 1 ? ts.E : ts(a.q, first + k, n);
+            s_e[k] = e - ts.Eprev;
+            s_x[k] = px[first + k];
+            s_y[k] = py[first + k];
+        }
     }
     __syncthreads();
+    // this thread's share of the merge: diagonals [ds, de)
+    const int items = d1 - d0;
+    const int ds = d0 + min(tid * IPT, items), de = d0 + min((tid + 1) * IPT, items);
+    if (ds >= de) return;
+    // first k in [0, tt] with s_e[k] + k >= ds (k = tt stands for true)
+    int lo = 0, hi = tt;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (s_e[mid] + mid >= ds) hi = mid;
+        else lo = mid + 1;
+    }
+    int k = lo, j = ds - lo;
     Store* sx = static_cast<Store*>(a.sx);
     Store* sy = static_cast<Store*>(a.sy);
-    for (int64_t j = j0 + tid; j < j1; j += kBlock) {
-        // ancestor: the first particle of the range whose end slot exceeds j
-        int lo = 0, hi = ni - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (s_e[mid] > j) hi = mid;
-            else lo = mid + 1;
+    for (int d = ds; d < de; ++d) {
+        if (k < tt && s_e[k] <= j) {
+            ++k;  // particle k has no slot left: the merge takes it
+        } else {
+            const int kk = min(k, tt - 1);
+            const int slot = ts.Eprev + j;
+            sx[slot] = s_x[kk];
+            sy[slot] = s_y[kk];
+            if (a.dg_anc) a.dg_anc[slot] = first + kk;
+            ++j;
         }
-        sx[j] = s_x[lo];
-        sy[j] = s_y[lo];
-        if (a.dg_anc) a.dg_anc[j] = (int32_t)(i0 + lo);
     }
 }
 
@@ -982,9 +1066,9 @@ __global__ __launch_bounds__(kBlock) void pass_c_kernel(StepArgs a)
 template <int DT>
 __global__ __launch_bounds__(kBlock) void diag_weights_kernel(StepArgs a)
 {
-    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (k >= a.n) return;
-    const int t = (int)(k / tile_of(DT));
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= (int)a.n) return;
+    const int t = k / kTile;
     if constexpr (DT == PF_F64) {
         const TileTab64* tab = static_cast<const TileTab64*>(a.tab);
         a.dg_w[k] = a.dg_w[k] * tab[t].f / a.blk->Z;
@@ -1022,9 +1106,8 @@ static hipError_t launch_pass_a_t(const StepArgs& a, hipStream_t s)
 template <int DT>
 static hipError_t launch_pass_c_t(const StepArgs& a, hipStream_t s)
 {
-    const int64_t items = 2 * a.n;
-    const dim3 gc((unsigned)((items + kScatterItems - 1) / kScatterItems));
-    pass_c_kernel<DT><<<gc, dim3(kBlock), 0, s>>>(a);
+    // one workgroup per map entry; entries past the step's count exit at once
+    pass_c_kernel<DT><<<dim3((unsigned)a.max_wg), dim3(kBlock), 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -1039,13 +1122,22 @@ hipError_t launch_pass_a(int dtype, const StepArgs& a, hipStream_t s)
     }
 }
 
+template <int DT>
+static void launch_combine_t(const StepArgs& a, hipStream_t s)
+{
+    const dim3 g(1), blk(kCombThreads);
+    if (a.ntiles <= kCombThreads) combine_kernel<DT, 1><<<g, blk, 0, s>>>(a);
+    else if (a.ntiles <= 4 * kCombThreads) combine_kernel<DT, 4><<<g, blk, 0, s>>>(a);
+    else combine_kernel<DT, 16><<<g, blk, 0, s>>>(a);
+}
+
 hipError_t launch_combine(int dtype, const StepArgs& a, hipStream_t s)
 {
     switch (dtype) {
-    case PF_F64: combine_kernel<PF_F64><<<1, kBlock, 0, s>>>(a); break;
-    case PF_F32: combine_kernel<PF_F32><<<1, kBlock, 0, s>>>(a); break;
-    case PF_F16: combine_kernel<PF_F16><<<1, kBlock, 0, s>>>(a); break;
-    case PF_BF16: combine_kernel<PF_BF16><<<1, kBlock, 0, s>>>(a); break;
+    case PF_F64: launch_combine_t<PF_F64>(a, s); break;
+    case PF_F32: launch_combine_t<PF_F32>(a, s); break;
+    case PF_F16: launch_combine_t<PF_F16>(a, s); break;
+    case PF_BF16: launch_combine_t<PF_BF16>(a, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

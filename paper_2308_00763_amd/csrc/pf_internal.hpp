@@ -11,7 +11,7 @@ namespace pf {
 
 constexpr int kBlock = 256;        // threads per workgroup of every pass
 constexpr int kWaves = kBlock / 64;
-constexpr int kMaxTile = 1024;     // largest particles-per-workgroup tile
+constexpr int kTile = 1024;        // particles per pass-A workgroup (4 per thread)
 constexpr int kScatterItems = 2048; // merge-path items (particles + slots) per workgroup
 constexpr int kPrefPitch = 130;    // LDS row-prefix table: u16 entries per window row (65 dwords)
 constexpr int kPrefRows = 64;      // LDS row-prefix table: window rows
@@ -19,18 +19,19 @@ constexpr int kWinMaxW = 128;      // widest frame window staged in LDS
 constexpr int kMaxRadius = 32;
 
 // Particles per thread and tile size per precision mode.
-__host__ __device__ constexpr int ppt_of(int /*dtype*/) { return 4; }
-__host__ __device__ constexpr int tile_of(int dtype) { return kBlock * ppt_of(dtype); }
+__host__ __device__ constexpr int tile_of(int /*dtype*/) { return kTile; }
 __host__ __device__ constexpr int elt_of(int dtype) { return dtype == PF_F64 ? 8 : dtype == PF_F32 ? 4 : 2; }
 
 // Per-filter scalars in device memory (first 256 bytes of the workspace).
 struct DevBlock {
-    uint32_t pad0[2];
+    int32_t n_wg;         // pass-C workgroups of the latest step
+    uint32_t pad0;
     int32_t ci_x, ci_y;   // reduced modes: origin cell of the stored positions
     int32_t cn_x, cn_y;   // reduced modes: origin cell of the next propagation
     double est_x, est_y;  // estimate of the latest step
-    // double mode: normaliser and maximum log-likelihood of the latest step
-    double Z, M, u0;
+    // double mode: normaliser, maximum log-likelihood, resampling offset and
+    // R = N / Z of the latest step
+    double Z, M, u0, R;
     // reduced modes: the same in float / two-float form
     float Zf, u0_hi, u0_lo, R_hi, R_lo;  // R = N / Z
     int32_t Smax;
@@ -50,20 +51,23 @@ struct TileRec32 {
 // Per-tile table written by the combine: cumulative weight before the tile
 // (two-float in reduced modes; entry ntiles holds the total), the factor
 // exp(m_t - M), and E = the end slot of the tile's last particle.
+// B = index of the first pass-C workgroup of the tile (the tile takes
+// ceil((particles + slots) / kScatterItems) workgroups, none without slots).
 struct TileTab64 {
     double off, f;
-    int64_t E;
+    int32_t E, B;
 };
 struct TileTab32 {
     float off_hi, off_lo, f;
-    int32_t E;
+    int32_t E, B, pad;
 };
 
 // Workspace layout; offsets in bytes from the workspace base.
 struct Layout {
     int64_t n, n_pad;
     int tile, ntiles;
-    size_t blk, rec, tab, sx, sy, px, py, q, dg_s, dg_w, dg_anc, total;
+    int max_wg;  // upper bound of pass-C workgroups
+    size_t blk, rec, tab, wgmap, sx, sy, px, py, q, dg_s, dg_w, dg_anc, total;
 };
 
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -83,6 +87,9 @@ inline Layout make_layout(const pf_params& p)
     L.blk = o; o += 256;
     L.rec = o; o = align256(o + rec * (size_t)L.ntiles);
     L.tab = o; o = align256(o + tab * (size_t)(L.ntiles + 1));
+    // sum over tiles of ceil((T_t + s_t) / D) <= ntiles + 2N / D
+    L.max_wg = L.ntiles + (int)((2 * L.n + kScatterItems - 1) / kScatterItems);
+    L.wgmap = o; o = align256(o + 4 * (size_t)(L.max_wg + 1));
     L.sx = o; o = align256(o + elt * (size_t)L.n_pad);
     L.sy = o; o = align256(o + elt * (size_t)L.n_pad);
     L.px = o; o = align256(o + elt * (size_t)L.n_pad);
@@ -119,6 +126,8 @@ struct StepArgs {
     void* px;
     void* py;
     void* q;
+    int32_t* wgmap;     // pass-C workgroup -> tile
+    int32_t max_wg;
     int32_t* dg_s;      // diagnostics (may be null)
     double* dg_w;
     int32_t* dg_anc;

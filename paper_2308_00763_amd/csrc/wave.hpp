@@ -3,7 +3,10 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 namespace pf {
 
@@ -21,59 +24,107 @@ __device__ __forceinline__ T shfl_up(T v, int d)
     return __shfl_up(v, (unsigned)d, kWave);
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_max(T v)
+// ---------------------------------------------------------------------------
+// Cross-lane moves through DPP (data-parallel primitives of the VALU; no LDS
+// traffic).  Control codes of gfx9: row_shr:n = 0x110 + n (shift within a
+// row of 16 lanes), row_bcast:15 = 0x142 (lane 15 of each row to the whole
+// next row), row_bcast:31 = 0x143 (lane 31 to rows 2 and 3), wave_shr:1 =
+// 0x138 (whole-wave shift by one lane).  Lanes whose source is outside the
+// pattern, or whose row is masked off, receive `fill`.
+
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ int dpp_i(int v, int fill)
 {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        const T o = shfl_xor(v, m);
-        v = o > v ? o : v;
+    return __builtin_amdgcn_update_dpp(fill, v, CTRL, ROW_MASK, 0xF, false);
+}
+
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ float dpp_f(float v, float fill)
+{
+    return __int_as_float(dpp_i<CTRL, ROW_MASK>(__float_as_int(v), __float_as_int(fill)));
+}
+
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ double dpp_d(double v, double fill)
+{
+    const int lo = dpp_i<CTRL, ROW_MASK>(__double2loint(v), __double2loint(fill));
+    const int hi = dpp_i<CTRL, ROW_MASK>(__double2hiint(v), __double2hiint(fill));
+    return __hiloint2double(hi, lo);
+}
+
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ int dpp(int v, int fill) { return dpp_i<CTRL, ROW_MASK>(v, fill); }
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ float dpp(float v, float fill) { return dpp_f<CTRL, ROW_MASK>(v, fill); }
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ double dpp(double v, double fill) { return dpp_d<CTRL, ROW_MASK>(v, fill); }
+
+struct OpAdd {
+    template <typename T> __device__ static T apply(T a, T b) { return a + b; }
+    template <typename T> __device__ static T identity() { return T(0); }
+};
+struct OpMax {
+    template <typename T> __device__ static T apply(T a, T b) { return a > b ? a : b; }
+    template <typename T> __device__ static T identity()
+    {
+        if constexpr (std::is_same<T, int>::value) return INT32_MIN;
+        else return -INFINITY;
     }
+};
+struct OpMin {
+    template <typename T> __device__ static T apply(T a, T b) { return a < b ? a : b; }
+    template <typename T> __device__ static T identity()
+    {
+        if constexpr (std::is_same<T, int>::value) return INT32_MAX;
+        else return INFINITY;
+    }
+};
+
+// Inclusive scan over the 64 lanes (Hillis-Steele inside each row of 16,
+// then the row totals carried by the two row broadcasts).  Every lane must
+// be active.  For a sum this is the same association on every call, so the
+// result is reproducible bit for bit.
+template <typename Op, typename T>
+__device__ __forceinline__ T wave_incl_scan(T v)
+{
+    const T id = Op::template identity<T>();
+    v = Op::apply(v, dpp<0x111>(v, id));
+    v = Op::apply(v, dpp<0x112>(v, id));
+    v = Op::apply(v, dpp<0x114>(v, id));
+    v = Op::apply(v, dpp<0x118>(v, id));
+    v = Op::apply(v, dpp<0x142, 0xA>(v, id));
+    v = Op::apply(v, dpp<0x143, 0xC>(v, id));
     return v;
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_min(T v)
+// Value of lane 63 (uniform result).
+__device__ __forceinline__ int lane63(int v) { return __builtin_amdgcn_readlane(v, 63); }
+__device__ __forceinline__ float lane63(float v) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63)); }
+__device__ __forceinline__ double lane63(double v)
 {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        const T o = shfl_xor(v, m);
-        v = o < v ? o : v;
-    }
-    return v;
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                            __builtin_amdgcn_readlane(__double2loint(v), 63));
+}
+
+// Previous lane's value (lane 0 receives `fill`).
+template <typename T>
+__device__ __forceinline__ T wave_shift_up1(T v, T fill)
+{
+    return dpp<0x138>(v, fill);
 }
 
 template <typename T>
-__device__ __forceinline__ T wave_sum(T v)
-{
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += shfl_xor(v, m);
-    return v;
-}
-
-// Inclusive prefix sum over the wave (Hillis-Steele).
+__device__ __forceinline__ T wave_max(T v) { return lane63(wave_incl_scan<OpMax>(v)); }
 template <typename T>
-__device__ __forceinline__ T wave_incl_sum(T v, int lane)
-{
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const T o = shfl_up(v, d);
-        if (lane >= d) v += o;
-    }
-    return v;
-}
-
-// Inclusive prefix maximum over the wave.
+__device__ __forceinline__ T wave_min(T v) { return lane63(wave_incl_scan<OpMin>(v)); }
 template <typename T>
-__device__ __forceinline__ T wave_incl_max(T v, int lane)
-{
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const T o = shfl_up(v, d);
-        if (lane >= d && o > v) v = o;
-    }
-    return v;
-}
+__device__ __forceinline__ T wave_sum(T v) { return lane63(wave_incl_scan<OpAdd>(v)); }
+
+// Inclusive prefix sum / maximum over the wave.
+template <typename T>
+__device__ __forceinline__ T wave_incl_sum(T v, int /*lane*/) { return wave_incl_scan<OpAdd>(v); }
+template <typename T>
+__device__ __forceinline__ T wave_incl_max(T v, int /*lane*/) { return wave_incl_scan<OpMax>(v); }
 
 // Workgroup-wide reductions for a block of NW waves.  `red` is LDS scratch of
 // at least NW elements; every thread receives the result.

@@ -161,6 +161,33 @@ def test_f64_matches_oracle_at_precision_sweep_size():
     print(f"[parity] f64 N=2^20 excused ties {ties}", flush=True)
 
 
+@pytest.mark.parametrize("n", [(1 << 20) + 777, (1 << 22) + 1])
+def test_f64_many_tiles(n):
+    # 1025 and 4097 tiles: the combine takes 4 and 16 tiles per thread
+    vid = pfsynth.moving_disk(512, 512, 3, 5, (256, 256), (1, -2), 2.0, seed=11)
+    for got, gs, est, ref in _run_teacher_forced("f64", n, vid, 5, 1, seed=3):
+        compare_f64_step(got, gs, est, ref, n)
+
+
+def test_f64_more_tiles_than_one_combine_round():
+    # 16389 tiles: the combine runs two rounds and carries the offset across
+    n = (1 << 24) + 5000
+    vid = pfsynth.moving_disk(512, 512, 2, 8, (256, 256), (1, -2), 8.0, seed=13)
+    for got, gs, est, ref in _run_teacher_forced("f64", n, vid, 8, 1, seed=5):
+        compare_f64_step(got, gs, est, ref, n)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+def test_reduced_modes_many_tiles(dtype):
+    n = (1 << 24) + 5000
+    vid = pfsynth.moving_disk(512, 512, 2, 8, (256, 256), (1, -2), 8.0, seed=13)
+    for got, gs, est, ref in _run_teacher_forced(dtype, n, vid, 8, 1, seed=5):
+        check_resample_consistency(got, gs, n)
+        d = tv(got["w"], ref["w"])
+        print(f"[parity] {dtype} N=2^24+5000 r=8 TV {d:.3e}", flush=True)
+        assert d <= 1e-2
+
+
 @pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
 @pytest.mark.parametrize("n", [1, 1025, 5000])
 def test_reduced_modes_small_and_ragged(dtype, n):
