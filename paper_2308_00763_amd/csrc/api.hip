@@ -206,8 +206,6 @@ int pf_init(const pf_params* p, void* d_workspace, size_t workspace_bytes, void*
     a.px = at(h, L.px);
     a.py = at(h, L.py);
     a.q = at(h, L.q);
-    a.wgmap = (int32_t*)at(h, L.wgmap);
-    a.max_wg = L.max_wg;
     if (p->flags & PF_FLAG_DIAGNOSTICS) {
         a.dg_s = (int32_t*)at(h, L.dg_s);
         a.dg_w = (double*)at(h, L.dg_w);

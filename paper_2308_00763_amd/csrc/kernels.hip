@@ -45,7 +45,8 @@ typedef float float2_t __attribute__((ext_vector_type(2)));
 // exactly the integer the per-pixel definition gives, with 2 (2r - 1) table
 // reads instead of one read per pixel.  The table holds, for every row of the
 // frame window a tile's particles look at, P[c] = sum of the window bytes in
-// columns [0, c), as u16 (a window row is at most 128 bytes wide).
+// columns [0, c), as u16 (a window row is at most 128 bytes wide), P[c] at
+// entry kPrefBase + c of the row.
 
 __host__ __device__ constexpr int disk_half_width_c(int r, int dy)
 {
@@ -65,8 +66,8 @@ struct DiskRows {
         for (int i = 0; i < ROWS; ++i) {
             const int dy = i - (R - 1);
             const int h = disk_half_width_c(R, dy);
-            plus[i] = i * kPrefPitch + (R - 1) + h + 1;
-            minus[i] = i * kPrefPitch + (R - 1) - h;
+            plus[i] = i * kPrefPitch + kPrefBase + (R - 1) + h + 1;
+            minus[i] = i * kPrefPitch + kPrefBase + (R - 1) - h;
         }
     }
 };
@@ -93,7 +94,7 @@ __device__ __forceinline__ int disk_sum_prefix(const uint16_t* p, int r)
     } else {
         for (int i = 0; i < 2 * r - 1; ++i) {
             const int h = disk_half_width(r, i - (r - 1));
-            const uint16_t* row = p + i * kPrefPitch + (r - 1);
+            const uint16_t* row = p + i * kPrefPitch + kPrefBase + (r - 1);
             s += (int)row[h + 1] - (int)row[-h];
         }
     }
@@ -404,39 +405,64 @@ __global__ __launch_bounds__(kBlock) void pass_a_kernel(StepArgs a)
     const int bx0 = b0, by0 = b1, bx1 = -b2, by1 = -b3;
 
     // Disk sums over the frame window of the tile: the window's row-prefix
-    // table is built in LDS.  Each wave takes every fourth window row, two
-    // columns per lane; all its row loads are issued before the first scan.
+    // table is built in LDS.  A window row is split over LPR lanes (16 for
+    // windows up to 64 columns, else 32), four columns per lane, so a wave
+    // covers 64 / LPR rows per round; every byte load of the wave is issued
+    // before the first scan, and each lane writes its four prefix values as
+    // two 32-bit LDS stores.
     const int wx0 = bx0 - (r - 1), wy0 = by0 - (r - 1);
     const int ww = bx1 - bx0 + 2 * r - 1, wh = by1 - by0 + 2 * r - 1;
     const bool in_lds = ww <= kWinMaxW && wh <= kPrefRows;
     int S[PPT];
     if (in_lds) {
-        constexpr int RPW = kPrefRows / kWaves;
-        const int c0 = 2 * lane, c1 = 2 * lane + 1;
-        const int col0 = min(max(wx0 + c0, 0), a.W - 1), col1 = min(max(wx0 + c1, 0), a.W - 1);
-        int v[RPW];
+        constexpr int kMaxRounds = kPrefRows / (kWaves * 2);  // 32-lane rows: 2 per wave per round
+        const bool narrow = ww <= 64;
+        const int lpr = narrow ? 16 : 32;
+        const int rpr = 64 / lpr;                 // rows per wave per round
+        const int sub = lane / lpr, l = lane - sub * lpr;
+        const int c0 = 4 * l;
+        const int rows_per_round = kWaves * rpr;
+        const int rounds = (wh + rows_per_round - 1) / rows_per_round;
+        uint32_t v[kMaxRounds];
 #pragma unroll
-        for (int k = 0; k < RPW; ++k) {
-            const int yy = wv + k * kWaves;
-            v[k] = 0;
-            if (yy < wh) {
+        for (int it = 0; it < kMaxRounds; ++it) {
+            const int yy = (it * kWaves + wv) * rpr + sub;
+            v[it] = 0;
+            if (it < rounds && yy < wh) {
                 const int row = min(max(wy0 + yy, 0), a.H - 1);
                 const uint8_t* rp = a.frame + (int64_t)row * a.pitch;
-                const int p0 = c0 < ww ? (int)rp[col0] : 0;
-                const int p1 = c1 < ww ? (int)rp[col1] : 0;
-                v[k] = p0 | (p1 << 16);
+                uint32_t pk = 0;
+#pragma unroll
+                for (int bb = 0; bb < 4; ++bb) {
+                    const int col = c0 + bb;
+                    if (col < ww) pk |= (uint32_t)rp[min(max(wx0 + col, 0), a.W - 1)] << (8 * bb);
+                }
+                v[it] = pk;
             }
         }
 #pragma unroll
-        for (int k = 0; k < RPW; ++k) {
-            const int yy = wv + k * kWaves;
-            if (yy < wh) {
-                const int p0 = v[k] & 0xFFFF, p1 = v[k] >> 16;
-                const int incl = wave_incl_sum(p0 + p1, lane);
-                uint16_t* prow = lds.pref + yy * kPrefPitch;
-                if (lane == 0) prow[0] = 0;
-                if (c0 < ww) prow[c0 + 1] = (uint16_t)(incl - p1);
-                if (c1 < ww) prow[c1 + 1] = (uint16_t)incl;
+        for (int it = 0; it < kMaxRounds; ++it) {
+            if (it < rounds) {  // uniform: every lane takes part in the scan
+                const int yy = (it * kWaves + wv) * rpr + sub;
+                const int p1 = (int)(v[it] & 0xFF);
+                const int p2 = p1 + (int)((v[it] >> 8) & 0xFF);
+                const int p3 = p2 + (int)((v[it] >> 16) & 0xFF);
+                const int p4 = p3 + (int)(v[it] >> 24);
+                // inclusive prefix of the 4-column sums over the lanes of one row
+                int sc = p4;
+                sc += dpp<0x111>(sc, 0);
+                sc += dpp<0x112>(sc, 0);
+                sc += dpp<0x114>(sc, 0);
+                sc += dpp<0x118>(sc, 0);
+                if (!narrow) sc += dpp<0x142, 0xA>(sc, 0);
+                const int ex = sc - p4;
+                if (yy < wh) {
+                    uint16_t* prow = lds.pref + yy * kPrefPitch + kPrefBase;
+                    if (l == 0) prow[0] = 0;
+                    uint32_t* w32 = reinterpret_cast<uint32_t*>(prow + c0 + 1);
+                    w32[0] = (uint32_t)(ex + p1) | ((uint32_t)(ex + p2) << 16);
+                    w32[1] = (uint32_t)(ex + p3) | ((uint32_t)(ex + p4) << 16);
+                }
             }
         }
         __syncthreads();
@@ -582,7 +608,7 @@ struct TileSlots;
 template <>
 struct TileSlots<PF_F64> {
     double base, scale, ymax;
-    int E, Eprev, B;
+    int E, Eprev;
     __device__ TileSlots(const StepArgs& a, int t)
     {
         const TileTab64* tab = static_cast<const TileTab64*>(a.tab);
@@ -591,7 +617,6 @@ struct TileSlots<PF_F64> {
         scale = R * tab[t].f;
         ymax = R * tab[t + 1].off - u0;
         E = tab[t].E;
-        B = tab[t].B;
         Eprev = t > 0 ? tab[t - 1].E : 0;
     }
     __device__ int operator()(const void* q, int i, int n) const
@@ -605,7 +630,7 @@ struct TileSlots<PF_F64> {
 template <>
 struct TileSlots<PF_F32> {
     ff base, scale, ymax;
-    int E, Eprev, B;
+    int E, Eprev;
     __device__ TileSlots(const StepArgs& a, int t)
     {
         const TileTab32* tab = static_cast<const TileTab32*>(a.tab);
@@ -614,7 +639,6 @@ struct TileSlots<PF_F32> {
         scale = ff_mul_f(R, tab[t].f);
         ymax = ff_add(ff_mul(R, ff{tab[t + 1].off_hi, tab[t + 1].off_lo}), mu0);
         E = tab[t].E;
-        B = tab[t].B;
         Eprev = t > 0 ? tab[t - 1].E : 0;
     }
     __device__ int operator()(const void* q, int i, int n) const
@@ -681,7 +705,7 @@ struct CombAcc<PF_F64> {
     static __device__ T add(T a, T b) { return a + b; }
     static __device__ T min_(T a, T b) { return a < b ? a : b; }
     static __device__ T max_(T a, T b) { return a > b ? a : b; }
-    static __device__ T scan(T v) { return wave_incl_max(wave_incl_sum(v, 0), 0); }
+    static __device__ T sum_scan(T v) { return wave_incl_sum(v, 0); }
     static __device__ T last(T v) { return lane63(v); }
     static __device__ T up1(T v, T fill) { return wave_shift_up1(v, fill); }
 };
@@ -693,7 +717,7 @@ struct CombAcc<PF_F32> {
     static __device__ T add(T a, T b) { return ff_add(a, b); }
     static __device__ T min_(T a, T b) { return ff_min(a, b); }
     static __device__ T max_(T a, T b) { return ff_max(a, b); }
-    static __device__ T scan(T v) { return wave_incl_max_ff(wave_incl_sum_ff(v)); }
+    static __device__ T sum_scan(T v) { return wave_incl_sum_ff(v); }
     static __device__ T last(T v) { return ff{lane63(v.hi), lane63(v.lo)}; }
     static __device__ T up1(T v, T fill) { return ff{wave_shift_up1(v.hi, fill.hi), wave_shift_up1(v.lo, fill.lo)}; }
 };
@@ -714,6 +738,8 @@ __global__ __launch_bounds__(kCombThreads) void combine_kernel(StepArgs a)
     __shared__ T red_s[kCombWaves];
     __shared__ T wave_off[kCombWaves + 1];
     __shared__ Fv red_x[kCombWaves], red_y[kCombWaves];
+    __shared__ int red_e[kCombWaves];
+    __shared__ int woff_e[kCombWaves + 1];
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int nt = a.ntiles;
@@ -742,12 +768,11 @@ __global__ __launch_bounds__(kCombThreads) void combine_kernel(StepArgs a)
 #pragma unroll
     for (int w = 1; w < kCombWaves; ++w) gm = red_m[w] > gm ? red_m[w] : gm;
 
+    // carried offsets: kPER consecutive tiles per thread, a wave scan, then a
+    // scan of the wave totals by wave 0; the total is the normaliser
     const u32x4 wu = philox4x32_10(0u, a.t, a.stream_id, 1u, a.key0, a.key1);
     T carry = A::zero();
     Fv ex = 0, ey = 0;
-    // Pass 1 of 2 over the rounds computes the offsets and the normaliser;
-    // the end slots need the normaliser, so they are written in pass 2 from
-    // the offsets kept in the table (one round when nt <= CHUNK: registers).
     constexpr bool KEEP = KPER <= 4;  // keep offsets in registers for the end slots
     T o_keep[KEEP ? KPER : 1];
     for (int base = 0; base < nt; base += CHUNK) {
@@ -773,34 +798,28 @@ __global__ __launch_bounds__(kCombThreads) void combine_kernel(StepArgs a)
             }
             loc = A::add(loc, v[k]);
         }
-        // level 1: monotone inclusive scan inside the wave
-        const T sw = A::scan(loc);
+        const T sw = A::sum_scan(loc);
         if (lane == 63) red_s[wv] = sw;
         __syncthreads();
-        // level 2: wave 0 scans the wave totals
         if (wv == 0) {
             T tv = lane < kCombWaves ? red_s[lane] : A::zero();
-            tv = A::scan(tv);
+            tv = A::sum_scan(tv);
             if (lane < kCombWaves) wave_off[lane + 1] = A::add(carry, tv);
             if (lane == 0) wave_off[0] = carry;
         }
         __syncthreads();
-        const T off = wave_off[wv], off_next = wave_off[wv + 1];
-        const T incl = A::min_(A::add(off, sw), off_next);
-        const T excl = A::up1(incl, off);
-        T run = A::zero(), prev = excl;
+        const T off = wave_off[wv];
+        const T excl = A::up1(A::add(off, sw), off);
+        T run = excl;
 #pragma unroll
         for (int k = 0; k < KPER; ++k) {
             const int t = base + tid * KPER + k;
             run = A::add(run, v[k]);
-            T o = A::min_(A::add(excl, run), incl);
-            o = A::max_(o, prev);
-            prev = o;
-            if constexpr (KEEP) o_keep[k] = o;
+            if constexpr (KEEP) o_keep[k] = run;
             if (t < nt) {
                 tab[t].f = f[k];
-                if constexpr (F64) tab[t + 1].off = o;
-                else { tab[t + 1].off_hi = o.hi; tab[t + 1].off_lo = o.lo; }
+                if constexpr (F64) tab[t + 1].off = run;
+                else { tab[t + 1].off_hi = run.hi; tab[t + 1].off_lo = run.lo; }
             }
         }
         carry = wave_off[kCombWaves];
@@ -815,8 +834,10 @@ __global__ __launch_bounds__(kCombThreads) void combine_kernel(StepArgs a)
 #pragma unroll
     for (int w = 1; w < kCombWaves; ++w) { sx = sx + red_x[w]; sy = sy + red_y[w]; }
 
-    // end slots of every tile: y = R off_{t+1} - u0 (the expression pass C
-    // caps its tiles with)
+    // End slot of every tile, y = R off_{t+1} - u0 (the expression pass C caps
+    // its tiles with), made non-decreasing by a prefix maximum so that the
+    // tiles' slot ranges [E_{t-1}, E_t) partition [0, N) whatever the
+    // rounding of the offsets; the last tile ends at N.
     using Y = typename std::conditional<F64, double, ff>::type;
     Y Rr, mu0;
     double u0d = 0.0;
@@ -838,8 +859,10 @@ __global__ __launch_bounds__(kCombThreads) void combine_kernel(StepArgs a)
         else return slot_end_of(ff_add(ff_mul(Rr, o), mu0), n);
     };
     const bool one_round = KEEP && nt <= CHUNK;
-    int Ek[KPER];
+    int carry_e = 0;
     for (int base = 0; base < nt; base += CHUNK) {
+        int Ek[KPER];
+        int mx = carry_e;
 #pragma unroll
         for (int k = 0; k < KPER; ++k) {
             const int t = base + tid * KPER + k;
@@ -850,103 +873,31 @@ __global__ __launch_bounds__(kCombThreads) void combine_kernel(StepArgs a)
                 else if constexpr (F64) o = tab[t + 1].off;
                 else o = ff{tab[t + 1].off_hi, tab[t + 1].off_lo};
                 Ek[k] = t == nt - 1 ? n : end_of(o);
-                tab[t].E = Ek[k];
             }
+            mx = max(mx, Ek[k]);
         }
-    }
-
-    // Pass-C work split: tile t takes P_t = ceil((T_t + s_t) / D) workgroups
-    // (none when it has no slots), numbered from B_t = P_0 + ... + P_{t-1};
-    // the workgroup -> tile map is the prefix maximum of the tile starts.  The
-    // map is built in LDS when it fits, else in global memory.
-    constexpr int kMapLds = 8192;
-    __shared__ int map_lds[kMapLds];
-    __shared__ int e_last[kCombThreads];
-    __shared__ int red_p[kCombWaves];
-    __shared__ int woff_p[kCombWaves + 1];
-    const bool map_in_lds = a.max_wg + 1 <= kMapLds;
-    int* map = map_in_lds ? map_lds : a.wgmap;
-    for (int w = tid; w <= a.max_wg; w += kCombThreads) map[w] = -1;
-    int carry_b = 0, e_carry = 0;
-    for (int base = 0; base < nt; base += CHUNK) {
-        if (!one_round) {
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < KPER; ++k) {
-                const int t = base + tid * KPER + k;
-                Ek[k] = t < nt ? tab[t].E : 0;
-            }
-        }
-        // end slot of the tile before this thread's first tile
-        const int tl = base + tid * KPER + KPER - 1;
-        e_last[tid] = tl < nt ? Ek[KPER - 1] : n;
-        __syncthreads();
-        int e_before = tid > 0 ? e_last[tid - 1] : e_carry;
-        int P[KPER];
-        int locp = 0;
-#pragma unroll
-        for (int k = 0; k < KPER; ++k) {
-            const int t = base + tid * KPER + k;
-            P[k] = 0;
-            if (t < nt) {
-                const int slots = Ek[k] - e_before;
-                const int tt = min(kTile, n - t * kTile);
-                P[k] = slots > 0 ? (tt + slots + kScatterItems - 1) / kScatterItems : 0;
-                e_before = Ek[k];
-            }
-            locp += P[k];
-        }
-        e_carry = e_last[kCombThreads - 1];
-        const int sp = wave_incl_scan<OpAdd>(locp);
-        if (lane == 63) red_p[wv] = sp;
+        const int sm = wave_incl_scan<OpMax>(mx);
+        if (lane == 63) red_e[wv] = sm;
         __syncthreads();
         if (wv == 0) {
-            int tv = lane < kCombWaves ? red_p[lane] : 0;
-            tv = wave_incl_scan<OpAdd>(tv);
-            if (lane < kCombWaves) woff_p[lane + 1] = carry_b + tv;
-            if (lane == 0) woff_p[0] = carry_b;
-        }
-        __syncthreads();
-        int run = woff_p[wv] + sp - locp;
-#pragma unroll
-        for (int k = 0; k < KPER; ++k) {
-            const int t = base + tid * KPER + k;
-            if (t < nt) {
-                tab[t].B = run;
-                if (P[k] > 0) map[run] = t;
-            }
-            run += P[k];
-        }
-        carry_b = woff_p[kCombWaves];
-    }
-    const int n_wg = carry_b;
-    __syncthreads();
-    // prefix maximum of the map: contiguous chunks per thread, then a scan of
-    // the chunk maxima; the result goes to the global map
-    {
-        const int per = (n_wg + kCombThreads - 1) / kCombThreads;
-        const int w0 = min(tid * per, n_wg), w1 = min(w0 + per, n_wg);
-        int mx = -1;
-        for (int w = w0; w < w1; ++w) mx = max(mx, map[w]);
-        const int sm2 = wave_incl_scan<OpMax>(mx);
-        if (lane == 63) red_p[wv] = sm2;
-        __syncthreads();
-        if (wv == 0) {
-            int tv = lane < kCombWaves ? red_p[lane] : -1;
+            int tv = lane < kCombWaves ? red_e[lane] : carry_e;
             tv = wave_incl_scan<OpMax>(tv);
-            if (lane < kCombWaves) woff_p[lane + 1] = tv;
-            if (lane == 0) woff_p[0] = -1;
+            if (lane < kCombWaves) woff_e[lane + 1] = max(carry_e, tv);
+            if (lane == 0) woff_e[0] = carry_e;
         }
         __syncthreads();
-        int cur = max(woff_p[wv], wave_shift_up1(sm2, -1));
-        for (int w = w0; w < w1; ++w) {
-            cur = max(cur, map[w]);
-            a.wgmap[w] = cur;
+        int run = max(woff_e[wv], wave_shift_up1(sm, carry_e));
+#pragma unroll
+        for (int k = 0; k < KPER; ++k) {
+            const int t = base + tid * KPER + k;
+            run = max(run, Ek[k]);
+            if (t < nt) tab[t].E = run;
         }
+        carry_e = woff_e[kCombWaves];
+        __syncthreads();
     }
 
     if (tid == 0) {
-        b->n_wg = n_wg;
         if constexpr (F64) {
             tab[0].off = 0.0;
             b->M = gm;
@@ -984,40 +935,33 @@ __global__ __launch_bounds__(kCombThreads) void combine_kernel(StepArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// Pass C: merge-path scatter, one tile per workgroup.
+// Pass C: merge-path scatter, one workgroup per tile.
 //
 // The slots of tile t are [E_{t-1}, E_t); inside the tile, particle k owns
-// the local slots [e_{k-1}, e_k) (local end slots e_k = e_i - E_{t-1}).  The
-// tile's particles and slots form two sorted sequences whose merge (a
-// particle going before local slot j when e_k <= j) is cut into pieces of
-// kScatterItems items, one per workgroup: with g(k) = e_k + k strictly
-// increasing, the cut at diagonal d is the first k with g(k) >= d.  Each
-// workgroup computes the end slots of its whole tile into LDS (one pass over
-// the tile's cumulative weights), finds its two cuts there, and writes the
-// ancestors' propagated positions to its slots.
+// the local slots [e_{k-1}, e_k) (local end slots e_k = e_i - E_{t-1},
+// non-decreasing, the last one E_t - E_{t-1}).  The tile's particles and slots
+// form two sorted sequences; their merge (a particle going before local slot
+// j when e_k <= j) is cut into equal pieces, one per thread: with
+// g(k) = e_k + k strictly increasing, the cut at diagonal d is the first k
+// with g(k) >= d.  Each thread finds its cut by a binary search over the
+// tile's end slots in LDS, then walks its piece, writing the ancestor's
+// propagated position to every slot it meets.  A tile that owns many slots
+// gives its threads longer pieces; the work never depends on how the slots
+// are spread inside the tile.
 
 template <int DT>
 __global__ __launch_bounds__(kBlock) void pass_c_kernel(StepArgs a)
 {
     using Store = typename ModeT<DT>::Store;
-    constexpr int D = kScatterItems;
-    constexpr int IPT = D / kBlock;  // merge items per thread
     __shared__ int32_t s_e[kTile];
     __shared__ Store s_x[kTile];
     __shared__ Store s_y[kTile];
 
-    const int w = blockIdx.x;
-    if (w >= a.blk->n_wg) return;
     const int n = (int)a.n;
-    const int t = a.wgmap[w];
+    const int t = blockIdx.x;
     const TileSlotsT<DT> ts(a, t);
-    const int part = w - ts.B;
-    const int slots = ts.E - ts.Eprev;
     const int first = t * kTile;
     const int tt = min(kTile, n - first);
-    const int total = tt + slots;
-    const int d0 = part * D;
-    const int d1 = min(d0 + D, total);
     const int tid = threadIdx.x;
 
     const Store* px = static_cast<const Store*>(a.px);
@@ -1033,9 +977,11 @@ __global__ __launch_bounds__(kBlock) void pass_c_kernel(StepArgs a)
         }
     }
     __syncthreads();
-    // this thread's share of the merge: diagonals [ds, de)
-    const int items = d1 - d0;
-    const int ds = d0 + min(tid * IPT, items), de = d0 + min((tid + 1) * IPT, items);
+    const int slots = ts.E - ts.Eprev;
+    if (slots <= 0) return;
+    const int total = tt + slots;
+    const int ipt = (total + kBlock - 1) / kBlock;
+    const int ds = min(tid * ipt, total), de = min(ds + ipt, total);
     if (ds >= de) return;
     // first k in [0, tt] with s_e[k] + k >= ds (k = tt stands for true)
     int lo = 0, hi = tt;
@@ -1106,8 +1052,7 @@ static hipError_t launch_pass_a_t(const StepArgs& a, hipStream_t s)
 template <int DT>
 static hipError_t launch_pass_c_t(const StepArgs& a, hipStream_t s)
 {
-    // one workgroup per map entry; entries past the step's count exit at once
-    pass_c_kernel<DT><<<dim3((unsigned)a.max_wg), dim3(kBlock), 0, s>>>(a);
+    pass_c_kernel<DT><<<dim3((unsigned)a.ntiles), dim3(kBlock), 0, s>>>(a);
     return hipGetLastError();
 }
 

@@ -12,8 +12,8 @@ namespace pf {
 constexpr int kBlock = 256;        // threads per workgroup of every pass
 constexpr int kWaves = kBlock / 64;
 constexpr int kTile = 1024;        // particles per pass-A workgroup (4 per thread)
-constexpr int kScatterItems = 2048; // merge-path items (particles + slots) per workgroup
-constexpr int kPrefPitch = 130;    // LDS row-prefix table: u16 entries per window row (65 dwords)
+constexpr int kPrefPitch = 134;    // LDS row-prefix table: u16 entries per window row (67 dwords)
+constexpr int kPrefBase = 3;       // entry of P[0] in a row (so P[4l+1..4l+4] is 4-byte aligned)
 constexpr int kPrefRows = 64;      // LDS row-prefix table: window rows
 constexpr int kWinMaxW = 128;      // widest frame window staged in LDS
 constexpr int kMaxRadius = 32;
@@ -24,8 +24,7 @@ __host__ __device__ constexpr int elt_of(int dtype) { return dtype == PF_F64 ? 8
 
 // Per-filter scalars in device memory (first 256 bytes of the workspace).
 struct DevBlock {
-    int32_t n_wg;         // pass-C workgroups of the latest step
-    uint32_t pad0;
+    uint32_t pad0[2];
     int32_t ci_x, ci_y;   // reduced modes: origin cell of the stored positions
     int32_t cn_x, cn_y;   // reduced modes: origin cell of the next propagation
     double est_x, est_y;  // estimate of the latest step
@@ -51,23 +50,20 @@ struct TileRec32 {
 // Per-tile table written by the combine: cumulative weight before the tile
 // (two-float in reduced modes; entry ntiles holds the total), the factor
 // exp(m_t - M), and E = the end slot of the tile's last particle.
-// B = index of the first pass-C workgroup of the tile (the tile takes
-// ceil((particles + slots) / kScatterItems) workgroups, none without slots).
 struct TileTab64 {
     double off, f;
-    int32_t E, B;
+    int32_t E, pad;
 };
 struct TileTab32 {
     float off_hi, off_lo, f;
-    int32_t E, B, pad;
+    int32_t E;
 };
 
 // Workspace layout; offsets in bytes from the workspace base.
 struct Layout {
     int64_t n, n_pad;
     int tile, ntiles;
-    int max_wg;  // upper bound of pass-C workgroups
-    size_t blk, rec, tab, wgmap, sx, sy, px, py, q, dg_s, dg_w, dg_anc, total;
+    size_t blk, rec, tab, sx, sy, px, py, q, dg_s, dg_w, dg_anc, total;
 };
 
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -87,9 +83,6 @@ inline Layout make_layout(const pf_params& p)
     L.blk = o; o += 256;
     L.rec = o; o = align256(o + rec * (size_t)L.ntiles);
     L.tab = o; o = align256(o + tab * (size_t)(L.ntiles + 1));
-    // sum over tiles of ceil((T_t + s_t) / D) <= ntiles + 2N / D
-    L.max_wg = L.ntiles + (int)((2 * L.n + kScatterItems - 1) / kScatterItems);
-    L.wgmap = o; o = align256(o + 4 * (size_t)(L.max_wg + 1));
     L.sx = o; o = align256(o + elt * (size_t)L.n_pad);
     L.sy = o; o = align256(o + elt * (size_t)L.n_pad);
     L.px = o; o = align256(o + elt * (size_t)L.n_pad);
@@ -126,8 +119,6 @@ struct StepArgs {
     void* px;
     void* py;
     void* q;
-    int32_t* wgmap;     // pass-C workgroup -> tile
-    int32_t max_wg;
     int32_t* dg_s;      // diagnostics (may be null)
     double* dg_w;
     int32_t* dg_anc;
