@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define PF_ABI_VERSION 1
+#define PF_ABI_VERSION 2
 
 typedef enum pf_status {
     PF_OK = 0,
@@ -176,6 +176,65 @@ const char* pf_last_error(void);
  * PF_ERR_HIP. */
 int pf_profile_start(pf_filter* h, uint32_t max_steps);
 int pf_profile_read(pf_filter* h, double out_ms[3], uint32_t* steps);
+
+/* ------------------------------------------------------------------------
+ * Batches: many independent filters (one per video stream, say), each running
+ * the step of pf_step (paper Sec. 2 and Sec. 4) on its own frame, advanced
+ * together with one launch per pass.  The filters of a batch share the dtype;
+ * everything else in their parameters may differ (N, frame size, radius,
+ * seeds, motion model).  A filter's results in a batch are bit-identical to
+ * the same filter run alone through pf_step with the same parameters, frames
+ * and step count: each of its workgroups runs the single-filter code on that
+ * filter's data, whatever else the batch holds.
+ */
+typedef struct pf_batch pf_batch;
+
+/* Device bytes for a batch of n filters (1 <= n <= 2^20) with parameters
+ * ps[0..n-1], all of one dtype, at most 2^31 - 1 tiles of 1024 particles in
+ * total.  Pure function.  Errors: PF_ERR_INVALID_ARG (the text names the
+ * first offending filter). */
+int pf_batch_workspace_bytes(const pf_params* ps, int32_t n, size_t* out_bytes);
+
+/* Initialise every filter of the batch as pf_init does, inside one caller-
+ * owned workspace (device memory, 256-byte aligned, at least
+ * pf_batch_workspace_bytes() bytes; the batch must not outlive it).  The
+ * batch allocates pinned host memory for staging each step's plan (32 bytes
+ * per filter plus 4 bytes per tile, three copies) and frees it in
+ * pf_batch_destroy.  All device work is ordered on `hip_stream`; waits for
+ * the initialisation to finish.  Errors: PF_ERR_INVALID_ARG,
+ * PF_ERR_WORKSPACE, PF_ERR_HIP. */
+int pf_batch_init(const pf_params* ps, int32_t n, void* d_workspace, size_t workspace_bytes,
+                  void* hip_stream, pf_batch** out);
+
+/* One step of every filter k whose active[k] is non-zero (`active` NULL: all
+ * filters) on frame d_frames[k] (device, H_k x W_k uint8, row pitch
+ * pitches[k] >= W_k).  d_frames and pitches are host arrays of n entries;
+ * entries of inactive filters are not read.  Continuous batching: the active
+ * set may change from call to call.  Asynchronous on the batch's stream; the
+ * frames must stay valid until the step has run.  Errors: PF_ERR_INVALID_ARG
+ * (nothing is stepped), PF_ERR_HIP (the batch and its filters are then
+ * poisoned), PF_ERR_STATE. */
+int pf_batch_step(pf_batch* b, const uint8_t* const* d_frames, const int64_t* pitches,
+                  const uint8_t* active);
+
+/* The latest estimate of every filter: out_2n[2k], out_2n[2k + 1] = (x, y) of
+ * filter k (host array of 2n doubles); (x0, y0) for a filter not yet stepped.
+ * Waits for the stream. */
+int pf_batch_estimates(pf_batch* b, double* out_2n);
+
+/* The same into device memory (`d_out_2n`, 2n doubles), stream-ordered; does
+ * not wait. */
+int pf_batch_estimates_async(pf_batch* b, double* d_out_2n);
+
+/* Handle of filter k (0 <= k < n) of the batch, owned by the batch and valid
+ * until pf_batch_destroy.  pf_estimate, pf_estimate_async, pf_export,
+ * pf_export_step, pf_import, pf_step (which steps that filter alone) and the
+ * profile calls accept it; pf_destroy refuses it (PF_ERR_INVALID_ARG). */
+int pf_batch_filter(pf_batch* b, int32_t k, pf_filter** out);
+
+/* Free the batch's host objects and its filters' handles (not the
+ * workspace).  Waits for the stream.  NULL is accepted. */
+int pf_batch_destroy(pf_batch* b);
 
 /* PF_ABI_VERSION of the loaded library. */
 int pf_abi_version(void);

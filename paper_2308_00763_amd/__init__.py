@@ -27,10 +27,14 @@ DTYPES = {"f64": PF_F64, "f32": PF_F32, "f16": PF_F16, "bf16": PF_BF16}
 PF_LIK_MEAN, PF_LIK_SUM = 0, 1
 PF_FLAG_DIAGNOSTICS = 1
 
+PF_ABI_VERSION = 2
+
 # Every function the C header declares (checked against include/pf.h by the tests).
 EXPORTS = ("pf_workspace_bytes", "pf_init", "pf_step", "pf_estimate", "pf_estimate_async",
            "pf_export", "pf_export_step", "pf_import", "pf_destroy", "pf_last_error",
-           "pf_abi_version", "pf_profile_start", "pf_profile_read")
+           "pf_abi_version", "pf_profile_start", "pf_profile_read",
+           "pf_batch_workspace_bytes", "pf_batch_init", "pf_batch_step", "pf_batch_estimates",
+           "pf_batch_estimates_async", "pf_batch_filter", "pf_batch_destroy")
 
 
 class PfError(RuntimeError):
@@ -89,6 +93,13 @@ def lib():
         L.pf_abi_version.argtypes = []
         L.pf_profile_start.argtypes = [vp, ctypes.c_uint32]
         L.pf_profile_read.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_uint32)]
+        L.pf_batch_workspace_bytes.argtypes = [P(pf_params), ctypes.c_int32, P(ctypes.c_size_t)]
+        L.pf_batch_init.argtypes = [P(pf_params), ctypes.c_int32, vp, ctypes.c_size_t, vp, P(vp)]
+        L.pf_batch_step.argtypes = [vp, vp, vp, vp]
+        L.pf_batch_estimates.argtypes = [vp, vp]
+        L.pf_batch_estimates_async.argtypes = [vp, vp]
+        L.pf_batch_filter.argtypes = [vp, ctypes.c_int32, P(vp)]
+        L.pf_batch_destroy.argtypes = [vp]
         for name in EXPORTS:
             if name != "pf_last_error":
                 getattr(L, name).restype = ctypes.c_int
@@ -193,6 +204,57 @@ def pf_profile_read(h):
     return float(out[0]), float(out[1]), float(out[2]), steps.value
 
 
+def _params_array(params):
+    arr = (pf_params * len(params))()
+    for i, p in enumerate(params):
+        arr[i] = p
+    return arr
+
+
+def pf_batch_workspace_bytes(params) -> int:
+    arr = _params_array(params)
+    out = ctypes.c_size_t()
+    _check(lib().pf_batch_workspace_bytes(arr, len(params), ctypes.byref(out)))
+    return out.value
+
+
+def pf_batch_init(params, d_workspace: int, workspace_bytes: int, hip_stream: int):
+    arr = _params_array(params)
+    b = ctypes.c_void_p()
+    _check(lib().pf_batch_init(arr, len(params), ctypes.c_void_p(d_workspace), workspace_bytes,
+                               ctypes.c_void_p(hip_stream), ctypes.byref(b)))
+    return b
+
+
+def pf_batch_step(b, d_frames, pitches, active=None):
+    """d_frames: uint64 array of device pointers; pitches: int64 array;
+    active: uint8 array or None (all)."""
+    fr = np.ascontiguousarray(d_frames, dtype=np.uint64)
+    pi = np.ascontiguousarray(pitches, dtype=np.int64)
+    ac = None if active is None else np.ascontiguousarray(active, dtype=np.uint8)
+    _check(lib().pf_batch_step(b, _np_ptr(fr), _np_ptr(pi), _np_ptr(ac)))
+
+
+def pf_batch_estimates(b, n: int):
+    out = np.zeros(2 * n)
+    _check(lib().pf_batch_estimates(b, _np_ptr(out)))
+    return out.reshape(n, 2)
+
+
+def pf_batch_estimates_async(b, d_out: int):
+    _check(lib().pf_batch_estimates_async(b, ctypes.c_void_p(d_out)))
+
+
+def pf_batch_filter(b, k: int):
+    h = ctypes.c_void_p()
+    _check(lib().pf_batch_filter(b, int(k), ctypes.byref(h)))
+    return h
+
+
+def pf_batch_destroy(b):
+    _check(lib().pf_batch_destroy(b))
+
+
 # ---------------------------------------------------------------------------
 # Convenience wrapper: workspace and stream from PyTorch.
 
@@ -231,6 +293,57 @@ class Filter:
     def close(self):
         if self.handle is not None:
             pf_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """A batch of filters in one torch-allocated workspace on `device`."""
+
+    def __init__(self, params, device="cuda:0", stream=None):
+        import torch
+        self.params = list(params)
+        self.n = len(self.params)
+        self.device = torch.device(device)
+        nbytes = pf_batch_workspace_bytes(self.params)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.handle = pf_batch_init(self.params, self.workspace.data_ptr(), nbytes,
+                                    self.stream.cuda_stream)
+
+    def step(self, frames, active=None):
+        """frames: list of n (H_k, W_k) uint8 CUDA tensors (None where inactive)."""
+        ptrs = np.zeros(self.n, dtype=np.uint64)
+        pitches = np.zeros(self.n, dtype=np.int64)
+        for k, f in enumerate(frames):
+            if f is None:
+                continue
+            assert f.dtype.itemsize == 1 and f.dim() == 2 and f.stride(1) == 1 and f.is_cuda
+            ptrs[k] = f.data_ptr()
+            pitches[k] = f.stride(0)
+        pf_batch_step(self.handle, ptrs, pitches, active)
+
+    def step_ptrs(self, ptrs, pitches, active=None):
+        pf_batch_step(self.handle, ptrs, pitches, active)
+
+    def estimates(self):
+        return pf_batch_estimates(self.handle, self.n)
+
+    def filter(self, k: int):
+        return pf_batch_filter(self.handle, k)
+
+    def export(self, k: int):
+        p = self.params[k]
+        return pf_export(self.filter(k), p.n_particles, bool(p.flags & PF_FLAG_DIAGNOSTICS))
+
+    def close(self):
+        if self.handle is not None:
+            pf_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

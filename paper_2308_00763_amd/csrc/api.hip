@@ -25,9 +25,41 @@ struct pf_filter {
     StepArgs args;
     uint32_t t;
     bool poisoned;
+    pf_batch* owner;  // the batch this filter belongs to, or null
     // per-pass timing (pf_profile_start / pf_profile_read)
     std::vector<hipEvent_t> prof_ev;  // kProfEv events per recorded step
     uint32_t prof_max, prof_used;
+};
+
+// A batch of filters in one workspace:
+//   [StepArgs x n][BatchEntry x n][tile map: int32 x total tiles]
+//   [estimates: 2n doubles][filter 0 layout][filter 1 layout]...
+// Each step uploads, from a ring of pinned host buffers, the entries of the
+// stepped filters (grouped by combine class) and, when the set of stepped
+// filters changed, the map from grid tile to entry.
+constexpr int kRing = 3;
+
+struct pf_batch {
+    int32_t n;
+    int dtype;
+    int rc;  // common disk radius when 5 or 8, else 0
+    hipStream_t stream;
+    uint8_t* ws;
+    int64_t total_tiles;
+    StepArgs* d_args;
+    BatchEntry* d_entries;
+    int32_t* d_tile_entry;
+    double* d_est;
+    std::vector<pf_filter*> f;
+    std::vector<int> cls;  // combine class of every filter
+    uint8_t* h_stage[kRing];
+    hipEvent_t ev[kRing];
+    bool ev_used[kRing];
+    int ring;
+    size_t stage_bytes;
+    std::vector<uint8_t> map_active;  // stepped set of the uploaded tile map
+    bool map_valid;
+    bool poisoned;
 };
 
 namespace {
@@ -141,41 +173,20 @@ hipError_t write_block(pf_filter* h, const DevBlock& b)
 
 int floor_cell(double v) { return (int)floor(v + 0.5); }
 
-}  // namespace
-
-extern "C" {
-
-int pf_abi_version(void) { return PF_ABI_VERSION; }
-
-const char* pf_last_error(void) { return g_err.c_str(); }
-
-int pf_workspace_bytes(const pf_params* p, size_t* out_bytes)
+// Fill the handle for a filter with params p (checked) over workspace ws, and
+// return its initial device block and the stored value of every particle.
+void setup_filter(pf_filter* h, const pf_params& pr, uint8_t* ws, hipStream_t stream, DevBlock* blk,
+                  double* vx, double* vy)
 {
-    if (int rc = check_params(p)) return rc;
-    if (!out_bytes) return fail(PF_ERR_INVALID_ARG, "out_bytes is NULL");
-    *out_bytes = make_layout(*p).total;
-    return ok();
-}
-
-int pf_init(const pf_params* p, void* d_workspace, size_t workspace_bytes, void* hip_stream, pf_filter** out)
-{
-    if (int rc = check_params(p)) return rc;
-    if (!out) return fail(PF_ERR_INVALID_ARG, "out is NULL");
-    *out = nullptr;
-    if (!d_workspace) return fail(PF_ERR_INVALID_ARG, "workspace is NULL");
-    if (((uintptr_t)d_workspace & 255) != 0) return fail(PF_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
-    const Layout L = make_layout(*p);
-    if (workspace_bytes < L.total)
-        return fail(PF_ERR_WORKSPACE, "workspace %zu bytes < %zu needed", workspace_bytes, L.total);
-
-    pf_filter* h = new (std::nothrow) pf_filter{};
-    if (!h) return fail(PF_ERR_INVALID_ARG, "out of host memory");
-    h->p = *p;
+    const pf_params* p = &pr;
+    const Layout L = make_layout(pr);
+    h->p = pr;
     h->L = L;
-    h->stream = (hipStream_t)hip_stream;
-    h->ws = (uint8_t*)d_workspace;
+    h->stream = stream;
+    h->ws = ws;
     h->t = 0;
     h->poisoned = false;
+    h->owner = nullptr;
 
     StepArgs& a = h->args;
     a.frame = nullptr;
@@ -217,19 +228,55 @@ int pf_init(const pf_params* p, void* d_workspace, size_t workspace_bytes, void*
     }
 
     DevBlock b{};
-    double vx = p->x0, vy = p->y0;
+    *vx = p->x0;
+    *vy = p->y0;
     if (p->dtype != PF_F64) {
         b.ci_x = floor_cell(p->x0);
         b.ci_y = floor_cell(p->y0);
         b.cn_x = floor_cell(p->x0 + p->drift_x);
         b.cn_y = floor_cell(p->y0 + p->drift_y);
-        vx = p->x0 - (double)b.ci_x;
-        vy = p->y0 - (double)b.ci_y;
+        *vx = p->x0 - (double)b.ci_x;
+        *vy = p->y0 - (double)b.ci_y;
     }
     b.est_x = p->x0;
     b.est_y = p->y0;
+    *blk = b;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pf_abi_version(void) { return PF_ABI_VERSION; }
+
+const char* pf_last_error(void) { return g_err.c_str(); }
+
+int pf_workspace_bytes(const pf_params* p, size_t* out_bytes)
+{
+    if (int rc = check_params(p)) return rc;
+    if (!out_bytes) return fail(PF_ERR_INVALID_ARG, "out_bytes is NULL");
+    *out_bytes = make_layout(*p).total;
+    return ok();
+}
+
+int pf_init(const pf_params* p, void* d_workspace, size_t workspace_bytes, void* hip_stream, pf_filter** out)
+{
+    if (int rc = check_params(p)) return rc;
+    if (!out) return fail(PF_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!d_workspace) return fail(PF_ERR_INVALID_ARG, "workspace is NULL");
+    if (((uintptr_t)d_workspace & 255) != 0) return fail(PF_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    const Layout L = make_layout(*p);
+    if (workspace_bytes < L.total)
+        return fail(PF_ERR_WORKSPACE, "workspace %zu bytes < %zu needed", workspace_bytes, L.total);
+
+    pf_filter* h = new (std::nothrow) pf_filter{};
+    if (!h) return fail(PF_ERR_INVALID_ARG, "out of host memory");
+    DevBlock b;
+    double vx, vy;
+    setup_filter(h, *p, (uint8_t*)d_workspace, (hipStream_t)hip_stream, &b, &vx, &vy);
     hipError_t e = write_block(h, b);
-    if (e == hipSuccess) e = launch_fill(p->dtype, a, vx, vy, h->stream);
+    if (e == hipSuccess) e = launch_fill(p->dtype, h->args, vx, vy, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) {
         int rc = hip_fail(h, e, "pf_init");
@@ -449,8 +496,283 @@ int pf_profile_read(pf_filter* h, double out_ms[3], uint32_t* steps)
 
 int pf_destroy(pf_filter* h)
 {
+    if (h && h->owner) return fail(PF_ERR_INVALID_ARG, "filter belongs to a batch; use pf_batch_destroy");
     if (h) profile_free(h);
     delete h;
+    return ok();
+}
+
+// ---------------------------------------------------------------------------
+// Batches.
+
+struct BatchLayout {
+    size_t args, entries, tile_entry, est, filters, total;
+    int64_t tiles;
+};
+
+static int check_batch(const pf_params* ps, int32_t n, BatchLayout* bl, std::vector<size_t>* foff)
+{
+    if (!ps) return fail(PF_ERR_INVALID_ARG, "params is NULL");
+    if (n < 1 || n > (1 << 20)) return fail(PF_ERR_INVALID_ARG, "batch size %d outside [1, 2^20]", n);
+    int64_t tiles = 0;
+    size_t fbytes = 0;
+    if (foff) foff->resize((size_t)n);
+    for (int32_t k = 0; k < n; ++k) {
+        if (check_params(&ps[k])) return fail(PF_ERR_INVALID_ARG, "filter %d: %s", k, g_err.c_str());
+        if (ps[k].dtype != ps[0].dtype) return fail(PF_ERR_INVALID_ARG, "filter %d: dtype differs from filter 0", k);
+        const Layout L = make_layout(ps[k]);
+        if (foff) (*foff)[k] = fbytes;
+        fbytes += L.total;
+        tiles += L.ntiles;
+    }
+    if (tiles > INT32_MAX) return fail(PF_ERR_INVALID_ARG, "batch has %lld tiles, more than 2^31 - 1", (long long)tiles);
+    size_t o = 0;
+    bl->args = o; o = align256(o + sizeof(StepArgs) * (size_t)n);
+    bl->entries = o; o = align256(o + sizeof(BatchEntry) * (size_t)n);
+    bl->tile_entry = o; o = align256(o + 4 * (size_t)tiles);
+    bl->est = o; o = align256(o + 16 * (size_t)n);
+    bl->filters = o; o += fbytes;
+    bl->total = o;
+    bl->tiles = tiles;
+    return PF_OK;
+}
+
+static int batch_fail(pf_batch* b, hipError_t e, const char* what)
+{
+    b->poisoned = true;
+    b->map_valid = false;
+    for (pf_filter* h : b->f) h->poisoned = true;
+    return fail(PF_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+static void batch_free(pf_batch* b)
+{
+    for (pf_filter* h : b->f) {
+        profile_free(h);
+        delete h;
+    }
+    b->f.clear();
+    for (int i = 0; i < kRing; ++i) {
+        if (b->ev[i]) (void)hipEventDestroy(b->ev[i]);
+        if (b->h_stage[i]) (void)hipHostFree(b->h_stage[i]);
+    }
+    delete b;
+}
+
+int pf_batch_workspace_bytes(const pf_params* ps, int32_t n, size_t* out_bytes)
+{
+    BatchLayout bl;
+    if (int rc = check_batch(ps, n, &bl, nullptr)) return rc;
+    if (!out_bytes) return fail(PF_ERR_INVALID_ARG, "out_bytes is NULL");
+    *out_bytes = bl.total;
+    return ok();
+}
+
+int pf_batch_init(const pf_params* ps, int32_t n, void* d_workspace, size_t workspace_bytes, void* hip_stream,
+                  pf_batch** out)
+{
+    BatchLayout bl;
+    std::vector<size_t> foff;
+    if (int rc = check_batch(ps, n, &bl, &foff)) return rc;
+    if (!out) return fail(PF_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!d_workspace) return fail(PF_ERR_INVALID_ARG, "workspace is NULL");
+    if (((uintptr_t)d_workspace & 255) != 0) return fail(PF_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (workspace_bytes < bl.total)
+        return fail(PF_ERR_WORKSPACE, "workspace %zu bytes < %zu needed", workspace_bytes, bl.total);
+
+    pf_batch* b = new (std::nothrow) pf_batch{};
+    if (!b) return fail(PF_ERR_INVALID_ARG, "out of host memory");
+    b->n = n;
+    b->dtype = ps[0].dtype;
+    b->stream = (hipStream_t)hip_stream;
+    b->ws = (uint8_t*)d_workspace;
+    b->total_tiles = bl.tiles;
+    b->d_args = (StepArgs*)(b->ws + bl.args);
+    b->d_entries = (BatchEntry*)(b->ws + bl.entries);
+    b->d_tile_entry = (int32_t*)(b->ws + bl.tile_entry);
+    b->d_est = (double*)(b->ws + bl.est);
+    b->map_valid = false;
+    b->poisoned = false;
+    b->ring = 0;
+    bool all5 = true, all8 = true;
+    for (int32_t k = 0; k < n; ++k) {
+        all5 = all5 && ps[k].disk_radius == 5;
+        all8 = all8 && ps[k].disk_radius == 8;
+    }
+    b->rc = all5 ? 5 : all8 ? 8 : 0;
+
+    std::vector<DevBlock> blocks((size_t)n);
+    std::vector<StepArgs> args((size_t)n);
+    std::vector<double> vx((size_t)n), vy((size_t)n);
+    b->f.reserve((size_t)n);
+    b->cls.resize((size_t)n);
+    for (int32_t k = 0; k < n; ++k) {
+        pf_filter* h = new (std::nothrow) pf_filter{};
+        if (!h) {
+            batch_free(b);
+            return fail(PF_ERR_INVALID_ARG, "out of host memory");
+        }
+        b->f.push_back(h);
+        setup_filter(h, ps[k], b->ws + bl.filters + foff[k], b->stream, &blocks[k], &vx[k], &vy[k]);
+        h->owner = b;
+        args[k] = h->args;
+        b->cls[k] = comb_class(h->L.ntiles);
+    }
+    b->stage_bytes = sizeof(BatchEntry) * (size_t)n + 4 * (size_t)bl.tiles;
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < kRing && e == hipSuccess; ++i) {
+        e = hipHostMalloc((void**)&b->h_stage[i], b->stage_bytes, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_args, args.data(), sizeof(StepArgs) * (size_t)n, hipMemcpyHostToDevice, b->stream);
+    for (int32_t k = 0; k < n && e == hipSuccess; ++k) {
+        pf_filter* h = b->f[k];
+        e = hipMemcpyAsync(at(h, h->L.blk), &blocks[k], sizeof(DevBlock), hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess) e = launch_fill(b->dtype, h->args, vx[k], vy[k], b->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        const int rc = fail(PF_ERR_HIP, "pf_batch_init: %s", hipGetErrorString(e));
+        batch_free(b);
+        return rc;
+    }
+    *out = b;
+    return ok();
+}
+
+static int batch_live(pf_batch* b)
+{
+    if (!b) return fail(PF_ERR_INVALID_ARG, "batch is NULL");
+    if (b->poisoned) return fail(PF_ERR_STATE, "batch poisoned by an earlier HIP error");
+    return PF_OK;
+}
+
+int pf_batch_step(pf_batch* b, const uint8_t* const* d_frames, const int64_t* pitches, const uint8_t* active)
+{
+    if (int rc = batch_live(b)) return rc;
+    if (!d_frames || !pitches) return fail(PF_ERR_INVALID_ARG, "frames/pitches is NULL");
+    const int32_t n = b->n;
+    // check everything before any state changes
+    int32_t n_act = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        if (active && !active[k]) continue;
+        const pf_filter* h = b->f[k];
+        if (h->poisoned) return fail(PF_ERR_STATE, "filter %d poisoned", k);
+        if (!d_frames[k]) return fail(PF_ERR_INVALID_ARG, "filter %d: frame is NULL", k);
+        if (pitches[k] < h->p.width)
+            return fail(PF_ERR_INVALID_ARG, "filter %d: row_pitch %lld < width %d", k, (long long)pitches[k], h->p.width);
+        if (h->t == UINT32_MAX) return fail(PF_ERR_INVALID_ARG, "filter %d: step counter exhausted", k);
+        ++n_act;
+    }
+    if (n_act == 0) return ok();
+
+    // the stepped set, and whether the uploaded tile map still describes it
+    bool same = b->map_valid && (int32_t)b->map_active.size() == n;
+    if (same)
+        for (int32_t k = 0; k < n && same; ++k) same = b->map_active[k] == (uint8_t)(active ? active[k] != 0 : 1);
+
+    const int slot = b->ring;
+    b->ring = (b->ring + 1) % kRing;
+    hipError_t e = hipSuccess;
+    if (b->ev_used[slot]) e = hipEventSynchronize(b->ev[slot]);
+    if (e != hipSuccess) return batch_fail(b, e, "pf_batch_step");
+    BatchEntry* ent = reinterpret_cast<BatchEntry*>(b->h_stage[slot]);
+    int32_t* tmap = reinterpret_cast<int32_t*>(b->h_stage[slot] + sizeof(BatchEntry) * (size_t)n);
+    int32_t cls_begin[kCombClasses + 1];
+    int32_t ne = 0, tiles = 0;
+    for (int c = 0; c < kCombClasses; ++c) {
+        cls_begin[c] = ne;
+        for (int32_t k = 0; k < n; ++k) {
+            if ((active && !active[k]) || b->cls[k] != c) continue;
+            const pf_filter* h = b->f[k];
+            BatchEntry& en = ent[ne];
+            en.frame = d_frames[k];
+            en.pitch = pitches[k];
+            en.fid = k;
+            en.tile_base = tiles;
+            en.t = h->t + 1;
+            en.pad = 0;
+            if (!same)
+                for (int i = 0; i < h->L.ntiles; ++i) tmap[tiles + i] = ne;
+            tiles += h->L.ntiles;
+            ++ne;
+        }
+    }
+    cls_begin[kCombClasses] = ne;
+
+    e = hipMemcpyAsync(b->d_entries, ent, sizeof(BatchEntry) * (size_t)ne, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess && !same)
+        e = hipMemcpyAsync(b->d_tile_entry, tmap, 4 * (size_t)tiles, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipEventRecord(b->ev[slot], b->stream);
+    if (e == hipSuccess) b->ev_used[slot] = true;
+    BatchArgs ba;
+    ba.args = b->d_args;
+    ba.entries = b->d_entries;
+    ba.tile_entry = b->d_tile_entry;
+    ba.entry0 = 0;
+    if (e == hipSuccess) e = launch_batch_pass_a(b->dtype, b->rc, ba, tiles, b->stream);
+    for (int c = 0; c < kCombClasses && e == hipSuccess; ++c) {
+        const int32_t cnt = cls_begin[c + 1] - cls_begin[c];
+        if (cnt == 0) continue;
+        ba.entry0 = cls_begin[c];
+        e = launch_batch_combine(b->dtype, c, ba, cnt, b->stream);
+    }
+    ba.entry0 = 0;
+    if (e == hipSuccess) e = launch_batch_pass_c(b->dtype, ba, tiles, b->stream);
+    for (int32_t i = 0; i < ne && e == hipSuccess; ++i) {
+        const pf_filter* h = b->f[ent[i].fid];
+        if (!h->args.dg_w) continue;
+        StepArgs a = h->args;
+        a.t = ent[i].t;
+        e = launch_diag_weights(b->dtype, a, b->stream);
+    }
+    if (e != hipSuccess) return batch_fail(b, e, "pf_batch_step launch");
+    if (!same) {
+        b->map_active.resize((size_t)n);
+        for (int32_t k = 0; k < n; ++k) b->map_active[k] = (uint8_t)(active ? active[k] != 0 : 1);
+        b->map_valid = true;
+    }
+    for (int32_t i = 0; i < ne; ++i) b->f[ent[i].fid]->t = ent[i].t;
+    return ok();
+}
+
+int pf_batch_estimates_async(pf_batch* b, double* d_out_2n)
+{
+    if (int rc = batch_live(b)) return rc;
+    if (!d_out_2n) return fail(PF_ERR_INVALID_ARG, "d_out_2n is NULL");
+    const hipError_t e = launch_gather_est(b->d_args, b->n, d_out_2n, b->stream);
+    if (e != hipSuccess) return batch_fail(b, e, "pf_batch_estimates_async");
+    return ok();
+}
+
+int pf_batch_estimates(pf_batch* b, double* out_2n)
+{
+    if (int rc = batch_live(b)) return rc;
+    if (!out_2n) return fail(PF_ERR_INVALID_ARG, "out_2n is NULL");
+    hipError_t e = launch_gather_est(b->d_args, b->n, b->d_est, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out_2n, b->d_est, 16 * (size_t)b->n, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return batch_fail(b, e, "pf_batch_estimates");
+    return ok();
+}
+
+int pf_batch_filter(pf_batch* b, int32_t k, pf_filter** out)
+{
+    if (!b) return fail(PF_ERR_INVALID_ARG, "batch is NULL");
+    if (!out) return fail(PF_ERR_INVALID_ARG, "out is NULL");
+    if (k < 0 || k >= b->n) return fail(PF_ERR_INVALID_ARG, "filter index %d outside [0, %d)", k, b->n);
+    *out = b->f[k];
+    return ok();
+}
+
+int pf_batch_destroy(pf_batch* b)
+{
+    if (!b) return ok();
+    (void)hipStreamSynchronize(b->stream);
+    batch_free(b);
     return ok();
 }
 

@@ -340,17 +340,16 @@ struct PassALds {
     int red_i[kWaves];
 };
 
+// Pass A of tile `tile` of the filter described by `a`.
 template <int DT, int RC>
-__global__ __launch_bounds__(kBlock) void pass_a_kernel(StepArgs a)
+__device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALds& lds)
 {
     using M = ModeT<DT>;
     constexpr int PPT = M::PPT;
     static_assert(kBlock * PPT == kTile, "tile size");
-    __shared__ PassALds lds;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
-    const int tile = blockIdx.x;
     const int k0 = tile * kTile + tid * PPT;
     const int n = (int)a.n;
     const int r = RC > 0 ? RC : a.r;
@@ -579,6 +578,13 @@ __global__ __launch_bounds__(kBlock) void pass_a_kernel(StepArgs a)
     }
 }
 
+template <int DT, int RC>
+__global__ __launch_bounds__(kBlock) void pass_a_kernel(StepArgs a)
+{
+    __shared__ PassALds lds;
+    pass_a_tile<DT, RC>(a, blockIdx.x, lds);
+}
+
 // ---------------------------------------------------------------------------
 // End slots.  A particle with normalised cumulative weight C = P / Z ends the
 // strata (j + u0) / N <= C, i.e. its end slot is floor(N P / Z - u0) + 1
@@ -653,15 +659,14 @@ template <int DT>
 using TileSlotsT = TileSlots<DT == PF_F64 ? PF_F64 : PF_F32>;
 
 // ---------------------------------------------------------------------------
-// Combine: one workgroup of 1024 threads turns the tile records into the tile
+// Combine: one workgroup per filter turns the tile records into the tile
 // table.  Every thread owns KPER consecutive tiles per round; the carried
 // offsets come from a two-level scan (per wave, then over the wave totals)
 // whose total is the normaliser Z; the estimate sums ride on the same
-// exchange.  Offsets are made monotone by prefix maxima and by clamping each
-// value to the next wave's offset.
-
-constexpr int kCombThreads = 1024;
-constexpr int kCombWaves = kCombThreads / 64;
+// exchange.  The tiles' end slots are made non-decreasing by an integer
+// prefix maximum.  The workgroup size and KPER depend on the filter's tile
+// count only (comb_class), so a filter combines the same way alone and in a
+// batch.
 
 // Two-float DPP moves and scans.
 template <int CTRL, int RM = 0xF>
@@ -722,9 +727,11 @@ struct CombAcc<PF_F32> {
     static __device__ T up1(T v, T fill) { return ff{wave_shift_up1(v.hi, fill.hi), wave_shift_up1(v.lo, fill.lo)}; }
 };
 
-template <int DT, int KPER>
-__global__ __launch_bounds__(kCombThreads) void combine_kernel(StepArgs a)
+// Combine of the filter described by `a`, run by one workgroup of NT threads.
+template <int DT, int KPER, int NT>
+__device__ __forceinline__ void combine_filter(const StepArgs& a)
 {
+    constexpr int NW = NT / 64;
     constexpr bool F64 = DT == PF_F64;
     using A = CombAcc<F64 ? PF_F64 : PF_F32>;
     using T = typename A::T;
@@ -732,14 +739,14 @@ __global__ __launch_bounds__(kCombThreads) void combine_kernel(StepArgs a)
     using Tab = typename std::conditional<F64, TileTab64, TileTab32>::type;
     using Fv = typename std::conditional<F64, double, float>::type;
     using Mx = typename std::conditional<F64, double, int>::type;
-    constexpr int CHUNK = KPER * kCombThreads;
+    constexpr int CHUNK = KPER * NT;
 
-    __shared__ Mx red_m[kCombWaves];
-    __shared__ T red_s[kCombWaves];
-    __shared__ T wave_off[kCombWaves + 1];
-    __shared__ Fv red_x[kCombWaves], red_y[kCombWaves];
-    __shared__ int red_e[kCombWaves];
-    __shared__ int woff_e[kCombWaves + 1];
+    __shared__ Mx red_m[NW];
+    __shared__ T red_s[NW];
+    __shared__ T wave_off[NW + 1];
+    __shared__ Fv red_x[NW], red_y[NW];
+    __shared__ int red_e[NW];
+    __shared__ int woff_e[NW + 1];
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int nt = a.ntiles;
@@ -766,7 +773,7 @@ __global__ __launch_bounds__(kCombThreads) void combine_kernel(StepArgs a)
     __syncthreads();
     Mx gm = red_m[0];
 #pragma unroll
-    for (int w = 1; w < kCombWaves; ++w) gm = red_m[w] > gm ? red_m[w] : gm;
+    for (int w = 1; w < NW; ++w) gm = red_m[w] > gm ? red_m[w] : gm;
 
     // carried offsets: kPER consecutive tiles per thread, a wave scan, then a
     // scan of the wave totals by wave 0; the total is the normaliser
@@ -802,9 +809,9 @@ __global__ __launch_bounds__(kCombThreads) void combine_kernel(StepArgs a)
         if (lane == 63) red_s[wv] = sw;
         __syncthreads();
         if (wv == 0) {
-            T tv = lane < kCombWaves ? red_s[lane] : A::zero();
+            T tv = lane < NW ? red_s[lane] : A::zero();
             tv = A::sum_scan(tv);
-            if (lane < kCombWaves) wave_off[lane + 1] = A::add(carry, tv);
+            if (lane < NW) wave_off[lane + 1] = A::add(carry, tv);
             if (lane == 0) wave_off[0] = carry;
         }
         __syncthreads();
@@ -822,7 +829,7 @@ __global__ __launch_bounds__(kCombThreads) void combine_kernel(StepArgs a)
                 else { tab[t + 1].off_hi = run.hi; tab[t + 1].off_lo = run.lo; }
             }
         }
-        carry = wave_off[kCombWaves];
+        carry = wave_off[NW];
         __syncthreads();
     }
     const T Z = carry;
@@ -832,7 +839,7 @@ __global__ __launch_bounds__(kCombThreads) void combine_kernel(StepArgs a)
     __syncthreads();
     Fv sx = red_x[0], sy = red_y[0];
 #pragma unroll
-    for (int w = 1; w < kCombWaves; ++w) { sx = sx + red_x[w]; sy = sy + red_y[w]; }
+    for (int w = 1; w < NW; ++w) { sx = sx + red_x[w]; sy = sy + red_y[w]; }
 
     // End slot of every tile, y = R off_{t+1} - u0 (the expression pass C caps
     // its tiles with), made non-decreasing by a prefix maximum so that the
@@ -880,9 +887,9 @@ __global__ __launch_bounds__(kCombThreads) void combine_kernel(StepArgs a)
         if (lane == 63) red_e[wv] = sm;
         __syncthreads();
         if (wv == 0) {
-            int tv = lane < kCombWaves ? red_e[lane] : carry_e;
+            int tv = lane < NW ? red_e[lane] : carry_e;
             tv = wave_incl_scan<OpMax>(tv);
-            if (lane < kCombWaves) woff_e[lane + 1] = max(carry_e, tv);
+            if (lane < NW) woff_e[lane + 1] = max(carry_e, tv);
             if (lane == 0) woff_e[0] = carry_e;
         }
         __syncthreads();
@@ -893,7 +900,7 @@ __global__ __launch_bounds__(kCombThreads) void combine_kernel(StepArgs a)
             run = max(run, Ek[k]);
             if (t < nt) tab[t].E = run;
         }
-        carry_e = woff_e[kCombWaves];
+        carry_e = woff_e[NW];
         __syncthreads();
     }
 
@@ -934,6 +941,12 @@ __global__ __launch_bounds__(kCombThreads) void combine_kernel(StepArgs a)
     }
 }
 
+template <int DT, int KPER, int NT>
+__global__ __launch_bounds__(NT) void combine_kernel(StepArgs a)
+{
+    combine_filter<DT, KPER, NT>(a);
+}
+
 // ---------------------------------------------------------------------------
 // Pass C: merge-path scatter, one workgroup per tile.
 //
@@ -950,15 +963,23 @@ __global__ __launch_bounds__(kCombThreads) void combine_kernel(StepArgs a)
 // are spread inside the tile.
 
 template <int DT>
-__global__ __launch_bounds__(kBlock) void pass_c_kernel(StepArgs a)
+struct PassCLds {
+    using Store = typename ModeT<DT>::Store;
+    int32_t e[kTile];
+    Store x[kTile];
+    Store y[kTile];
+};
+
+// Pass C of tile `t` of the filter described by `a`.
+template <int DT>
+__device__ __forceinline__ void pass_c_tile(const StepArgs& a, int t, PassCLds<DT>& lds)
 {
     using Store = typename ModeT<DT>::Store;
-    __shared__ int32_t s_e[kTile];
-    __shared__ Store s_x[kTile];
-    __shared__ Store s_y[kTile];
+    int32_t* s_e = lds.e;
+    Store* s_x = lds.x;
+    Store* s_y = lds.y;
 
     const int n = (int)a.n;
-    const int t = blockIdx.x;
     const TileSlotsT<DT> ts(a, t);
     const int first = t * kTile;
     const int tt = min(kTile, n - first);
@@ -1007,6 +1028,13 @@ __global__ __launch_bounds__(kBlock) void pass_c_kernel(StepArgs a)
     }
 }
 
+template <int DT>
+__global__ __launch_bounds__(kBlock) void pass_c_kernel(StepArgs a)
+{
+    __shared__ PassCLds<DT> lds;
+    pass_c_tile<DT>(a, blockIdx.x, lds);
+}
+
 // ---------------------------------------------------------------------------
 // Normalised weights of the latest step for diagnostics: w_k = wt_k f_t / Z.
 template <int DT>
@@ -1032,6 +1060,58 @@ __global__ __launch_bounds__(kBlock) void fill_kernel(Store* x, Store* y, int64_
     if (k < n_pad) {
         x[k] = vx;
         y[k] = vy;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Batched step: many independent filters per launch.  Pass A and pass C run
+// one workgroup per tile of every stepped filter; the combine one workgroup
+// per filter, one launch per combine class.  Each workgroup runs exactly the
+// code of the single-filter kernels on its filter's arguments, so a filter's
+// results do not depend on the batch it runs in.
+
+__device__ __forceinline__ StepArgs batch_args(const BatchArgs& b, int e)
+{
+    const BatchEntry en = b.entries[e];
+    StepArgs a = b.args[en.fid];
+    a.frame = en.frame;
+    a.pitch = en.pitch;
+    a.t = en.t;
+    return a;
+}
+
+template <int DT, int RC>
+__global__ __launch_bounds__(kBlock) void pass_a_batch_kernel(BatchArgs b)
+{
+    __shared__ PassALds lds;
+    const int e = b.tile_entry[blockIdx.x];
+    const StepArgs a = batch_args(b, e);
+    pass_a_tile<DT, RC>(a, (int)blockIdx.x - b.entries[e].tile_base, lds);
+}
+
+template <int DT, int KPER, int NT>
+__global__ __launch_bounds__(NT) void combine_batch_kernel(BatchArgs b)
+{
+    const StepArgs a = batch_args(b, b.entry0 + (int)blockIdx.x);
+    combine_filter<DT, KPER, NT>(a);
+}
+
+template <int DT>
+__global__ __launch_bounds__(kBlock) void pass_c_batch_kernel(BatchArgs b)
+{
+    __shared__ PassCLds<DT> lds;
+    const int e = b.tile_entry[blockIdx.x];
+    const StepArgs a = batch_args(b, e);
+    pass_c_tile<DT>(a, (int)blockIdx.x - b.entries[e].tile_base, lds);
+}
+
+__global__ __launch_bounds__(kBlock) void gather_est_kernel(const StepArgs* args, int n, double* out)
+{
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k < n) {
+        const DevBlock* blk = args[k].blk;
+        out[2 * k] = blk->est_x;
+        out[2 * k + 1] = blk->est_y;
     }
 }
 
@@ -1070,10 +1150,12 @@ hipError_t launch_pass_a(int dtype, const StepArgs& a, hipStream_t s)
 template <int DT>
 static void launch_combine_t(const StepArgs& a, hipStream_t s)
 {
-    const dim3 g(1), blk(kCombThreads);
-    if (a.ntiles <= kCombThreads) combine_kernel<DT, 1><<<g, blk, 0, s>>>(a);
-    else if (a.ntiles <= 4 * kCombThreads) combine_kernel<DT, 4><<<g, blk, 0, s>>>(a);
-    else combine_kernel<DT, 16><<<g, blk, 0, s>>>(a);
+    switch (comb_class(a.ntiles)) {
+    case 0: combine_kernel<DT, 1, 256><<<1, 256, 0, s>>>(a); break;
+    case 1: combine_kernel<DT, 1, 1024><<<1, 1024, 0, s>>>(a); break;
+    case 2: combine_kernel<DT, 4, 1024><<<1, 1024, 0, s>>>(a); break;
+    default: combine_kernel<DT, 16, 1024><<<1, 1024, 0, s>>>(a); break;
+    }
 }
 
 hipError_t launch_combine(int dtype, const StepArgs& a, hipStream_t s)
@@ -1097,6 +1179,70 @@ hipError_t launch_pass_c(int dtype, const StepArgs& a, hipStream_t s)
     case PF_BF16: return launch_pass_c_t<PF_BF16>(a, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+template <int DT>
+static void launch_batch_pass_a_t(int rc, const BatchArgs& b, int tiles, hipStream_t s)
+{
+    const dim3 g((unsigned)tiles), blk(kBlock);
+    if (rc == 5) pass_a_batch_kernel<DT, 5><<<g, blk, 0, s>>>(b);
+    else if (rc == 8) pass_a_batch_kernel<DT, 8><<<g, blk, 0, s>>>(b);
+    else pass_a_batch_kernel<DT, 0><<<g, blk, 0, s>>>(b);
+}
+
+template <int DT>
+static void launch_batch_combine_t(int cls, const BatchArgs& b, int count, hipStream_t s)
+{
+    const dim3 g((unsigned)count);
+    switch (cls) {
+    case 0: combine_batch_kernel<DT, 1, 256><<<g, 256, 0, s>>>(b); break;
+    case 1: combine_batch_kernel<DT, 1, 1024><<<g, 1024, 0, s>>>(b); break;
+    case 2: combine_batch_kernel<DT, 4, 1024><<<g, 1024, 0, s>>>(b); break;
+    default: combine_batch_kernel<DT, 16, 1024><<<g, 1024, 0, s>>>(b); break;
+    }
+}
+
+hipError_t launch_batch_pass_a(int dtype, int rc, const BatchArgs& b, int tiles, hipStream_t s)
+{
+    switch (dtype) {
+    case PF_F64: launch_batch_pass_a_t<PF_F64>(rc, b, tiles, s); break;
+    case PF_F32: launch_batch_pass_a_t<PF_F32>(rc, b, tiles, s); break;
+    case PF_F16: launch_batch_pass_a_t<PF_F16>(rc, b, tiles, s); break;
+    case PF_BF16: launch_batch_pass_a_t<PF_BF16>(rc, b, tiles, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_combine(int dtype, int cls, const BatchArgs& b, int count, hipStream_t s)
+{
+    switch (dtype) {
+    case PF_F64: launch_batch_combine_t<PF_F64>(cls, b, count, s); break;
+    case PF_F32: launch_batch_combine_t<PF_F32>(cls, b, count, s); break;
+    case PF_F16: launch_batch_combine_t<PF_F16>(cls, b, count, s); break;
+    case PF_BF16: launch_batch_combine_t<PF_BF16>(cls, b, count, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_pass_c(int dtype, const BatchArgs& b, int tiles, hipStream_t s)
+{
+    const dim3 g((unsigned)tiles), blk(kBlock);
+    switch (dtype) {
+    case PF_F64: pass_c_batch_kernel<PF_F64><<<g, blk, 0, s>>>(b); break;
+    case PF_F32: pass_c_batch_kernel<PF_F32><<<g, blk, 0, s>>>(b); break;
+    case PF_F16: pass_c_batch_kernel<PF_F16><<<g, blk, 0, s>>>(b); break;
+    case PF_BF16: pass_c_batch_kernel<PF_BF16><<<g, blk, 0, s>>>(b); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_est(const StepArgs* args, int n, double* out, hipStream_t s)
+{
+    gather_est_kernel<<<dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s>>>(args, n, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_step(int dtype, const StepArgs& a, hipStream_t s)

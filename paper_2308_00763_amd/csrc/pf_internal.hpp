@@ -18,6 +18,15 @@ constexpr int kPrefRows = 64;      // LDS row-prefix table: window rows
 constexpr int kWinMaxW = 128;      // widest frame window staged in LDS
 constexpr int kMaxRadius = 32;
 
+// Combine configuration of a filter of nt tiles: class 0 = 256 threads, one
+// tile per thread and round; 1 = 1024 threads, one tile; 2 = 1024 threads,
+// four tiles; 3 = 1024 threads, sixteen tiles.
+__host__ __device__ constexpr int comb_class(int nt)
+{
+    return nt <= 256 ? 0 : nt <= 1024 ? 1 : nt <= 4096 ? 2 : 3;
+}
+constexpr int kCombClasses = 4;
+
 // Particles per thread and tile size per precision mode.
 __host__ __device__ constexpr int tile_of(int /*dtype*/) { return kTile; }
 __host__ __device__ constexpr int elt_of(int dtype) { return dtype == PF_F64 ? 8 : dtype == PF_F32 ? 4 : 2; }
@@ -124,6 +133,27 @@ struct StepArgs {
     int32_t* dg_anc;
 };
 
+// One filter of a batched step: the per-step part of its arguments.
+struct BatchEntry {
+    const uint8_t* frame;
+    int64_t pitch;
+    int32_t fid;        // index of the filter's StepArgs in the batch
+    int32_t tile_base;  // first tile of the filter in the step's grid
+    uint32_t t;         // index of the step
+    int32_t pad;
+};
+static_assert(sizeof(BatchEntry) == 32, "BatchEntry layout");
+
+// Arguments of the batched passes: the filters' static arguments, this
+// step's entries (one per stepped filter, grouped by combine class) and the
+// map from grid tile to entry.
+struct BatchArgs {
+    const StepArgs* args;
+    const BatchEntry* entries;
+    const int32_t* tile_entry;
+    int32_t entry0;     // combine: entry of the launch's first workgroup
+};
+
 // Host-side launchers (kernels.hip).  launch_step = launch_pass_a,
 // launch_combine, launch_pass_c on the same stream.
 hipError_t launch_step(int dtype, const StepArgs& a, hipStream_t s);
@@ -132,5 +162,13 @@ hipError_t launch_combine(int dtype, const StepArgs& a, hipStream_t s);
 hipError_t launch_pass_c(int dtype, const StepArgs& a, hipStream_t s);
 hipError_t launch_fill(int dtype, const StepArgs& a, double vx, double vy, hipStream_t s);
 hipError_t launch_diag_weights(int dtype, const StepArgs& a, hipStream_t s);
+// Batched passes: pass A and pass C over `tiles` grid tiles, the combine over
+// `count` entries of one combine class starting at b.entry0.  rc: the common
+// disk radius of the batch when it is 5 or 8, else 0.
+hipError_t launch_batch_pass_a(int dtype, int rc, const BatchArgs& b, int tiles, hipStream_t s);
+hipError_t launch_batch_combine(int dtype, int cls, const BatchArgs& b, int count, hipStream_t s);
+hipError_t launch_batch_pass_c(int dtype, const BatchArgs& b, int tiles, hipStream_t s);
+// out[2k], out[2k+1] = estimate of filter k (device memory).
+hipError_t launch_gather_est(const StepArgs* args, int n, double* out, hipStream_t s);
 
 }  // namespace pf

@@ -128,3 +128,69 @@ def workload_video(w: Workload, frames: int | None = None, bounce: bool = False)
     T = w.frames if frames is None else frames
     return moving_disk(w.width, w.height, T, w.radius, w.start, w.velocity, w.noise_sigma,
                        w.video_seed, bounce=bounce)
+
+
+# ---------------------------------------------------------------------------
+# Fleets of independent streams (many trackers advanced together): each stream
+# has its own video of the disk moving at an integer velocity without bouncing,
+# its own particle count and noise level.
+
+@dataclass
+class Stream:
+    stream_id: int
+    n_particles: int
+    start: tuple
+    velocity: tuple
+    noise_sigma: float
+    video_seed: int
+
+
+def stream_mix(n_streams: int, side: int = 256, frames: int = 50, radius: int = 5,
+               n_lo: int = 256, n_hi: int = 65536, noise=(2.0, 6.0), vmax: int = 3,
+               seed: int = 4_000_000) -> list:
+    """Parameters of n_streams streams: N log-uniform in [n_lo, n_hi] (rounded),
+    velocity uniform in {-vmax..vmax}^2, noise sigma uniform in `noise`, start
+    uniform among the centres that keep the disk inside [r, side-1-r] for all
+    frames.  Stream i has stream_id i and video seed seed + i."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    span = frames - 1
+    for i in range(n_streams):
+        n = int(round(float(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi))))))
+        n = min(max(n, n_lo), n_hi)
+        v = (int(rng.integers(-vmax, vmax + 1)), int(rng.integers(-vmax, vmax + 1)))
+        start = []
+        for c in range(2):
+            lo = radius - min(0, v[c] * span)
+            hi = side - 1 - radius - max(0, v[c] * span)
+            start.append(int(rng.integers(lo, hi + 1)))
+        sig = float(rng.uniform(noise[0], noise[1]))
+        out.append(Stream(i, n, (start[0], start[1]), v, sig, seed + i))
+    return out
+
+
+def stream_video(s: Stream, side: int, frames: int, radius: int = 5) -> Video:
+    """The stream's own video, drawn on the host with PCG64(video_seed)."""
+    return moving_disk(side, side, frames, radius, s.start, s.velocity, s.noise_sigma,
+                       s.video_seed)
+
+
+def render_fleet_torch(streams, t: int, side: int, radius: int, device, seed: int,
+                       fg: int = 228, bg: int = 100):
+    """Frame t of every stream as one (n, side, side) uint8 tensor drawn on
+    `device`: same scene and noise model as stream_video, but the noise comes
+    from torch's generator seeded with seed + t (for fleets whose videos are
+    too large to draw on the host)."""
+    import torch
+    n = len(streams)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed) + int(t))
+    c = torch.tensor([[s.start[0] + s.velocity[0] * t, s.start[1] + s.velocity[1] * t]
+                      for s in streams], dtype=torch.float32, device=device)
+    sig = torch.tensor([s.noise_sigma for s in streams], dtype=torch.float32, device=device)
+    ax = torch.arange(side, dtype=torch.float32, device=device)
+    dx2 = (ax.view(1, 1, side) - c[:, 0].view(n, 1, 1)) ** 2
+    dy2 = (ax.view(1, side, 1) - c[:, 1].view(n, 1, 1)) ** 2
+    img = torch.where(dx2 + dy2 < float(radius * radius), float(fg), float(bg))
+    img = img + torch.randn((n, side, side), generator=g, device=device) * sig.view(n, 1, 1)
+    return torch.clamp(torch.floor(img + 0.5), 0, 255).to(torch.uint8)

@@ -25,7 +25,7 @@ def test_library_exports_every_declared_symbol():
     L = ctypes.CDLL(pf.LIB_PATH)
     for name in _declared():
         assert hasattr(L, name), name
-    assert pf.pf_abi_version() == 1
+    assert pf.pf_abi_version() == pf.PF_ABI_VERSION
 
 
 def test_params_struct_matches_header_size():
@@ -72,3 +72,42 @@ def test_null_pointers_are_rejected_without_a_device():
                      ctypes.byref(out)) == pf.PF_ERR_WORKSPACE
     assert L.pf_init(ctypes.byref(p), ctypes.c_void_p(257), 1 << 30, None,
                      ctypes.byref(out)) == pf.PF_ERR_INVALID_ARG
+
+
+def test_batch_workspace_is_the_sum_of_its_filters_plus_the_plan():
+    ps = [pf.make_params(n, 256, 256, "f16", stream_id=i) for i, n in enumerate([256, 1000, 5000, 65536])]
+    total = pf.pf_batch_workspace_bytes(ps)
+    singles = sum(pf.pf_workspace_bytes(p) for p in ps)
+    tiles = sum((p.n_particles + 1023) // 1024 for p in ps)
+    assert total >= singles + 4 * tiles + 32 * len(ps)
+    assert total < singles + 8192 + 4 * tiles + 400 * len(ps)
+
+
+def test_batch_params_are_checked_per_filter():
+    good = pf.make_params(1000, 128, 128, "f16")
+    bad = pf.make_params(1000, 128, 128, "f16", radius=0)
+    with pytest.raises(pf.PfError) as ei:
+        pf.pf_batch_workspace_bytes([good, good, bad])
+    assert ei.value.code == pf.PF_ERR_INVALID_ARG and "filter 2" in pf.pf_last_error()
+    # one dtype per batch
+    with pytest.raises(pf.PfError):
+        pf.pf_batch_workspace_bytes([good, pf.make_params(1000, 128, 128, "f32")])
+    L = pf.lib()
+    out = ctypes.c_size_t()
+    arr = (pf.pf_params * 1)(good)
+    assert L.pf_batch_workspace_bytes(arr, 0, ctypes.byref(out)) == pf.PF_ERR_INVALID_ARG
+    assert L.pf_batch_workspace_bytes(None, 1, ctypes.byref(out)) == pf.PF_ERR_INVALID_ARG
+    assert L.pf_batch_workspace_bytes(arr, 1, None) == pf.PF_ERR_INVALID_ARG
+
+
+def test_batch_null_handles_are_rejected_without_a_device():
+    L = pf.lib()
+    assert L.pf_batch_step(None, None, None, None) == pf.PF_ERR_INVALID_ARG
+    assert L.pf_batch_estimates(None, None) == pf.PF_ERR_INVALID_ARG
+    out = ctypes.c_void_p()
+    assert L.pf_batch_filter(None, 0, ctypes.byref(out)) == pf.PF_ERR_INVALID_ARG
+    assert L.pf_batch_destroy(None) == pf.PF_OK
+    good = pf.make_params(1000, 128, 128, "f16")
+    arr = (pf.pf_params * 1)(good)
+    assert L.pf_batch_init(arr, 1, ctypes.c_void_p(256), 16, None,
+                           ctypes.byref(out)) == pf.PF_ERR_WORKSPACE

@@ -218,3 +218,51 @@ def test_f32_track_matches_f64_track():
         rms = np.sqrt(np.mean(np.sum((ests - est64) ** 2, axis=1)))
         print(f"[parity] {dtype} track RMS vs FP64 oracle {rms:.3e} px")
         assert rms <= (1e-6 if dtype == "f64" else 0.5)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f16", "bf16"])
+def test_runs_are_bit_identical(dtype):
+    w = pfsynth.WORKLOADS["disk128_n1000"]
+    vid = pfsynth.workload_video(w)
+    frames = _dev(vid.frames)
+    outs = []
+    for _ in range(2):
+        f = make_filter(dtype, 3000, w.width, w.height, w.radius, *vid.centres[0], seed=9)
+        ests = []
+        for t in range(1, w.frames):
+            f.step(frames[t])
+            ests.append(f.estimate())
+        got = f.export()
+        f.close()
+        outs.append((np.array(ests), got))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    for key in ("x", "y", "w", "anc"):
+        assert np.array_equal(outs[0][1][key], outs[1][1][key]), key
+
+
+def test_f64_checkpoint_resume_is_bit_identical():
+    # counter-based random streams: 10 steps == 5 steps, export, import into a
+    # fresh filter, 5 more steps
+    w = pfsynth.WORKLOADS["disk128_n1000"]
+    vid = pfsynth.workload_video(w)
+    frames = _dev(vid.frames)
+    n = 2500
+    a = make_filter("f64", n, w.width, w.height, w.radius, *vid.centres[0], seed=3)
+    for t in range(1, 10):
+        a.step(frames[t])
+    full = a.export()
+    est_a = a.estimate()
+    b = make_filter("f64", n, w.width, w.height, w.radius, *vid.centres[0], seed=3)
+    for t in range(1, 5):
+        b.step(frames[t])
+    mid = b.export()
+    c = make_filter("f64", n, w.width, w.height, w.radius, *vid.centres[0], seed=3)
+    c.load(mid["x"], mid["y"], mid["t"])
+    for t in range(5, 10):
+        c.step(frames[t])
+    res = c.export()
+    assert res["t"] == full["t"] == 9
+    assert np.array_equal(res["x"], full["x"]) and np.array_equal(res["y"], full["y"])
+    assert c.estimate() == est_a
+    for f in (a, b, c):
+        f.close()
