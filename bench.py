@@ -131,6 +131,53 @@ def track(pf, frames_dev, centres, w, dtype, nsteps):
     return np.array(est)
 
 
+def run_fleet(pf, torch, pfsynth, n_streams, side, frames, steps, warmup, dtype="f16"):
+    """The stream fleet: n_streams independent filters (N log-uniform in
+    [256, 65536]) on their own side x side videos, drawn on the device and
+    resident before timing; one pf_batch_step per frame index."""
+    import ctypes
+    assert warmup + steps <= frames - 1
+    streams = pfsynth.stream_mix(n_streams, side=side, frames=frames)
+    log(f"[bench] fleet: drawing {frames} frames of {n_streams} streams ({side}x{side}) on the device")
+    vids = torch.stack([pfsynth.render_fleet_torch(streams, t, side, 5, "cuda:0", seed=4_000_000)
+                        for t in range(frames)])  # (T, n, side, side)
+    params = [pf.make_params(s.n_particles, side, side, dtype, radius=5, x0=s.start[0],
+                             y0=s.start[1], drift=s.velocity, seed=0, stream_id=s.stream_id)
+              for s in streams]
+    b = pf.Batch(params)
+    base = int(vids.data_ptr())
+    fstride, sstride = int(vids.stride(0)), int(vids.stride(1))
+    ptrs = [np.array([base + t * fstride + k * sstride for k in range(n_streams)], dtype=np.uint64)
+            for t in range(frames)]
+    pitches = np.full(n_streams, int(vids.stride(2)), dtype=np.int64)
+    step = pf.lib().pf_batch_step
+    pp = ctypes.c_void_p(pitches.ctypes.data)
+    h = b.handle
+    for t in range(1, warmup + 1):
+        if step(h, ctypes.c_void_p(ptrs[t].ctypes.data), pp, None):
+            raise pf.PfError(-1, pf.pf_last_error())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(warmup + 1, warmup + steps + 1):
+        step(h, ctypes.c_void_p(ptrs[t].ctypes.data), pp, None)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    est = b.estimates()
+    t_end = warmup + steps
+    truth = np.array([[s.start[0] + s.velocity[0] * t_end, s.start[1] + s.velocity[1] * t_end]
+                      for s in streams])
+    err = np.hypot(*(est - truth).T)
+    b.close()
+    total = sum(p.n_particles for p in params)
+    return dict(workload=f"{n_streams} streams, {side}x{side} uint8 video each (drawn on the device), "
+                         f"{frames} frames, disk r=5, noise sigma U[2,6], velocity in {{-3..3}}^2, "
+                         f"N log-uniform in [256, 65536]",
+                dtype=dtype, filters=n_streams, particles=total, steps=steps, warmup=warmup,
+                ms_per_step=1e3 * secs / steps, updates_per_s=total * steps / secs,
+                final_error_median_px=float(np.median(err)),
+                final_error_p99_px=float(np.percentile(err, 99)))
+
+
 def cpu_baseline(w, vid, budget_s):
     """The FP64 oracle (sequential C, one thread) on the first steps of the
     same video at the same N, as many steps as fit in about budget_s."""
@@ -164,6 +211,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-track", action="store_true")
+    ap.add_argument("--large", default="disk512_r8_n16m",
+                    help="second single-filter workload timed in every mode ('none' to skip)")
+    ap.add_argument("--fleet", type=int, default=4096, metavar="STREAMS",
+                    help="streams of the batched fleet workload (0 to skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (five times), "
                          "to scale hardware byte counters")
@@ -262,6 +313,31 @@ def main():
         out["speedup_f16_vs_f64"] = res["f64"]["seconds"] / res.get("f16", res["f64"])["seconds"]
     if "f32" in res and "f16" in res:
         out["speedup_f16_vs_f32"] = res["f32"]["seconds"] / res["f16"]["seconds"]
+    if args.large and args.large != "none":
+        wl = pfsynth.WORKLOADS[args.large]
+        log(f"[bench] generating {wl.name}: {wl.frames} frames {wl.width}x{wl.height}")
+        vl = pfsynth.workload_video(wl)
+        fl = torch.from_numpy(vl.frames).to("cuda:0")
+        ls, lw = min(args.steps, wl.frames - 6), 5
+        lres = {}
+        for dt in modes:
+            secs, _ = run_mode(pf, torch, fl, vl.centres, wl, dt, ls, lw, profile=False)
+            lres[dt] = dict(ms_per_step=1e3 * secs / ls, updates_per_s=wl.n_particles * ls / secs)
+        if not args.no_track and "f64" in modes:
+            ref = track(pf, fl, vl.centres, wl, "f64", wl.frames - 1)
+            for dt in modes:
+                est = ref if dt == "f64" else track(pf, fl, vl.centres, wl, dt, wl.frames - 1)
+                lres[dt]["track_rms_vs_f64_px"] = float(np.sqrt(np.mean(np.sum((est - ref) ** 2, axis=1))))
+        log(f"[bench] {wl.name}: {lres}")
+        out["large"] = dict(workload=f"{wl.name}: {wl.width}x{wl.height}, {wl.frames} frames, disk r={wl.radius}, "
+                                     f"noise sigma {wl.noise_sigma}, N={wl.n_particles}, one filter",
+                            steps=ls, warmup=lw, modes=lres)
+        del fl
+    if args.fleet:
+        fr = run_fleet(pf, torch, pfsynth, args.fleet, 256, 50, 40, 5)
+        log(f"[bench] fleet: {fr}")
+        out["fleet"] = fr
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(w, vid, args.cpu_budget)

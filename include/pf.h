@@ -166,9 +166,10 @@ const char* pf_last_error(void);
 
 /* Per-pass timing with HIP events on the filter's stream.  pf_profile_start
  * creates the events for up to `max_steps` steps (host-side objects, no device
- * memory) and records them around every kernel of the following pf_step
- * calls; pf_profile_read waits for the stream and returns the summed
- * durations in milliseconds: out_ms[0] = pass A (propagate, likelihood, tile
+ * memory); the following pf_step calls launch their kernels with start and
+ * stop events stamped by each kernel's own dispatch (its execution time, no
+ * extra queue packets); pf_profile_read waits for the stream and returns the
+ * summed durations in milliseconds: out_ms[0] = pass A (propagate, likelihood, tile
  * maximum, weights, tile prefix sums), out_ms[1] = combine (global maximum,
  * normaliser, carried offsets, estimate, resampling offset), out_ms[2] = pass C
  * (systematic-resampling scatter), and the number of steps recorded; it then

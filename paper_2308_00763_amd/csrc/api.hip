@@ -15,7 +15,7 @@
 
 using namespace pf;
 
-constexpr int kProfEv = 4;  // before pass A, after pass A, after combine, after pass C
+constexpr int kProfEv = 6;  // start and end of pass A, of the combine and of pass C
 
 struct pf_filter {
     pf_params p;
@@ -300,13 +300,13 @@ int pf_step(pf_filter* h, const uint8_t* d_frame, int64_t row_pitch)
     hipError_t e;
     if (h->prof_used < h->prof_max) {
         hipEvent_t* ev = &h->prof_ev[kProfEv * (size_t)h->prof_used];
-        e = hipEventRecord(ev[0], h->stream);
-        if (e == hipSuccess) e = launch_pass_a(h->p.dtype, a, h->stream);
-        if (e == hipSuccess) e = hipEventRecord(ev[1], h->stream);
-        if (e == hipSuccess) e = launch_combine(h->p.dtype, a, h->stream);
-        if (e == hipSuccess) e = hipEventRecord(ev[2], h->stream);
-        if (e == hipSuccess) e = launch_pass_c(h->p.dtype, a, h->stream);
-        if (e == hipSuccess) e = hipEventRecord(ev[3], h->stream);
+        KTiming ta, tb, tc;
+        ta.start = ev[0]; ta.stop = ev[1];
+        tb.start = ev[2]; tb.stop = ev[3];
+        tc.start = ev[4]; tc.stop = ev[5];
+        e = launch_pass_a(h->p.dtype, a, h->stream, ta);
+        if (e == hipSuccess) e = launch_combine(h->p.dtype, a, h->stream, tb);
+        if (e == hipSuccess) e = launch_pass_c(h->p.dtype, a, h->stream, tc);
         ++h->prof_used;
     } else {
         e = launch_step(h->p.dtype, a, h->stream);
@@ -482,7 +482,7 @@ int pf_profile_read(pf_filter* h, double out_ms[3], uint32_t* steps)
     for (uint32_t i = 0; e == hipSuccess && i < h->prof_used; ++i) {
         for (int k = 0; k < 3 && e == hipSuccess; ++k) {
             float ms = 0;
-            e = hipEventElapsedTime(&ms, h->prof_ev[kProfEv * i + k], h->prof_ev[kProfEv * i + k + 1]);
+            e = hipEventElapsedTime(&ms, h->prof_ev[kProfEv * i + 2 * k], h->prof_ev[kProfEv * i + 2 * k + 1]);
             acc[k] += ms;
         }
     }

@@ -23,6 +23,7 @@
 // The maximum and weighting are fused into pass A and the cumulative
 // distribution is evaluated on the fly in pass C, so the six kernels of the
 // paper become three, two of them wide.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -140,7 +141,7 @@ struct ModeT;
 
 template <>
 struct ModeT<PF_F64> {
-    static constexpr int PPT = 4;
+    static constexpr int PPT = kPPT;
     using Store = double;
     using Val = double;
     struct Prop {
@@ -149,14 +150,17 @@ struct ModeT<PF_F64> {
     static __device__ __forceinline__ void load(const void* p, int k0, Val* v)
     {
         const double2* q = reinterpret_cast<const double2*>(static_cast<const double*>(p) + k0);
-        const double2 a = q[0], b = q[1];
-        v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+#pragma unroll
+        for (int i = 0; i < PPT / 2; ++i) {
+            const double2 a = q[i];
+            v[2 * i] = a.x; v[2 * i + 1] = a.y;
+        }
     }
     static __device__ __forceinline__ void store(void* p, int k0, const Val* v)
     {
         double2* q = reinterpret_cast<double2*>(static_cast<double*>(p) + k0);
-        q[0] = make_double2(v[0], v[1]);
-        q[1] = make_double2(v[2], v[3]);
+#pragma unroll
+        for (int i = 0; i < PPT / 2; ++i) q[i] = make_double2(v[2 * i], v[2 * i + 1]);
     }
     // x <- x + (d + sigma z), each operation rounded (library built without
     // contraction), as Eq. (1)-(2) are written.
@@ -182,7 +186,7 @@ struct ModeT<PF_F64> {
 
 template <>
 struct ModeT<PF_F32> {
-    static constexpr int PPT = 4;
+    static constexpr int PPT = kPPT;
     using Store = float;
     using Val = float;
     struct Prop {
@@ -190,12 +194,18 @@ struct ModeT<PF_F32> {
     };
     static __device__ __forceinline__ void load(const void* p, int k0, Val* v)
     {
-        const float4 a = *reinterpret_cast<const float4*>(static_cast<const float*>(p) + k0);
-        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        const float2* q = reinterpret_cast<const float2*>(static_cast<const float*>(p) + k0);
+#pragma unroll
+        for (int i = 0; i < PPT / 2; ++i) {
+            const float2 a = q[i];
+            v[2 * i] = a.x; v[2 * i + 1] = a.y;
+        }
     }
     static __device__ __forceinline__ void store(void* p, int k0, const Val* v)
     {
-        *reinterpret_cast<float4*>(static_cast<float*>(p) + k0) = make_float4(v[0], v[1], v[2], v[3]);
+        float2* q = reinterpret_cast<float2*>(static_cast<float*>(p) + k0);
+#pragma unroll
+        for (int i = 0; i < PPT / 2; ++i) q[i] = make_float2(v[2 * i], v[2 * i + 1]);
     }
     static __device__ __forceinline__ void propagate(Val* x, Val* y, const Prop& pr, const StepArgs& a,
                                                      int k0)
@@ -219,7 +229,7 @@ struct ModeT<PF_F32> {
 // fused multiply-add (sigma * z + d) and one packed add per pair and axis.
 template <>
 struct ModeT<PF_F16> {
-    static constexpr int PPT = 4;
+    static constexpr int PPT = kPPT;
     using Store = _Float16;
     using Val = _Float16;
     struct Prop {
@@ -227,15 +237,21 @@ struct ModeT<PF_F16> {
     };
     static __device__ __forceinline__ void load(const void* p, int k0, Val* v)
     {
-        const uint2 a = *reinterpret_cast<const uint2*>(static_cast<const _Float16*>(p) + k0);
-        const half2_t h0 = __builtin_bit_cast(half2_t, a.x), h1 = __builtin_bit_cast(half2_t, a.y);
-        v[0] = h0.x; v[1] = h0.y; v[2] = h1.x; v[3] = h1.y;
+        const uint32_t* q = reinterpret_cast<const uint32_t*>(static_cast<const _Float16*>(p) + k0);
+#pragma unroll
+        for (int i = 0; i < PPT / 2; ++i) {
+            const half2_t h = __builtin_bit_cast(half2_t, q[i]);
+            v[2 * i] = h.x; v[2 * i + 1] = h.y;
+        }
     }
     static __device__ __forceinline__ void store(void* p, int k0, const Val* v)
     {
-        const half2_t h0 = {v[0], v[1]}, h1 = {v[2], v[3]};
-        *reinterpret_cast<uint2*>(static_cast<_Float16*>(p) + k0) =
-            make_uint2(__builtin_bit_cast(uint32_t, h0), __builtin_bit_cast(uint32_t, h1));
+        uint32_t* q = reinterpret_cast<uint32_t*>(static_cast<_Float16*>(p) + k0);
+#pragma unroll
+        for (int i = 0; i < PPT / 2; ++i) {
+            const half2_t h = {v[2 * i], v[2 * i + 1]};
+            q[i] = __builtin_bit_cast(uint32_t, h);
+        }
     }
     static __device__ __forceinline__ void propagate(Val* x, Val* y, const Prop& pr, const StepArgs& a,
                                                      int k0)
@@ -270,7 +286,7 @@ struct ModeT<PF_F16> {
 // rounding reaches the next step's ancestors.
 template <>
 struct ModeT<PF_BF16> {
-    static constexpr int PPT = 4;
+    static constexpr int PPT = kPPT;
     using Store = uint16_t;
     using Val = float;  // widened on load
     struct Prop {
@@ -278,11 +294,13 @@ struct ModeT<PF_BF16> {
     };
     static __device__ __forceinline__ void load(const void* p, int k0, Val* v)
     {
-        const uint2 a = *reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(p) + k0);
-        v[0] = __uint_as_float(a.x << 16);
-        v[1] = __uint_as_float(a.x & 0xFFFF0000u);
-        v[2] = __uint_as_float(a.y << 16);
-        v[3] = __uint_as_float(a.y & 0xFFFF0000u);
+        const uint32_t* q = reinterpret_cast<const uint32_t*>(static_cast<const uint16_t*>(p) + k0);
+#pragma unroll
+        for (int i = 0; i < PPT / 2; ++i) {
+            const uint32_t a = q[i];
+            v[2 * i] = __uint_as_float(a << 16);
+            v[2 * i + 1] = __uint_as_float(a & 0xFFFF0000u);
+        }
     }
     static __device__ __forceinline__ uint32_t pack(float lo, float hi)
     {
@@ -291,7 +309,9 @@ struct ModeT<PF_BF16> {
     }
     static __device__ __forceinline__ void store(void* p, int k0, const Val* v)
     {
-        *reinterpret_cast<uint2*>(static_cast<uint16_t*>(p) + k0) = make_uint2(pack(v[0], v[1]), pack(v[2], v[3]));
+        uint32_t* q = reinterpret_cast<uint32_t*>(static_cast<uint16_t*>(p) + k0);
+#pragma unroll
+        for (int i = 0; i < PPT / 2; ++i) q[i] = pack(v[2 * i], v[2 * i + 1]);
     }
     static __device__ __forceinline__ void propagate(Val* x, Val* y, const Prop& pr, const StepArgs& a,
                                                      int k0)
@@ -334,10 +354,10 @@ __device__ __forceinline__ typename ModeT<DT>::Prop make_prop(const StepArgs& a,
 
 struct PassALds {
     uint16_t pref[kPrefPitch * kPrefRows];
-    int box[kWaves][4];
-    double red_d[3][kWaves];
-    float red_f[3][kWaves];
-    int red_i[kWaves];
+    int box[kWavesA][4];
+    double red_d[3][kWavesA];
+    float red_f[3][kWavesA];
+    int red_i[kWavesA];
 };
 
 // Pass A of tile `tile` of the filter described by `a`.
@@ -346,7 +366,7 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
 {
     using M = ModeT<DT>;
     constexpr int PPT = M::PPT;
-    static_assert(kBlock * PPT == kTile, "tile size");
+    static_assert(kBlockA * PPT == kTile, "tile size");
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
@@ -397,7 +417,7 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
     }
     __syncthreads();
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
+    for (int w = 0; w < kWavesA; ++w) {
         b0 = min(b0, lds.box[w][0]); b1 = min(b1, lds.box[w][1]);
         b2 = min(b2, lds.box[w][2]); b3 = min(b3, lds.box[w][3]);
     }
@@ -414,18 +434,18 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
     const bool in_lds = ww <= kWinMaxW && wh <= kPrefRows;
     int S[PPT];
     if (in_lds) {
-        constexpr int kMaxRounds = kPrefRows / (kWaves * 2);  // 32-lane rows: 2 per wave per round
+        constexpr int kMaxRounds = kPrefRows / (kWavesA * 2);  // 32-lane rows: 2 per wave per round
         const bool narrow = ww <= 64;
         const int lpr = narrow ? 16 : 32;
         const int rpr = 64 / lpr;                 // rows per wave per round
         const int sub = lane / lpr, l = lane - sub * lpr;
         const int c0 = 4 * l;
-        const int rows_per_round = kWaves * rpr;
+        const int rows_per_round = kWavesA * rpr;
         const int rounds = (wh + rows_per_round - 1) / rows_per_round;
         uint32_t v[kMaxRounds];
 #pragma unroll
         for (int it = 0; it < kMaxRounds; ++it) {
-            const int yy = (it * kWaves + wv) * rpr + sub;
+            const int yy = (it * kWavesA + wv) * rpr + sub;
             v[it] = 0;
             if (it < rounds && yy < wh) {
                 const int row = min(max(wy0 + yy, 0), a.H - 1);
@@ -442,7 +462,7 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
 #pragma unroll
         for (int it = 0; it < kMaxRounds; ++it) {
             if (it < rounds) {  // uniform: every lane takes part in the scan
-                const int yy = (it * kWaves + wv) * rpr + sub;
+                const int yy = (it * kWavesA + wv) * rpr + sub;
                 const int p1 = (int)(v[it] & 0xFF);
                 const int p2 = p1 + (int)((v[it] >> 8) & 0xFF);
                 const int p3 = p2 + (int)((v[it] >> 16) & 0xFF);
@@ -493,7 +513,7 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
             L[i] = (double)S[i] / a.denom;
             if (valid[i]) m = fmax(m, L[i]);
         }
-        m = block_max<kWaves>(m, lds.red_d[0]);
+        m = block_max<kWavesA>(m, lds.red_d[0]);
         tile_m = m;
 #pragma unroll
         for (int i = 0; i < PPT; ++i) wt[i] = valid[i] ? exp(L[i] - m) : 0.0;
@@ -502,7 +522,7 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
 #pragma unroll
         for (int i = 0; i < PPT; ++i)
             if (valid[i]) sm = max(sm, S[i]);
-        sm = block_max<kWaves>(sm, lds.red_i);
+        sm = block_max<kWavesA>(sm, lds.red_i);
         tile_smax = sm;
 #pragma unroll
         for (int i = 0; i < PPT; ++i)
@@ -528,7 +548,7 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
     sw = wave_incl_max(sw, lane);
     ex = wave_sum(ex);
     ey = wave_sum(ey);
-    Acc (*red)[kWaves];
+    Acc (*red)[kWavesA];
     if constexpr (DT == PF_F64) red = lds.red_d; else red = lds.red_f;
     if (lane == 63) {
         red[0][wv] = sw;
@@ -551,10 +571,12 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
     }
     if constexpr (DT == PF_F64) {
         double2* qp = reinterpret_cast<double2*>(static_cast<double*>(a.q) + k0);
-        qp[0] = make_double2(q[0], q[1]);
-        qp[1] = make_double2(q[2], q[3]);
+#pragma unroll
+        for (int i = 0; i < PPT / 2; ++i) qp[i] = make_double2(q[2 * i], q[2 * i + 1]);
     } else {
-        *reinterpret_cast<float4*>(static_cast<float*>(a.q) + k0) = make_float4(q[0], q[1], q[2], q[3]);
+        float2* qp = reinterpret_cast<float2*>(static_cast<float*>(a.q) + k0);
+#pragma unroll
+        for (int i = 0; i < PPT / 2; ++i) qp[i] = make_float2(q[2 * i], q[2 * i + 1]);
     }
     if (a.dg_s) {
 #pragma unroll
@@ -563,10 +585,10 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
             a.dg_w[k0 + i] = (double)wt[i];
         }
     }
-    if (tid == kBlock - 1) {
+    if (tid == kBlockA - 1) {
         // the tile total is the last thread's inclusive value
         Acc tx = red[1][0], ty = red[2][0];
-        for (int w = 1; w < kWaves; ++w) {
+        for (int w = 1; w < kWavesA; ++w) {
             tx = tx + red[1][w];
             ty = ty + red[2][w];
         }
@@ -579,7 +601,7 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
 }
 
 template <int DT, int RC>
-__global__ __launch_bounds__(kBlock) void pass_a_kernel(StepArgs a)
+__global__ __launch_bounds__(kBlockA) void pass_a_kernel(StepArgs a)
 {
     __shared__ PassALds lds;
     pass_a_tile<DT, RC>(a, blockIdx.x, lds);
@@ -957,10 +979,13 @@ __global__ __launch_bounds__(NT) void combine_kernel(StepArgs a)
 // j when e_k <= j) is cut into equal pieces, one per thread: with
 // g(k) = e_k + k strictly increasing, the cut at diagonal d is the first k
 // with g(k) >= d.  Each thread finds its cut by a binary search over the
-// tile's end slots in LDS, then walks its piece, writing the ancestor's
-// propagated position to every slot it meets.  A tile that owns many slots
-// gives its threads longer pieces; the work never depends on how the slots
-// are spread inside the tile.
+// tile's end slots in LDS, then walks its piece, noting the ancestor of every
+// slot it meets in LDS; the workgroup then writes the ancestors' propagated
+// positions to the slots with consecutive lanes on consecutive slots.  A tile
+// that owns many slots takes several rounds of at most kDiagRound diagonals;
+// the work never depends on how the slots are spread inside the tile.
+
+constexpr int kDiagRound = 16 * kBlock;  // merge diagonals per round (16 per thread)
 
 template <int DT>
 struct PassCLds {
@@ -968,7 +993,20 @@ struct PassCLds {
     int32_t e[kTile];
     Store x[kTile];
     Store y[kTile];
+    uint16_t anc[kDiagRound];  // tile-local ancestor of each slot of the round
 };
+
+// First k in [0, tt] with e[k] + k >= d (k = tt stands for true).
+__device__ __forceinline__ int merge_cut(const int32_t* e, int tt, int d)
+{
+    int lo = 0, hi = tt;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (e[mid] + mid >= d) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
 
 // Pass C of tile `t` of the filter described by `a`.
 template <int DT>
@@ -999,32 +1037,38 @@ __device__ __forceinline__ void pass_c_tile(const StepArgs& a, int t, PassCLds<D
     }
     __syncthreads();
     const int slots = ts.E - ts.Eprev;
-    if (slots <= 0) return;
+    if (slots <= 0) return;  // uniform over the workgroup
     const int total = tt + slots;
-    const int ipt = (total + kBlock - 1) / kBlock;
-    const int ds = min(tid * ipt, total), de = min(ds + ipt, total);
-    if (ds >= de) return;
-    // first k in [0, tt] with s_e[k] + k >= ds (k = tt stands for true)
-    int lo = 0, hi = tt;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (s_e[mid] + mid >= ds) hi = mid;
-        else lo = mid + 1;
-    }
-    int k = lo, j = ds - lo;
-    Store* sx = static_cast<Store*>(a.sx);
-    Store* sy = static_cast<Store*>(a.sy);
-    for (int d = ds; d < de; ++d) {
-        if (k < tt && s_e[k] <= j) {
-            ++k;  // particle k has no slot left: the merge takes it
-        } else {
-            const int kk = min(k, tt - 1);
-            const int slot = ts.Eprev + j;
-            sx[slot] = s_x[kk];
-            sy[slot] = s_y[kk];
-            if (a.dg_anc) a.dg_anc[slot] = first + kk;
-            ++j;
+    const int ipt = min((total + kBlock - 1) / kBlock, kDiagRound / kBlock);
+    const int round = ipt * kBlock;
+    Store* sx = static_cast<Store*>(a.sx) + ts.Eprev;
+    Store* sy = static_cast<Store*>(a.sy) + ts.Eprev;
+    int32_t* anc_out = a.dg_anc ? a.dg_anc + ts.Eprev : nullptr;
+    for (int d0 = 0; d0 < total; d0 += round) {
+        // slots of this round: [j0, j1), the slot coordinates of its two cuts
+        const int d1 = min(d0 + round, total);
+        const int j0 = d0 == 0 ? 0 : d0 - merge_cut(s_e, tt, d0);
+        const int j1 = d1 == total ? slots : d1 - merge_cut(s_e, tt, d1);
+        const int ds = min(d0 + tid * ipt, d1), de = min(ds + ipt, d1);
+        if (ds < de) {
+            int k = merge_cut(s_e, tt, ds), j = ds - k;
+            for (int d = ds; d < de; ++d) {
+                if (k < tt && s_e[k] <= j) {
+                    ++k;  // particle k has no slot left: the merge takes it
+                } else {
+                    lds.anc[j - j0] = (uint16_t)min(k, tt - 1);
+                    ++j;
+                }
+            }
         }
+        __syncthreads();
+        for (int i = tid; i < j1 - j0; i += kBlock) {
+            const int kk = lds.anc[i];
+            sx[j0 + i] = s_x[kk];
+            sy[j0 + i] = s_y[kk];
+            if (anc_out) anc_out[j0 + i] = first + kk;
+        }
+        __syncthreads();
     }
 }
 
@@ -1081,7 +1125,7 @@ __device__ __forceinline__ StepArgs batch_args(const BatchArgs& b, int e)
 }
 
 template <int DT, int RC>
-__global__ __launch_bounds__(kBlock) void pass_a_batch_kernel(BatchArgs b)
+__global__ __launch_bounds__(kBlockA) void pass_a_batch_kernel(BatchArgs b)
 {
     __shared__ PassALds lds;
     const int e = b.tile_entry[blockIdx.x];
@@ -1116,127 +1160,104 @@ __global__ __launch_bounds__(kBlock) void gather_est_kernel(const StepArgs* args
 }
 
 // ---------------------------------------------------------------------------
-// Launchers.
+// Launchers.  With a KTiming the kernel goes through hipExtLaunchKernel, whose
+// events take the start and end timestamps of the kernel's own execution.
 
-template <int DT>
-static hipError_t launch_pass_a_t(const StepArgs& a, hipStream_t s)
+template <typename Arg>
+static hipError_t launch1(void (*kernel)(Arg), dim3 g, dim3 b, hipStream_t s, const KTiming& tm, Arg arg)
 {
-    const dim3 blk(kBlock);
-    const dim3 ga((unsigned)a.ntiles);
-    if (a.r == 5) pass_a_kernel<DT, 5><<<ga, blk, 0, s>>>(a);
-    else if (a.r == 8) pass_a_kernel<DT, 8><<<ga, blk, 0, s>>>(a);
-    else pass_a_kernel<DT, 0><<<ga, blk, 0, s>>>(a);
-    return hipGetLastError();
-}
-
-template <int DT>
-static hipError_t launch_pass_c_t(const StepArgs& a, hipStream_t s)
-{
-    pass_c_kernel<DT><<<dim3((unsigned)a.ntiles), dim3(kBlock), 0, s>>>(a);
-    return hipGetLastError();
-}
-
-hipError_t launch_pass_a(int dtype, const StepArgs& a, hipStream_t s)
-{
-    switch (dtype) {
-    case PF_F64: return launch_pass_a_t<PF_F64>(a, s);
-    case PF_F32: return launch_pass_a_t<PF_F32>(a, s);
-    case PF_F16: return launch_pass_a_t<PF_F16>(a, s);
-    case PF_BF16: return launch_pass_a_t<PF_BF16>(a, s);
-    default: return hipErrorInvalidValue;
+    if (tm.start) {
+        void* args[] = {&arg};
+        return hipExtLaunchKernel(reinterpret_cast<const void*>(kernel), g, b, args, 0, s, tm.start, tm.stop, 0);
     }
+    kernel<<<g, b, 0, s>>>(arg);
+    return hipGetLastError();
 }
 
 template <int DT>
-static void launch_combine_t(const StepArgs& a, hipStream_t s)
+static hipError_t launch_pass_a_t(const StepArgs& a, hipStream_t s, const KTiming& tm)
+{
+    const dim3 g((unsigned)a.ntiles), blk(kBlockA);
+    if (a.r == 5) return launch1(pass_a_kernel<DT, 5>, g, blk, s, tm, a);
+    if (a.r == 8) return launch1(pass_a_kernel<DT, 8>, g, blk, s, tm, a);
+    return launch1(pass_a_kernel<DT, 0>, g, blk, s, tm, a);
+}
+
+template <int DT>
+static hipError_t launch_pass_c_t(const StepArgs& a, hipStream_t s, const KTiming& tm)
+{
+    return launch1(pass_c_kernel<DT>, dim3((unsigned)a.ntiles), dim3(kBlock), s, tm, a);
+}
+
+template <int DT>
+static hipError_t launch_combine_t(const StepArgs& a, hipStream_t s, const KTiming& tm)
 {
     switch (comb_class(a.ntiles)) {
-    case 0: combine_kernel<DT, 1, 256><<<1, 256, 0, s>>>(a); break;
-    case 1: combine_kernel<DT, 1, 1024><<<1, 1024, 0, s>>>(a); break;
-    case 2: combine_kernel<DT, 4, 1024><<<1, 1024, 0, s>>>(a); break;
-    default: combine_kernel<DT, 16, 1024><<<1, 1024, 0, s>>>(a); break;
+    case 0: return launch1(combine_kernel<DT, 1, 256>, dim3(1), dim3(256), s, tm, a);
+    case 1: return launch1(combine_kernel<DT, 1, 1024>, dim3(1), dim3(1024), s, tm, a);
+    case 2: return launch1(combine_kernel<DT, 4, 1024>, dim3(1), dim3(1024), s, tm, a);
+    default: return launch1(combine_kernel<DT, 16, 1024>, dim3(1), dim3(1024), s, tm, a);
     }
 }
 
-hipError_t launch_combine(int dtype, const StepArgs& a, hipStream_t s)
-{
-    switch (dtype) {
-    case PF_F64: launch_combine_t<PF_F64>(a, s); break;
-    case PF_F32: launch_combine_t<PF_F32>(a, s); break;
-    case PF_F16: launch_combine_t<PF_F16>(a, s); break;
-    case PF_BF16: launch_combine_t<PF_BF16>(a, s); break;
-    default: return hipErrorInvalidValue;
+#define PF_DISPATCH(dtype, call)                         \
+    switch (dtype) {                                     \
+    case PF_F64: { constexpr int DT = PF_F64; return call; } \
+    case PF_F32: { constexpr int DT = PF_F32; return call; } \
+    case PF_F16: { constexpr int DT = PF_F16; return call; } \
+    case PF_BF16: { constexpr int DT = PF_BF16; return call; } \
+    default: return hipErrorInvalidValue;                \
     }
-    return hipGetLastError();
+
+hipError_t launch_pass_a(int dtype, const StepArgs& a, hipStream_t s, const KTiming& tm)
+{
+    PF_DISPATCH(dtype, launch_pass_a_t<DT>(a, s, tm))
 }
 
-hipError_t launch_pass_c(int dtype, const StepArgs& a, hipStream_t s)
+hipError_t launch_combine(int dtype, const StepArgs& a, hipStream_t s, const KTiming& tm)
 {
-    switch (dtype) {
-    case PF_F64: return launch_pass_c_t<PF_F64>(a, s);
-    case PF_F32: return launch_pass_c_t<PF_F32>(a, s);
-    case PF_F16: return launch_pass_c_t<PF_F16>(a, s);
-    case PF_BF16: return launch_pass_c_t<PF_BF16>(a, s);
-    default: return hipErrorInvalidValue;
-    }
+    PF_DISPATCH(dtype, launch_combine_t<DT>(a, s, tm))
+}
+
+hipError_t launch_pass_c(int dtype, const StepArgs& a, hipStream_t s, const KTiming& tm)
+{
+    PF_DISPATCH(dtype, launch_pass_c_t<DT>(a, s, tm))
 }
 
 template <int DT>
-static void launch_batch_pass_a_t(int rc, const BatchArgs& b, int tiles, hipStream_t s)
+static hipError_t launch_batch_pass_a_t(int rc, const BatchArgs& b, int tiles, hipStream_t s, const KTiming& tm)
 {
-    const dim3 g((unsigned)tiles), blk(kBlock);
-    if (rc == 5) pass_a_batch_kernel<DT, 5><<<g, blk, 0, s>>>(b);
-    else if (rc == 8) pass_a_batch_kernel<DT, 8><<<g, blk, 0, s>>>(b);
-    else pass_a_batch_kernel<DT, 0><<<g, blk, 0, s>>>(b);
+    const dim3 g((unsigned)tiles), blk(kBlockA);
+    if (rc == 5) return launch1(pass_a_batch_kernel<DT, 5>, g, blk, s, tm, b);
+    if (rc == 8) return launch1(pass_a_batch_kernel<DT, 8>, g, blk, s, tm, b);
+    return launch1(pass_a_batch_kernel<DT, 0>, g, blk, s, tm, b);
 }
 
 template <int DT>
-static void launch_batch_combine_t(int cls, const BatchArgs& b, int count, hipStream_t s)
+static hipError_t launch_batch_combine_t(int cls, const BatchArgs& b, int count, hipStream_t s, const KTiming& tm)
 {
     const dim3 g((unsigned)count);
     switch (cls) {
-    case 0: combine_batch_kernel<DT, 1, 256><<<g, 256, 0, s>>>(b); break;
-    case 1: combine_batch_kernel<DT, 1, 1024><<<g, 1024, 0, s>>>(b); break;
-    case 2: combine_batch_kernel<DT, 4, 1024><<<g, 1024, 0, s>>>(b); break;
-    default: combine_batch_kernel<DT, 16, 1024><<<g, 1024, 0, s>>>(b); break;
+    case 0: return launch1(combine_batch_kernel<DT, 1, 256>, g, dim3(256), s, tm, b);
+    case 1: return launch1(combine_batch_kernel<DT, 1, 1024>, g, dim3(1024), s, tm, b);
+    case 2: return launch1(combine_batch_kernel<DT, 4, 1024>, g, dim3(1024), s, tm, b);
+    default: return launch1(combine_batch_kernel<DT, 16, 1024>, g, dim3(1024), s, tm, b);
     }
 }
 
-hipError_t launch_batch_pass_a(int dtype, int rc, const BatchArgs& b, int tiles, hipStream_t s)
+hipError_t launch_batch_pass_a(int dtype, int rc, const BatchArgs& b, int tiles, hipStream_t s, const KTiming& tm)
 {
-    switch (dtype) {
-    case PF_F64: launch_batch_pass_a_t<PF_F64>(rc, b, tiles, s); break;
-    case PF_F32: launch_batch_pass_a_t<PF_F32>(rc, b, tiles, s); break;
-    case PF_F16: launch_batch_pass_a_t<PF_F16>(rc, b, tiles, s); break;
-    case PF_BF16: launch_batch_pass_a_t<PF_BF16>(rc, b, tiles, s); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    PF_DISPATCH(dtype, launch_batch_pass_a_t<DT>(rc, b, tiles, s, tm))
 }
 
-hipError_t launch_batch_combine(int dtype, int cls, const BatchArgs& b, int count, hipStream_t s)
+hipError_t launch_batch_combine(int dtype, int cls, const BatchArgs& b, int count, hipStream_t s, const KTiming& tm)
 {
-    switch (dtype) {
-    case PF_F64: launch_batch_combine_t<PF_F64>(cls, b, count, s); break;
-    case PF_F32: launch_batch_combine_t<PF_F32>(cls, b, count, s); break;
-    case PF_F16: launch_batch_combine_t<PF_F16>(cls, b, count, s); break;
-    case PF_BF16: launch_batch_combine_t<PF_BF16>(cls, b, count, s); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    PF_DISPATCH(dtype, launch_batch_combine_t<DT>(cls, b, count, s, tm))
 }
 
-hipError_t launch_batch_pass_c(int dtype, const BatchArgs& b, int tiles, hipStream_t s)
+hipError_t launch_batch_pass_c(int dtype, const BatchArgs& b, int tiles, hipStream_t s, const KTiming& tm)
 {
-    const dim3 g((unsigned)tiles), blk(kBlock);
-    switch (dtype) {
-    case PF_F64: pass_c_batch_kernel<PF_F64><<<g, blk, 0, s>>>(b); break;
-    case PF_F32: pass_c_batch_kernel<PF_F32><<<g, blk, 0, s>>>(b); break;
-    case PF_F16: pass_c_batch_kernel<PF_F16><<<g, blk, 0, s>>>(b); break;
-    case PF_BF16: pass_c_batch_kernel<PF_BF16><<<g, blk, 0, s>>>(b); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    PF_DISPATCH(dtype, launch1(pass_c_batch_kernel<DT>, dim3((unsigned)tiles), dim3(kBlock), s, tm, b))
 }
 
 hipError_t launch_gather_est(const StepArgs* args, int n, double* out, hipStream_t s)

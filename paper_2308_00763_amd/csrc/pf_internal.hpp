@@ -9,9 +9,12 @@
 
 namespace pf {
 
-constexpr int kBlock = 256;        // threads per workgroup of every pass
+constexpr int kBlock = 256;        // threads per workgroup of pass C and the small kernels
 constexpr int kWaves = kBlock / 64;
-constexpr int kTile = 1024;        // particles per pass-A workgroup (4 per thread)
+constexpr int kTile = 1024;        // particles per tile (one pass-A and one pass-C workgroup)
+constexpr int kPPT = 4;            // particles per pass-A thread
+constexpr int kBlockA = kTile / kPPT;  // threads per pass-A workgroup
+constexpr int kWavesA = kBlockA / 64;
 constexpr int kPrefPitch = 134;    // LDS row-prefix table: u16 entries per window row (67 dwords)
 constexpr int kPrefBase = 3;       // entry of P[0] in a row (so P[4l+1..4l+4] is 4-byte aligned)
 constexpr int kPrefRows = 64;      // LDS row-prefix table: window rows
@@ -154,20 +157,29 @@ struct BatchArgs {
     int32_t entry0;     // combine: entry of the launch's first workgroup
 };
 
+// Optional timing of one launch: events stamped by the kernel's own dispatch
+// (start and end of its execution), no separate event records.
+struct KTiming {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
 // Host-side launchers (kernels.hip).  launch_step = launch_pass_a,
 // launch_combine, launch_pass_c on the same stream.
 hipError_t launch_step(int dtype, const StepArgs& a, hipStream_t s);
-hipError_t launch_pass_a(int dtype, const StepArgs& a, hipStream_t s);
-hipError_t launch_combine(int dtype, const StepArgs& a, hipStream_t s);
-hipError_t launch_pass_c(int dtype, const StepArgs& a, hipStream_t s);
+hipError_t launch_pass_a(int dtype, const StepArgs& a, hipStream_t s, const KTiming& tm = KTiming());
+hipError_t launch_combine(int dtype, const StepArgs& a, hipStream_t s, const KTiming& tm = KTiming());
+hipError_t launch_pass_c(int dtype, const StepArgs& a, hipStream_t s, const KTiming& tm = KTiming());
 hipError_t launch_fill(int dtype, const StepArgs& a, double vx, double vy, hipStream_t s);
 hipError_t launch_diag_weights(int dtype, const StepArgs& a, hipStream_t s);
 // Batched passes: pass A and pass C over `tiles` grid tiles, the combine over
 // `count` entries of one combine class starting at b.entry0.  rc: the common
 // disk radius of the batch when it is 5 or 8, else 0.
-hipError_t launch_batch_pass_a(int dtype, int rc, const BatchArgs& b, int tiles, hipStream_t s);
-hipError_t launch_batch_combine(int dtype, int cls, const BatchArgs& b, int count, hipStream_t s);
-hipError_t launch_batch_pass_c(int dtype, const BatchArgs& b, int tiles, hipStream_t s);
+hipError_t launch_batch_pass_a(int dtype, int rc, const BatchArgs& b, int tiles, hipStream_t s,
+                               const KTiming& tm = KTiming());
+hipError_t launch_batch_combine(int dtype, int cls, const BatchArgs& b, int count, hipStream_t s,
+                                const KTiming& tm = KTiming());
+hipError_t launch_batch_pass_c(int dtype, const BatchArgs& b, int tiles, hipStream_t s,
+                               const KTiming& tm = KTiming());
 // out[2k], out[2k+1] = estimate of filter k (device memory).
 hipError_t launch_gather_est(const StepArgs* args, int n, double* out, hipStream_t s);
 

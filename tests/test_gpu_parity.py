@@ -106,6 +106,44 @@ def test_f64_wide_cloud_uses_the_global_path():
         compare_f64_step(got, gs, est, ref, n)
 
 
+def _one_hot_tile_init(n, vid):
+    # the particles of tile 0 sit on the object (small integer offsets, so
+    # their weights differ), every other particle on background far from it:
+    # tile 0 takes every slot, far more than one merge round holds
+    cx, cy = vid.centres[1]
+    x = np.full(n, 20.0)
+    y = np.full(n, 20.0)
+    k = np.arange(1024)
+    x[:1024] = cx + (k % 5) - 2
+    y[:1024] = cy + (k // 5) % 3 - 1
+    return x, y
+
+
+def test_f64_one_tile_takes_every_slot():
+    w = pfsynth.WORKLOADS["disk128_n1000"]
+    vid = pfsynth.workload_video(w)
+    n = 8192 + 300
+    out = _run_teacher_forced("f64", n, vid, 5, 2, init=_one_hot_tile_init(n, vid),
+                              sigma=(0.0, 0.0), drift=(0.0, 0.0))
+    for got, gs, est, ref in out:
+        compare_f64_step(got, gs, est, ref, n)
+    got = out[0][0]
+    assert got["anc"].max() < 1024  # every slot went to tile 0
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+def test_reduced_modes_one_tile_takes_every_slot(dtype):
+    w = pfsynth.WORKLOADS["disk128_n1000"]
+    vid = pfsynth.workload_video(w)
+    n = 8192 + 300
+    out = _run_teacher_forced(dtype, n, vid, 5, 2, init=_one_hot_tile_init(n, vid),
+                              sigma=(0.0, 0.0), drift=(0.0, 0.0))
+    for got, gs, est, ref in out:
+        check_resample_consistency(got, gs, n)
+        assert tv(got["w"], ref["w"]) <= 1e-2
+    assert out[0][0]["anc"].max() < 1024
+
+
 def test_f64_uniform_frame_gives_uniform_weights():
     vid = pfsynth.moving_disk(64, 64, 3, 5, (32, 32), (0, 0), 0.0, seed=0)
     vid.frames[:] = 100
