@@ -178,6 +178,89 @@ def run_fleet(pf, torch, pfsynth, n_streams, side, frames, steps, warmup, dtype=
                 final_error_p99_px=float(np.percentile(err, 99)))
 
 
+def run_serving(pf, torch, pfsynth, seconds, warmup_s, rate=200.0, fps=30.0, hbm_gb=(6.0, 12.0)):
+    """Continuous batching of arriving streams: Poisson arrivals at `rate`
+    streams/s (PCG64(5)); per stream frames ~ U{20..500} at `fps`, side ~
+    U{64, 128, 256, 512, 1024}, N = round(exp(U(ln 1e3, ln 1e6))), FP16 or FP32
+    with probability 1/2, disk r = 5, noise sigma ~ U[2, 6], velocity in
+    {-3..3}^2 with specular bounce.  Frames come from a device-resident bank of
+    bouncing-disk videos (four per side, 560 frames) at a random start frame.
+    Latency is frame arrival to estimate ready, over frames arriving after
+    `warmup_s`."""
+    from paper_2308_00763_amd.serve import GpuPoolBackend, Scheduler, StreamRequest, plan_pool, slot_classes
+    sides = [64, 128, 256, 512, 1024]
+    bank_T = 560
+    rng = np.random.Generator(np.random.PCG64(5))
+    log("[bench] serving: drawing the video bank on the device")
+    bank = {}
+    for side in sides:
+        for j in range(4):
+            v = (int(rng.integers(-3, 4)), int(rng.integers(-3, 4)))
+            start = (int(rng.integers(5, side - 5)), int(rng.integers(5, side - 5)))
+            cen = pfsynth.trajectory(bank_T, start, v, side, side, 5, bounce=True)
+            sig = float(rng.uniform(2.0, 6.0))
+            bank[(side, j)] = (cen, pfsynth.render_video_torch(cen, side, 5, sig, "cuda:0",
+                                                                seed=7_000 + 10 * side + j))
+    caps = slot_classes(1000, 1_000_000)
+    pools = {"f16": plan_pool(int(hbm_gb[0] * 2**30), "f16", caps),
+             "f32": plan_pool(int(hbm_gb[1] * 2**30), "f32", caps)}
+    log(f"[bench] serving: pools {pools}")
+    be = GpuPoolBackend(pools)
+    sched = Scheduler(be, stall_timeout=5.0)
+    total = warmup_s + seconds
+    t = 0.0
+    sid = 0
+    t_base = time.perf_counter() + 1.0
+    while True:
+        t += float(rng.exponential(1.0 / rate))
+        if t > total:
+            break
+        frames = int(rng.integers(20, 501))
+        side = int(rng.choice(sides))
+        j = int(rng.integers(0, 4))
+        cen, vid = bank[(side, j)]
+        o = int(rng.integers(0, bank_T - frames + 1))
+        n = int(round(float(np.exp(rng.uniform(np.log(1e3), np.log(1e6))))))
+        dtype = "f16" if rng.random() < 0.5 else "f32"
+        d = cen[o + 1] - cen[o]
+        p = pf.make_params(n, side, side, dtype, x0=cen[o][0], y0=cen[o][1], drift=(d[0], d[1]),
+                           seed=5, stream_id=sid)
+        base, fst, pitch = int(vid.data_ptr()), int(vid.stride(0)), int(vid.stride(1))
+        sched.submit(StreamRequest(sid, t_base + t, p, frames, fps,
+                                   lambda i, b=base + o * fst, s=fst, q=pitch: (b + i * s, q)))
+        sid += 1
+    log(f"[bench] serving: {sid} streams over {total:.0f} s; running")
+    while time.perf_counter() < t_base:
+        time.sleep(0.01)
+    n_warm = None
+    last = time.perf_counter()
+    while not sched.idle() and time.perf_counter() < t_base + total + 30.0:
+        if sched.tick() == 0:
+            time.sleep(0.0002)
+        now = time.perf_counter()
+        if n_warm is None and now >= t_base + warmup_s:
+            n_warm = len(sched.latencies)
+            u_warm = sched.updates
+            t_warm = now
+        if now - last > 5.0:
+            log(f"[bench] serving: t={now - t_base:.0f} s, live {len(sched.live)}, queued {len(sched.queue)}, "
+                f"frames {len(sched.latencies)}")
+            last = now
+        if now >= t_base + total:
+            break
+    t_end = time.perf_counter()
+    summ = sched.summary(since_latency=n_warm or 0)
+    summ.update(workload=f"Poisson arrivals at {rate:g} streams/s for {seconds:g} s after {warmup_s:g} s warm-up; "
+                         f"per stream U{{20..500}} frames at {fps:g} fps, side U{{64..1024}}, "
+                         f"N log-uniform [1e3, 1e6], FP16 or FP32, r=5, bounce",
+                updates_per_s=(sched.updates - (u_warm if n_warm is not None else 0)) /
+                              max(t_end - (t_warm if n_warm is not None else t_base), 1e-9),
+                live_at_end=len(sched.live), queued_at_end=len(sched.queue),
+                pool_bytes=be.pool_bytes, streams_submitted=sid)
+    be.close()
+    return summ
+
+
 def cpu_baseline(w, vid, budget_s):
     """The FP64 oracle (sequential C, one thread) on the first steps of the
     same video at the same N, as many steps as fit in about budget_s."""
@@ -215,6 +298,8 @@ def main():
                     help="second single-filter workload timed in every mode ('none' to skip)")
     ap.add_argument("--fleet", type=int, default=4096, metavar="STREAMS",
                     help="streams of the batched fleet workload (0 to skip)")
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="measured seconds of the serving workload after a 10 s warm-up (0 to skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (five times), "
                          "to scale hardware byte counters")
@@ -337,6 +422,11 @@ def main():
         fr = run_fleet(pf, torch, pfsynth, args.fleet, 256, 50, 40, 5)
         log(f"[bench] fleet: {fr}")
         out["fleet"] = fr
+        torch.cuda.empty_cache()
+    if args.serve_seconds > 0:
+        sv = run_serving(pf, torch, pfsynth, args.serve_seconds, 10.0)
+        log(f"[bench] serving: {sv}")
+        out["serving"] = sv
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")

@@ -227,6 +227,15 @@ int pf_batch_estimates(pf_batch* b, double* out_2n);
  * not wait. */
 int pf_batch_estimates_async(pf_batch* b, double* d_out_2n);
 
+/* Re-initialise filter k of the batch in place with new parameters, as
+ * pf_init does (particles at (x0, y0), t = 0): a continuous-batching server
+ * hands the share of a finished stream to an arriving one.  The parameters
+ * must have the batch's dtype and fit the filter's workspace share (at most
+ * the bytes and tiles of the parameters it was created with).  Waits for the
+ * stream before and after.  Errors: PF_ERR_INVALID_ARG, PF_ERR_WORKSPACE (the
+ * share is too small; nothing changes), PF_ERR_HIP, PF_ERR_STATE. */
+int pf_batch_reinit(pf_batch* b, int32_t k, const pf_params* p);
+
 /* Handle of filter k (0 <= k < n) of the batch, owned by the batch and valid
  * until pf_batch_destroy.  pf_estimate, pf_estimate_async, pf_export,
  * pf_export_step, pf_import, pf_step (which steps that filter alone) and the

@@ -34,7 +34,7 @@ EXPORTS = ("pf_workspace_bytes", "pf_init", "pf_step", "pf_estimate", "pf_estima
            "pf_export", "pf_export_step", "pf_import", "pf_destroy", "pf_last_error",
            "pf_abi_version", "pf_profile_start", "pf_profile_read",
            "pf_batch_workspace_bytes", "pf_batch_init", "pf_batch_step", "pf_batch_estimates",
-           "pf_batch_estimates_async", "pf_batch_filter", "pf_batch_destroy")
+           "pf_batch_estimates_async", "pf_batch_reinit", "pf_batch_filter", "pf_batch_destroy")
 
 
 class PfError(RuntimeError):
@@ -98,6 +98,7 @@ def lib():
         L.pf_batch_step.argtypes = [vp, vp, vp, vp]
         L.pf_batch_estimates.argtypes = [vp, vp]
         L.pf_batch_estimates_async.argtypes = [vp, vp]
+        L.pf_batch_reinit.argtypes = [vp, ctypes.c_int32, P(pf_params)]
         L.pf_batch_filter.argtypes = [vp, ctypes.c_int32, P(vp)]
         L.pf_batch_destroy.argtypes = [vp]
         for name in EXPORTS:
@@ -245,6 +246,10 @@ def pf_batch_estimates_async(b, d_out: int):
     _check(lib().pf_batch_estimates_async(b, ctypes.c_void_p(d_out)))
 
 
+def pf_batch_reinit(b, k: int, p: pf_params):
+    _check(lib().pf_batch_reinit(b, int(k), ctypes.byref(p)))
+
+
 def pf_batch_filter(b, k: int):
     h = ctypes.c_void_p()
     _check(lib().pf_batch_filter(b, int(k), ctypes.byref(h)))
@@ -336,6 +341,10 @@ class Batch:
 
     def filter(self, k: int):
         return pf_batch_filter(self.handle, k)
+
+    def reinit(self, k: int, params: pf_params):
+        pf_batch_reinit(self.handle, k, params)
+        self.params[k] = params
 
     def export(self, k: int):
         p = self.params[k]

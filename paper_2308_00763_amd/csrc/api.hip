@@ -51,7 +51,10 @@ struct pf_batch {
     int32_t* d_tile_entry;
     double* d_est;
     std::vector<pf_filter*> f;
-    std::vector<int> cls;  // combine class of every filter
+    std::vector<int> cls;            // combine class of every filter
+    std::vector<size_t> slot_bytes;  // workspace share of every filter
+    std::vector<int> slot_tiles;     // tiles of every filter at creation (the most it may have)
+    std::vector<StepArgs> args_host; // host copy of the filters' StepArgs
     uint8_t* h_stage[kRing];
     hipEvent_t ev[kRing];
     bool ev_used[kRing];
@@ -603,7 +606,10 @@ int pf_batch_init(const pf_params* ps, int32_t n, void* d_workspace, size_t work
     b->rc = all5 ? 5 : all8 ? 8 : 0;
 
     std::vector<DevBlock> blocks((size_t)n);
-    std::vector<StepArgs> args((size_t)n);
+    std::vector<StepArgs>& args = b->args_host;
+    args.resize((size_t)n);
+    b->slot_bytes.resize((size_t)n);
+    b->slot_tiles.resize((size_t)n);
     std::vector<double> vx((size_t)n), vy((size_t)n);
     b->f.reserve((size_t)n);
     b->cls.resize((size_t)n);
@@ -618,6 +624,8 @@ int pf_batch_init(const pf_params* ps, int32_t n, void* d_workspace, size_t work
         h->owner = b;
         args[k] = h->args;
         b->cls[k] = comb_class(h->L.ntiles);
+        b->slot_bytes[k] = h->L.total;
+        b->slot_tiles[k] = h->L.ntiles;
     }
     b->stage_bytes = sizeof(BatchEntry) * (size_t)n + 4 * (size_t)bl.tiles;
     hipError_t e = hipSuccess;
@@ -756,6 +764,41 @@ int pf_batch_estimates(pf_batch* b, double* out_2n)
         e = hipMemcpyAsync(out_2n, b->d_est, 16 * (size_t)b->n, hipMemcpyDeviceToHost, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return batch_fail(b, e, "pf_batch_estimates");
+    return ok();
+}
+
+int pf_batch_reinit(pf_batch* b, int32_t k, const pf_params* p)
+{
+    if (int rc = batch_live(b)) return rc;
+    if (k < 0 || k >= b->n) return fail(PF_ERR_INVALID_ARG, "filter index %d outside [0, %d)", k, b->n);
+    if (int rc = check_params(p)) return rc;
+    if (p->dtype != b->dtype) return fail(PF_ERR_INVALID_ARG, "dtype %d differs from the batch's %d", p->dtype, b->dtype);
+    const Layout L = make_layout(*p);
+    if (L.total > b->slot_bytes[k] || L.ntiles > b->slot_tiles[k])
+        return fail(PF_ERR_WORKSPACE, "filter %d: %zu bytes / %d tiles needed, its share holds %zu / %d", k, L.total,
+                    L.ntiles, b->slot_bytes[k], b->slot_tiles[k]);
+    pf_filter* h = b->f[k];
+    hipError_t e = hipStreamSynchronize(b->stream);  // earlier work may still read the slot
+    if (e != hipSuccess) return batch_fail(b, e, "pf_batch_reinit");
+    profile_free(h);
+    DevBlock blk;
+    double vx, vy;
+    setup_filter(h, *p, h->ws, b->stream, &blk, &vx, &vy);
+    h->owner = b;
+    b->args_host[k] = h->args;
+    b->cls[k] = comb_class(L.ntiles);
+    b->map_valid = false;
+    bool all5 = true, all8 = true;
+    for (const pf_filter* g : b->f) {
+        all5 = all5 && g->p.disk_radius == 5;
+        all8 = all8 && g->p.disk_radius == 8;
+    }
+    b->rc = all5 ? 5 : all8 ? 8 : 0;
+    e = hipMemcpyAsync(b->d_args + k, &b->args_host[k], sizeof(StepArgs), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(at(h, h->L.blk), &blk, sizeof blk, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = launch_fill(b->dtype, h->args, vx, vy, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return batch_fail(b, e, "pf_batch_reinit");
     return ok();
 }
 

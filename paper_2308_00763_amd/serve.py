@@ -1,0 +1,327 @@
+"""Continuous batching of many tracking streams on one GPU.
+
+Streams arrive over time.  Each has its own video whose frames arrive at a
+fixed rate, its own particle count, precision mode and motion model, and runs
+the per-frame SIR step of the library (paper Sec. 2 and Sec. 4) on every frame.
+The server:
+
+  * admits a stream when a filter slot whose workspace share fits it is free
+    (slots are pre-sized from a device-memory budget, so admission is the HBM
+    budget check); otherwise the stream waits in a FIFO queue (first fit);
+  * rejects at submission a stream whose parameters the library refuses;
+  * at every tick steps, with one batched launch per slot pool, every admitted
+    stream that has a frame waiting (one frame per stream per tick, in order);
+  * measures per-frame latency: frame arrival to estimate ready;
+  * evicts a stream whose frames stop arriving for longer than a timeout, and
+    a stream whose step failed, reclaiming the slot either way.
+
+The scheduler is independent of the device: a backend provides slots, the
+batched step and estimates.  `GpuPoolBackend` keeps one `pf_batch` per
+precision whose members are re-initialised in place (pf_batch_reinit) for each
+admitted stream.  A HIP error in a batched step poisons that pool's batch, so
+every stream stepping in it fails; the scheduler then fails exactly those
+streams.
+"""
+from __future__ import annotations
+
+import heapq
+import math
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import (PF_F16, PF_F32, PF_F64, PF_BF16, Batch, PfError, make_params, pf_params,
+               pf_workspace_bytes)
+
+
+@dataclass
+class StreamRequest:
+    """One tracking stream.  Frame i (1 <= i < n_frames) arrives at
+    arrival + i / fps; frame 0 is the known starting position (params.x0, y0).
+    frame(i) returns the device frame (or host frame for a host backend), or
+    None while the source stalls."""
+    sid: int
+    arrival: float
+    params: pf_params
+    n_frames: int
+    fps: float
+    frame: object  # callable i -> frame or None
+    truth: object = None  # optional callable i -> (x, y)
+
+
+@dataclass
+class _Live:
+    req: StreamRequest
+    slot: object
+    admitted: float
+    next_frame: int = 1
+    estimates: list = field(default_factory=list)
+
+
+@dataclass
+class StreamResult:
+    sid: int
+    status: str          # "done", "rejected", "evicted", "failed"
+    reason: str = ""
+    admission_wait: float = float("nan")
+    frames_done: int = 0
+    estimates: list = field(default_factory=list)
+
+
+class Scheduler:
+    """Continuous-batching loop over a backend (see module docstring)."""
+
+    def __init__(self, backend, clock=time.perf_counter, stall_timeout: float = 1.0):
+        self.backend = backend
+        self.clock = clock
+        self.stall_timeout = stall_timeout
+        self.pending = []            # heap of (arrival, sid, request) not yet arrived
+        self.queue = deque()         # arrived requests waiting for a slot
+        self.live = {}               # sid -> _Live
+        self.results = {}            # sid -> StreamResult
+        self.latencies = []          # per processed frame: ready - arrival (seconds)
+        self.updates = 0             # particle updates done
+        self.ticks = 0
+        self.step_seconds = 0.0
+
+    # -- submission ---------------------------------------------------------
+    def submit(self, req: StreamRequest):
+        reason = self.backend.validate(req.params)
+        if reason:
+            self.results[req.sid] = StreamResult(req.sid, "rejected", reason)
+            return False
+        heapq.heappush(self.pending, (req.arrival, req.sid, req))
+        return True
+
+    # -- one tick -----------------------------------------------------------
+    def _arrivals(self, now):
+        while self.pending and self.pending[0][0] <= now:
+            _, _, req = heapq.heappop(self.pending)
+            self.queue.append(req)
+
+    def _admit(self, now):
+        waiting = deque()
+        while self.queue:
+            req = self.queue.popleft()
+            try:
+                slot = self.backend.try_admit(req)
+            except PfError as e:  # the pool cannot take streams any more
+                self.results[req.sid] = StreamResult(req.sid, "failed", str(e), now - req.arrival)
+                continue
+            if slot is None:
+                waiting.append(req)
+                continue
+            self.live[req.sid] = _Live(req, slot, now)
+        self.queue = waiting
+
+    def _finish(self, lv: _Live, status: str, reason: str = ""):
+        self.backend.release(lv.slot)
+        del self.live[lv.req.sid]
+        self.results[lv.req.sid] = StreamResult(
+            lv.req.sid, status, reason, lv.admitted - lv.req.arrival, lv.next_frame - 1, lv.estimates)
+
+    def tick(self):
+        """Admit, step every stream with a waiting frame once, record
+        latencies, evict stalled streams.  Returns the number of frames
+        stepped."""
+        now = self.clock()
+        self._arrivals(now)
+        self._admit(now)
+        work = []
+        for lv in list(self.live.values()):
+            r = lv.req
+            i = lv.next_frame
+            if i >= r.n_frames:
+                self._finish(lv, "done")
+                continue
+            t_arr = r.arrival + i / r.fps
+            if t_arr > now:
+                continue
+            fr = r.frame(i)
+            if fr is None:  # the source stalls: evict once it is late by the timeout
+                if now - t_arr > self.stall_timeout:
+                    self._finish(lv, "evicted", f"frame {i} late by more than {self.stall_timeout} s")
+                continue
+            work.append((lv, fr, t_arr))
+        if not work:
+            return 0
+        t0 = self.clock()
+        failed = self.backend.step([(lv.slot, fr) for lv, fr, _ in work])
+        ests = self.backend.estimates([lv.slot for lv, _, _ in work])
+        done = self.clock()
+        self.step_seconds += done - t0
+        self.ticks += 1
+        for (lv, _, t_arr), est in zip(work, ests):
+            if lv.slot in failed:
+                self._finish(lv, "failed", failed[lv.slot])
+                continue
+            self.latencies.append(done - t_arr)
+            self.updates += lv.req.params.n_particles
+            lv.estimates.append(est)
+            lv.next_frame += 1
+            if lv.next_frame >= lv.req.n_frames:
+                self._finish(lv, "done")
+        return len(work)
+
+    def idle(self):
+        return not self.pending and not self.queue and not self.live
+
+    def run(self, until: float = math.inf, sleep=time.sleep, poll: float = 0.0005):
+        """Tick until every submitted stream has finished or the clock passes
+        `until`."""
+        while not self.idle() and self.clock() < until:
+            if self.tick() == 0:
+                sleep(poll)
+        return self.summary()
+
+    def summary(self, since_latency: int = 0):
+        lat = np.array(self.latencies[since_latency:])
+        st = {}
+        for r in self.results.values():
+            st[r.status] = st.get(r.status, 0) + 1
+        waits = np.array([r.admission_wait for r in self.results.values()
+                          if r.status in ("done", "evicted", "failed")])
+        return dict(frames=int(lat.size),
+                    latency_p50_ms=float(np.percentile(lat, 50) * 1e3) if lat.size else None,
+                    latency_p99_ms=float(np.percentile(lat, 99) * 1e3) if lat.size else None,
+                    admission_wait_p50_ms=float(np.percentile(waits, 50) * 1e3) if waits.size else None,
+                    admission_wait_p99_ms=float(np.percentile(waits, 99) * 1e3) if waits.size else None,
+                    streams=st, ticks=self.ticks, particle_updates=self.updates,
+                    hbm_high_water_bytes=self.backend.high_water())
+
+
+# ---------------------------------------------------------------------------
+# GPU backend: one pf_batch per precision, slots in particle-count classes.
+
+def slot_classes(n_min: int, n_max: int):
+    """Particle capacities of the slot classes: powers of two covering
+    [n_min, n_max]."""
+    lo = 1 << max(0, math.ceil(math.log2(n_min)))
+    caps = []
+    c = lo
+    while True:
+        caps.append(c)
+        if c >= n_max:
+            break
+        c *= 2
+    return caps
+
+
+def plan_pool(budget_bytes: int, dtype: str, caps, weights=None):
+    """Slots per class for one precision so that the pool's workspace fits
+    `budget_bytes`: counts proportional to `weights` (default equal)."""
+    w = np.ones(len(caps)) if weights is None else np.asarray(weights, dtype=float)
+    per = [pf_workspace_bytes(make_params(c, 64, 64, dtype)) for c in caps]
+    scale = budget_bytes / float(np.dot(w, per))
+    counts = [max(1, int(scale * wi)) for wi in w]
+    return dict(zip(caps, counts))
+
+
+class GpuPoolBackend:
+    """Slot pools on one GPU: for every precision a pf_batch whose members are
+    created at the class capacities and re-initialised for each stream."""
+
+    def __init__(self, pools: dict, device="cuda:0", stream=None):
+        """pools: {dtype name: {capacity: slots}}."""
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.batches = {}
+        self.free = {}
+        self.slot_cap = {}
+        self.in_use_bytes = 0
+        self.high = 0
+        self.slot_bytes = {}
+        for dt, classes in pools.items():
+            params, caps = [], []
+            for cap, count in sorted(classes.items()):
+                for _ in range(count):
+                    params.append(make_params(cap, 64, 64, dt))
+                    caps.append(cap)
+            b = Batch(params, device=device, stream=self.stream)
+            self.batches[dt] = b
+            n = len(params)
+            self.free[dt] = {}
+            for k, cap in enumerate(caps):
+                self.free[dt].setdefault(cap, []).append(k)
+                self.slot_cap[(dt, k)] = cap
+                self.slot_bytes[(dt, k)] = pf_workspace_bytes(params[k])
+            for cap in self.free[dt]:
+                self.free[dt][cap].reverse()
+            b._ptrs = np.zeros(n, dtype=np.uint64)
+            b._pitch = np.zeros(n, dtype=np.int64)
+            b._active = np.zeros(n, dtype=np.uint8)
+        self.pool_bytes = sum(b.workspace.numel() for b in self.batches.values())
+
+    @staticmethod
+    def _dtype_name(code):
+        return {PF_F64: "f64", PF_F32: "f32", PF_F16: "f16", PF_BF16: "bf16"}[code]
+
+    def validate(self, params):
+        try:
+            pf_workspace_bytes(params)
+        except PfError as e:
+            return str(e)
+        dt = self._dtype_name(params.dtype)
+        if dt not in self.batches:
+            return f"no pool for dtype {dt}"
+        if params.n_particles > max(self.free[dt]):
+            return f"n_particles {params.n_particles} above the largest slot class"
+        return ""
+
+    def try_admit(self, req):
+        dt = self._dtype_name(req.params.dtype)
+        for cap in sorted(self.free[dt]):
+            if cap >= req.params.n_particles and self.free[dt][cap]:
+                k = self.free[dt][cap].pop()
+                self.batches[dt].reinit(k, req.params)
+                self.in_use_bytes += self.slot_bytes[(dt, k)]
+                self.high = max(self.high, self.in_use_bytes)
+                return (dt, k)
+        return None
+
+    def release(self, slot):
+        dt, k = slot
+        self.free[dt][self.slot_cap[slot]].append(k)
+        self.in_use_bytes -= self.slot_bytes[slot]
+
+    def step(self, items):
+        """items: [(slot, frame)] with frame an (H, W) uint8 device tensor or a
+        (device pointer, row pitch) pair; one pf_batch_step per pool.  Returns
+        {slot: error text} for the streams whose step failed."""
+        by = {}
+        for slot, fr in items:
+            by.setdefault(slot[0], []).append((slot[1], fr))
+        failed = {}
+        for dt, lst in by.items():
+            b = self.batches[dt]
+            b._active[:] = 0
+            for k, fr in lst:
+                if isinstance(fr, tuple):  # (device pointer, row pitch)
+                    b._ptrs[k], b._pitch[k] = fr
+                else:                      # (H, W) uint8 tensor
+                    b._ptrs[k] = fr.data_ptr()
+                    b._pitch[k] = fr.stride(0)
+                b._active[k] = 1
+            try:
+                b.step_ptrs(b._ptrs, b._pitch, b._active)
+            except PfError as e:
+                for k, _ in lst:
+                    failed[(dt, k)] = str(e)
+        return failed
+
+    def estimates(self, slots):
+        out = {}
+        for dt in {s[0] for s in slots}:
+            out[dt] = self.batches[dt].estimates()
+        return [tuple(out[dt][k]) for dt, k in slots]
+
+    def high_water(self):
+        return self.high
+
+    def close(self):
+        for b in self.batches.values():
+            b.close()

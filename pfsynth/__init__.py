@@ -194,3 +194,26 @@ def render_fleet_torch(streams, t: int, side: int, radius: int, device, seed: in
     img = torch.where(dx2 + dy2 < float(radius * radius), float(fg), float(bg))
     img = img + torch.randn((n, side, side), generator=g, device=device) * sig.view(n, 1, 1)
     return torch.clamp(torch.floor(img + 0.5), 0, 255).to(torch.uint8)
+
+
+def render_video_torch(centres, side: int, radius: int, noise_sigma: float, device, seed: int,
+                       fg: int = 228, bg: int = 100, chunk: int = 32):
+    """A (T, side, side) uint8 video drawn on `device` for the given integer
+    centres (T, 2): the scene and noise model of `render`, with the noise
+    from torch's generator seeded with `seed`."""
+    import torch
+    T = len(centres)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    out = torch.empty((T, side, side), dtype=torch.uint8, device=device)
+    c = torch.as_tensor(np.asarray(centres, dtype=np.float32), device=device)
+    ax = torch.arange(side, dtype=torch.float32, device=device)
+    for t0 in range(0, T, chunk):
+        cc = c[t0:t0 + chunk]
+        m = cc.shape[0]
+        dx2 = (ax.view(1, 1, side) - cc[:, 0].view(m, 1, 1)) ** 2
+        dy2 = (ax.view(1, side, 1) - cc[:, 1].view(m, 1, 1)) ** 2
+        img = torch.where(dx2 + dy2 < float(radius * radius), float(fg), float(bg))
+        img = img + torch.randn((m, side, side), generator=g, device=device) * float(noise_sigma)
+        out[t0:t0 + m] = torch.clamp(torch.floor(img + 0.5), 0, 255).to(torch.uint8)
+    return out
