@@ -261,6 +261,27 @@ def run_serving(pf, torch, pfsynth, seconds, warmup_s, rate=200.0, fps=30.0, hbm
     return summ
 
 
+def run_accuracy(pf, torch, pfsynth, modes):
+    """The paper's accuracy video (512x512, 100 frames, bounce off y = 0,
+    128 particles): per mode the RMS distance of the free-running estimates to
+    the ground truth, the largest distance to the FP64 estimates, and the
+    share of frames whose rounded estimate equals the FP64 one."""
+    w = pfsynth.WORKLOADS["bounce512_n128"]
+    vid = pfsynth.workload_video(w, bounce=True)
+    fr = torch.from_numpy(vid.frames).to("cuda:0")
+    tr = {dt: track(pf, fr, vid.centres, w, dt, w.frames - 1) for dt in modes}
+    res = {}
+    for dt, e in tr.items():
+        r = dict(rms_vs_truth_px=float(np.sqrt(np.mean(np.sum((e - vid.centres) ** 2, axis=1)))),
+                 max_vs_truth_px=float(np.max(np.hypot(*(e - vid.centres).T))))
+        if "f64" in tr:
+            r["max_vs_f64_px"] = float(np.max(np.hypot(*(e - tr["f64"]).T)))
+            r["rounded_equal_f64"] = float(np.mean(np.all(np.rint(e) == np.rint(tr["f64"]), axis=1)))
+        res[dt] = r
+    return dict(workload=f"{w.name}: {w.width}x{w.height}, {w.frames} frames, bounce off y = 0 at frame 47, "
+                         f"N={w.n_particles}", modes=res)
+
+
 def cpu_baseline(w, vid, budget_s):
     """The FP64 oracle (sequential C, one thread) on the first steps of the
     same video at the same N, as many steps as fit in about budget_s."""
@@ -398,6 +419,9 @@ def main():
         out["speedup_f16_vs_f64"] = res["f64"]["seconds"] / res.get("f16", res["f64"])["seconds"]
     if "f32" in res and "f16" in res:
         out["speedup_f16_vs_f32"] = res["f32"]["seconds"] / res["f16"]["seconds"]
+    if not args.no_track:
+        out["accuracy"] = run_accuracy(pf, torch, pfsynth, modes)
+        log(f"[bench] accuracy: {out['accuracy']}")
     if args.large and args.large != "none":
         wl = pfsynth.WORKLOADS[args.large]
         log(f"[bench] generating {wl.name}: {wl.frames} frames {wl.width}x{wl.height}")
