@@ -79,7 +79,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_mode(pf, torch, frames_dev, centres, w, dtype, steps, warmup, profile):
+def run_mode(pf, torch, frames_dev, centres, w, dtype, steps, warmup, profile, **variant):
     """Time `steps` SIR steps after `warmup` (a fresh filter each call).
 
     The timed loop calls the C ABI directly with precomputed frame pointers,
@@ -92,7 +92,7 @@ def run_mode(pf, torch, frames_dev, centres, w, dtype, steps, warmup, profile):
     assert warmup + steps <= T - 1, "the timed steps must fit in one pass over the video"
     x0, y0 = centres[0]
     p = pf.make_params(w.n_particles, w.width, w.height, dtype, radius=w.radius, x0=x0, y0=y0,
-                       drift=w.drift, sigma=w.sigma, seed=w.filter_seed)
+                       drift=w.drift, sigma=w.sigma, seed=w.filter_seed, **variant)
     f = pf.Filter(p)
     lib = pf.lib()
     pitch = int(frames_dev.stride(1))
@@ -261,6 +261,41 @@ def run_serving(pf, torch, pfsynth, seconds, warmup_s, rate=200.0, fps=30.0, hbm
     return summ
 
 
+ABLATION = [
+    ("optimised", {}),
+    ("naive likelihood (every disk pixel from the frame)", dict(naive_likelihood=True)),
+    ("naive resampling, 64 threads", dict(naive_resample=True, threads_c=64)),
+    ("naive resampling, 128 threads", dict(naive_resample=True, threads_c=128)),
+    ("naive resampling, 256 threads", dict(naive_resample=True, threads_c=256)),
+    ("naive resampling, 512 threads", dict(naive_resample=True, threads_c=512)),
+    ("naive resampling, 1024 threads", dict(naive_resample=True, threads_c=1024)),
+    ("naive likelihood + resampling, 128 threads",
+     dict(naive_likelihood=True, naive_resample=True, threads_c=128)),
+    ("pass A 128 threads (8 particles each)", dict(threads_a=128)),
+    ("pass A 512 threads (2 particles each)", dict(threads_a=512)),
+    ("pass C 64 threads", dict(threads_c=64)),
+    ("pass C 128 threads", dict(threads_c=128)),
+    ("pass C 512 threads", dict(threads_c=512)),
+    ("pass C 1024 threads", dict(threads_c=1024)),
+]
+
+
+def run_ablation(pf, torch, frames_dev, centres, w, steps, warmup, dtypes=("f16", "f64")):
+    """The straightforward step against the optimised one, and workgroup
+    sizes, at the headline workload: ms per step and per-pass times."""
+    res = {}
+    for dt in dtypes:
+        rows = {}
+        for name, var in ABLATION:
+            secs, _ = run_mode(pf, torch, frames_dev, centres, w, dt, steps, warmup, False, **var)
+            _, prof = run_mode(pf, torch, frames_dev, centres, w, dt, steps, warmup, True, **var)
+            a_ms, m_ms, c_ms, n = prof
+            rows[name] = dict(ms_per_step=1e3 * secs / steps, pass_a_us=1e3 * a_ms / n,
+                              combine_us=1e3 * m_ms / n, resample_us=1e3 * c_ms / n)
+        res[dt] = rows
+    return res
+
+
 def run_accuracy(pf, torch, pfsynth, modes):
     """The paper's accuracy video (512x512, 100 frames, bounce off y = 0,
     128 particles): per mode the RMS distance of the free-running estimates to
@@ -319,6 +354,8 @@ def main():
                     help="second single-filter workload timed in every mode ('none' to skip)")
     ap.add_argument("--fleet", type=int, default=4096, metavar="STREAMS",
                     help="streams of the batched fleet workload (0 to skip)")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the naive-vs-optimised and workgroup-size runs")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="measured seconds of the serving workload after a 10 s warm-up (0 to skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -419,6 +456,10 @@ def main():
         out["speedup_f16_vs_f64"] = res["f64"]["seconds"] / res.get("f16", res["f64"])["seconds"]
     if "f32" in res and "f16" in res:
         out["speedup_f16_vs_f32"] = res["f32"]["seconds"] / res["f16"]["seconds"]
+    if not args.no_ablation:
+        out["ablation"] = run_ablation(pf, torch, frames_dev, vid.centres, w, min(args.steps, 40),
+                                       args.warmup)
+        log(f"[bench] ablation: {json.dumps(out['ablation'])}")
     if not args.no_track:
         out["accuracy"] = run_accuracy(pf, torch, pfsynth, modes)
         log(f"[bench] accuracy: {out['accuracy']}")

@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define PF_ABI_VERSION 2
+#define PF_ABI_VERSION 3
 
 typedef enum pf_status {
     PF_OK = 0,
@@ -71,6 +71,43 @@ typedef enum pf_lik_norm { PF_LIK_MEAN = 0, PF_LIK_SUM = 1 } pf_lik_norm;
  * resampling, ancestors, disk sums) so that pf_export / pf_export_step can
  * return them.  Costs extra workspace and memory traffic; off by default. */
 #define PF_FLAG_DIAGNOSTICS 1u
+
+/* Implementation variants, for measuring what the optimised step gains over
+ * the straightforward one (paper Sec. 5: naive and optimised half-precision
+ * kernels, and the threads-per-block study).  Every variant computes the
+ * same step; results agree with the default up to the rounding of the
+ * distribution.  Not accepted by the batch calls.
+ *   PF_FLAG_NAIVE_LIKELIHOOD -- disk sums read every disk pixel from the frame
+ *       (no LDS row-prefix table).
+ *   PF_FLAG_NAIVE_RESAMPLE   -- the normalised cumulative distribution is
+ *       written out (one division per particle; double in PF_F64, float
+ *       otherwise), then one thread per slot binary-searches it, instead of
+ *       the tile-wise merge.  Costs N more elements of workspace.
+ *   Threads per workgroup, as a field value v in 1..5 selecting 2^(v+5)
+ *   threads (64, 128, 256, 512, 1024; 0 = the default 256):
+ *     bits 8-11 (PF_THREADS_A_SHIFT)  pass A, 1024 particles per workgroup:
+ *                                     128, 256 or 512 threads;
+ *     bits 12-15 (PF_THREADS_C_SHIFT) pass C or the naive resampler: 64-1024. */
+#define PF_FLAG_NAIVE_LIKELIHOOD 2u
+#define PF_FLAG_NAIVE_RESAMPLE 4u
+#define PF_THREADS_A_SHIFT 8
+#define PF_THREADS_C_SHIFT 12
+
+/* Metropolis resampling (Murray, Lee & Jacob, 2016; among the scan-free
+ * resamplers of the paper's related work, Sec. 3) instead of systematic
+ * resampling: slot j runs a chain of B steps that starts at particle j; each
+ * step proposes a particle i uniformly and moves there when
+ * u <= w_i / w_k = exp(L_i - L_k) (always when L_i >= L_k).  No maximum,
+ * normaliser or cumulative distribution enters the resampling (the estimate
+ * still uses them); the result is biased for finite B, the bias falling
+ * geometrically with B.  Random numbers: steps 2m and 2m + 1 of slot j at
+ * step t use counter (j, t, stream_id, 2 + m), words 0-1 and 2-3; the first
+ * of each pair picks i = floor(word * N / 2^32), the second gives u =
+ * (word + 1/2) 2^-32 (the top 24 bits in the reduced modes).  B in bits 18-25
+ * (PF_METROPOLIS_STEPS_SHIFT; 0 = 32).  Costs 4 bytes per particle of
+ * workspace.  Not accepted by the batch calls. */
+#define PF_FLAG_METROPOLIS (1u << 16)
+#define PF_METROPOLIS_STEPS_SHIFT 18
 
 typedef struct pf_params {
     uint32_t struct_size;  /* must be sizeof(pf_params) */

@@ -91,6 +91,8 @@ def lib():
                               dp, ip, dp]
         L.or_run.argtypes = [pp, u8p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
                              ctypes.c_double, dp, dp, dp]
+        L.or_metropolis.argtypes = [ctypes.c_int64, dp, ctypes.c_int32, ctypes.c_uint64,
+                                    ctypes.c_uint32, ctypes.c_uint32, ip, dp]
         _lib = L
     return _lib
 
@@ -234,3 +236,15 @@ def run(p: Params, video, x0, y0):
     lib().or_run(ctypes.byref(p), _ptr(video, ctypes.c_uint8), W, T, float(x0), float(y0),
                  _ptr(x, ctypes.c_double), _ptr(y, ctypes.c_double), _ptr(est, ctypes.c_double))
     return est.reshape(T, 2), x, y
+
+
+def metropolis(L, B: int, seed: int, stream_id: int, t: int):
+    """Metropolis resampling of log-likelihoods L with B steps per slot
+    (pf_oracle.c, or_metropolis).  Returns (ancestors, margins)."""
+    L = np.ascontiguousarray(L, dtype=np.float64)
+    n = L.size
+    anc = np.zeros(n, dtype=np.int32)
+    margin = np.zeros(n)
+    lib().or_metropolis(n, _ptr(L, ctypes.c_double), int(B), int(seed), int(stream_id), int(t),
+                        _ptr(anc, ctypes.c_int32), _ptr(margin, ctypes.c_double))
+    return anc, margin

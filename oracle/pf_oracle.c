@@ -285,6 +285,50 @@ void or_reweight_resample(int64_t n, const double *L, const double *w_prev,
     free(P);
 }
 
+/* ------------------------------------------------------------------ */
+/* Metropolis resampling (Murray, Lee & Jacob, "Parallel resampling in the
+ * particle filter", J. Comput. Graph. Stat. 2016), the scan-free resampler
+ * among the related work the paper cites (Sec. 3): slot j runs its own
+ * Metropolis chain of B steps over the particle indices, whose stationary
+ * distribution is the normalised weights.  The chain starts at k = j; each
+ * step proposes a particle i uniformly and moves there with probability
+ * min(1, w_i / w_k) = min(1, exp(L_i - L_k)).  Only ratios of weights enter:
+ * no maximum, sum or cumulative distribution.
+ * Random numbers of slot j at step t (this build's layout): steps b = 2m and
+ * 2m + 1 share ctr = (j, t, stream_id, 2 + m); step 2m uses words 0 and 1,
+ * step 2m + 1 words 2 and 3; the first picks i = floor(word * n / 2^32), the
+ * second gives u = (word + 1/2) 2^-32 in (0, 1), and the move is taken when
+ * L_i >= L_k or u <= exp(L_i - L_k).
+ * margin (optional, length n): for slot j the smallest |u - exp(L_i - L_k)|
+ * over its chain's comparisons with L_i < L_k (1 if none), so a comparison
+ * with another implementation can tell the decisions rounding could flip. */
+void or_metropolis(int64_t n, const double *L, int32_t B, uint64_t seed, uint32_t stream_id,
+                   uint32_t t, int32_t *anc, double *margin)
+{
+    for (int64_t j = 0; j < n; ++j) {
+        int64_t k = j;
+        double mg = 1.0;
+        uint32_t w[4] = {0, 0, 0, 0};
+        for (int32_t b = 0; b < B; ++b) {
+            if (b % 2 == 0) or_philox_words(seed, (uint32_t)j, t, stream_id, 2u + (uint32_t)(b / 2), w);
+            uint32_t wi = (b % 2 == 0) ? w[0] : w[2];
+            uint32_t wu = (b % 2 == 0) ? w[1] : w[3];
+            int64_t i = (int64_t)(((uint64_t)wi * (uint64_t)n) >> 32);
+            if (L[i] >= L[k]) {
+                k = i;
+                continue;
+            }
+            double ratio = exp(L[i] - L[k]);
+            double u = ((double)wu + 0.5) * 0x1.0p-32;
+            double d = fabs(u - ratio);
+            if (d < mg) mg = d;
+            if (u <= ratio) k = i;
+        }
+        anc[j] = (int32_t)k;
+        if (margin) margin[j] = mg;
+    }
+}
+
 /* One whole SIR step t (t = 1, 2, ...) on frame `frame`.
  * In:  x, y -- the particles after the previous resampling (all weights 1/n).
  * Out: x, y -- the particles after this step's resampling;

@@ -26,8 +26,14 @@ PF_F64, PF_F32, PF_F16, PF_BF16 = 0, 1, 2, 3
 DTYPES = {"f64": PF_F64, "f32": PF_F32, "f16": PF_F16, "bf16": PF_BF16}
 PF_LIK_MEAN, PF_LIK_SUM = 0, 1
 PF_FLAG_DIAGNOSTICS = 1
+PF_FLAG_NAIVE_LIKELIHOOD = 2
+PF_FLAG_NAIVE_RESAMPLE = 4
+PF_THREADS_A_SHIFT = 8
+PF_THREADS_C_SHIFT = 12
+PF_FLAG_METROPOLIS = 1 << 16
+PF_METROPOLIS_STEPS_SHIFT = 18
 
-PF_ABI_VERSION = 2
+PF_ABI_VERSION = 3
 
 # Every function the C header declares (checked against include/pf.h by the tests).
 EXPORTS = ("pf_workspace_bytes", "pf_init", "pf_step", "pf_estimate", "pf_estimate_async",
@@ -113,14 +119,35 @@ def _check(rc: int):
         raise PfError(rc, lib().pf_last_error().decode())
 
 
+def threads_field(threads: int) -> int:
+    """Field value of a threads-per-workgroup flag (0 for the default 256)."""
+    if threads in (0, 256):
+        return 0
+    v = int(threads).bit_length() - 6
+    if threads <= 0 or threads != 1 << (v + 5):
+        raise ValueError(f"threads per workgroup must be a power of two in [64, 1024], got {threads}")
+    return v
+
+
 def make_params(n, width, height, dtype="f64", radius=5, x0=0.0, y0=0.0, drift=(1.0, -2.0),
                 sigma=(5.0, 2.0), seed=0, stream_id=0, fg=228, bg=100, kappa=50.0,
-                lik_norm=PF_LIK_MEAN, diagnostics=False) -> pf_params:
+                lik_norm=PF_LIK_MEAN, diagnostics=False, naive_likelihood=False,
+                naive_resample=False, threads_a=256, threads_c=256,
+                metropolis_steps=0) -> pf_params:
     dt = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+    if not 0 <= int(metropolis_steps) <= 255:
+        raise ValueError(f"metropolis_steps must be in [0, 255], got {metropolis_steps}")
+    flags = ((PF_FLAG_DIAGNOSTICS if diagnostics else 0)
+             | (PF_FLAG_NAIVE_LIKELIHOOD if naive_likelihood else 0)
+             | (PF_FLAG_NAIVE_RESAMPLE if naive_resample else 0)
+             | (threads_field(threads_a) << PF_THREADS_A_SHIFT)
+             | (threads_field(threads_c) << PF_THREADS_C_SHIFT)
+             | ((PF_FLAG_METROPOLIS | (int(metropolis_steps) << PF_METROPOLIS_STEPS_SHIFT))
+                if metropolis_steps else 0))
     return pf_params(ctypes.sizeof(pf_params), dt, int(n), int(width), int(height), int(radius),
                      int(fg), int(bg), int(lik_norm), float(kappa), float(x0), float(y0),
                      float(drift[0]), float(drift[1]), float(sigma[0]), float(sigma[1]),
-                     int(seed) & (2**64 - 1), int(stream_id), PF_FLAG_DIAGNOSTICS if diagnostics else 0)
+                     int(seed) & (2**64 - 1), int(stream_id), flags)
 
 
 # ---------------------------------------------------------------------------

@@ -125,9 +125,21 @@ int check_params(const pf_params* p)
     for (double d : v)
         if (!isfinite(d) || fabs(d) > 1e6) return fail(PF_ERR_INVALID_ARG, "positions/drift/sigma must be finite, |v| <= 1e6");
     if (p->sigma_x < 0 || p->sigma_y < 0) return fail(PF_ERR_INVALID_ARG, "sigma must be >= 0");
-    if (p->flags & ~PF_FLAG_DIAGNOSTICS) return fail(PF_ERR_INVALID_ARG, "unknown flags 0x%x", p->flags);
+    const uint32_t known = PF_FLAG_DIAGNOSTICS | PF_FLAG_NAIVE_LIKELIHOOD | PF_FLAG_NAIVE_RESAMPLE |
+                           (0xFu << PF_THREADS_A_SHIFT) | (0xFu << PF_THREADS_C_SHIFT) | PF_FLAG_METROPOLIS |
+                           (0xFFu << PF_METROPOLIS_STEPS_SHIFT);
+    if (p->flags & ~known) return fail(PF_ERR_INVALID_ARG, "unknown flags 0x%x", p->flags);
+    const uint32_t ta = (p->flags >> PF_THREADS_A_SHIFT) & 0xF, tc = (p->flags >> PF_THREADS_C_SHIFT) & 0xF;
+    if (ta != 0 && (ta < 2 || ta > 4)) return fail(PF_ERR_INVALID_ARG, "pass A threads field %u outside {2, 3, 4}", ta);
+    if (tc > 5) return fail(PF_ERR_INVALID_ARG, "pass C threads field %u outside [0, 5]", tc);
+    if ((p->flags & PF_FLAG_METROPOLIS) && (p->flags & PF_FLAG_NAIVE_RESAMPLE))
+        return fail(PF_ERR_INVALID_ARG, "Metropolis and the naive systematic resampler exclude each other");
+    if (!(p->flags & PF_FLAG_METROPOLIS) && ((p->flags >> PF_METROPOLIS_STEPS_SHIFT) & 0xFFu))
+        return fail(PF_ERR_INVALID_ARG, "Metropolis steps given without PF_FLAG_METROPOLIS");
     return PF_OK;
 }
+
+int threads_of(uint32_t field) { return field == 0 ? 256 : 1 << (field + 5); }
 
 int live(pf_filter* h)
 {
@@ -228,6 +240,19 @@ void setup_filter(pf_filter* h, const pf_params& pr, uint8_t* ws, hipStream_t st
         a.dg_s = nullptr;
         a.dg_w = nullptr;
         a.dg_anc = nullptr;
+    }
+    a.naive_lik = (p->flags & PF_FLAG_NAIVE_LIKELIHOOD) ? 1 : 0;
+    a.naive_res = (p->flags & PF_FLAG_NAIVE_RESAMPLE) ? 1 : 0;
+    a.threads_a = threads_of((p->flags >> PF_THREADS_A_SHIFT) & 0xF);
+    a.threads_c = threads_of((p->flags >> PF_THREADS_C_SHIFT) & 0xF);
+    a.cdf = a.naive_res ? at(h, L.cdf) : nullptr;
+    if (p->flags & PF_FLAG_METROPOLIS) {
+        const int steps = (int)((p->flags >> PF_METROPOLIS_STEPS_SHIFT) & 0xFFu);
+        a.mh_steps = steps == 0 ? 32 : steps;
+        a.s_all = (int32_t*)at(h, L.s_all);
+    } else {
+        a.mh_steps = 0;
+        a.s_all = nullptr;
     }
 
     DevBlock b{};
@@ -523,6 +548,8 @@ static int check_batch(const pf_params* ps, int32_t n, BatchLayout* bl, std::vec
     for (int32_t k = 0; k < n; ++k) {
         if (check_params(&ps[k])) return fail(PF_ERR_INVALID_ARG, "filter %d: %s", k, g_err.c_str());
         if (ps[k].dtype != ps[0].dtype) return fail(PF_ERR_INVALID_ARG, "filter %d: dtype differs from filter 0", k);
+        if (ps[k].flags & ~PF_FLAG_DIAGNOSTICS)
+            return fail(PF_ERR_INVALID_ARG, "filter %d: implementation variants are not batched", k);
         const Layout L = make_layout(ps[k]);
         if (foff) (*foff)[k] = fbytes;
         fbytes += L.total;
@@ -773,6 +800,7 @@ int pf_batch_reinit(pf_batch* b, int32_t k, const pf_params* p)
     if (k < 0 || k >= b->n) return fail(PF_ERR_INVALID_ARG, "filter index %d outside [0, %d)", k, b->n);
     if (int rc = check_params(p)) return rc;
     if (p->dtype != b->dtype) return fail(PF_ERR_INVALID_ARG, "dtype %d differs from the batch's %d", p->dtype, b->dtype);
+    if (p->flags & ~PF_FLAG_DIAGNOSTICS) return fail(PF_ERR_INVALID_ARG, "implementation variants are not batched");
     const Layout L = make_layout(*p);
     if (L.total > b->slot_bytes[k] || L.ntiles > b->slot_tiles[k])
         return fail(PF_ERR_WORKSPACE, "filter %d: %zu bytes / %d tiles needed, its share holds %zu / %d", k, L.total,

@@ -130,7 +130,7 @@ __device__ __forceinline__ int disk_sum_global(const uint8_t* frame, int64_t pit
 // for every input (floor and the fraction v - floor(v) are exact).
 __device__ __forceinline__ int offset_cell(float v, int origin, int lo, int hi)
 {
-    v = fminf(fmaxf(v, (float)(lo - origin) - 1.0f), (float)(hi - origin) + 1.0f);
+    v = __builtin_amdgcn_fmed3f(v, (float)(lo - origin) - 1.0f, (float)(hi - origin) + 1.0f);
     const float fl = floorf(v);
     const int c = origin + (int)fl + ((v - fl) >= 0.5f ? 1 : 0);
     return min(max(c, lo), hi);
@@ -141,12 +141,12 @@ struct ModeT;
 
 template <>
 struct ModeT<PF_F64> {
-    static constexpr int PPT = kPPT;
     using Store = double;
     using Val = double;
     struct Prop {
         double dx, dy, sx, sy;
     };
+    template <int PPT>
     static __device__ __forceinline__ void load(const void* p, int k0, Val* v)
     {
         const double2* q = reinterpret_cast<const double2*>(static_cast<const double*>(p) + k0);
@@ -156,6 +156,7 @@ struct ModeT<PF_F64> {
             v[2 * i] = a.x; v[2 * i + 1] = a.y;
         }
     }
+    template <int PPT>
     static __device__ __forceinline__ void store(void* p, int k0, const Val* v)
     {
         double2* q = reinterpret_cast<double2*>(static_cast<double*>(p) + k0);
@@ -164,6 +165,7 @@ struct ModeT<PF_F64> {
     }
     // x <- x + (d + sigma z), each operation rounded (library built without
     // contraction), as Eq. (1)-(2) are written.
+    template <int PPT>
     static __device__ __forceinline__ void propagate(Val* x, Val* y, const Prop& pr, const StepArgs& a,
                                                      int k0)
     {
@@ -186,12 +188,12 @@ struct ModeT<PF_F64> {
 
 template <>
 struct ModeT<PF_F32> {
-    static constexpr int PPT = kPPT;
     using Store = float;
     using Val = float;
     struct Prop {
         float dx, dy, sx, sy;
     };
+    template <int PPT>
     static __device__ __forceinline__ void load(const void* p, int k0, Val* v)
     {
         const float2* q = reinterpret_cast<const float2*>(static_cast<const float*>(p) + k0);
@@ -201,12 +203,14 @@ struct ModeT<PF_F32> {
             v[2 * i] = a.x; v[2 * i + 1] = a.y;
         }
     }
+    template <int PPT>
     static __device__ __forceinline__ void store(void* p, int k0, const Val* v)
     {
         float2* q = reinterpret_cast<float2*>(static_cast<float*>(p) + k0);
 #pragma unroll
         for (int i = 0; i < PPT / 2; ++i) q[i] = make_float2(v[2 * i], v[2 * i + 1]);
     }
+    template <int PPT>
     static __device__ __forceinline__ void propagate(Val* x, Val* y, const Prop& pr, const StepArgs& a,
                                                      int k0)
     {
@@ -229,12 +233,12 @@ struct ModeT<PF_F32> {
 // fused multiply-add (sigma * z + d) and one packed add per pair and axis.
 template <>
 struct ModeT<PF_F16> {
-    static constexpr int PPT = kPPT;
     using Store = _Float16;
     using Val = _Float16;
     struct Prop {
         half2_t dx, dy, sx, sy;
     };
+    template <int PPT>
     static __device__ __forceinline__ void load(const void* p, int k0, Val* v)
     {
         const uint32_t* q = reinterpret_cast<const uint32_t*>(static_cast<const _Float16*>(p) + k0);
@@ -244,6 +248,7 @@ struct ModeT<PF_F16> {
             v[2 * i] = h.x; v[2 * i + 1] = h.y;
         }
     }
+    template <int PPT>
     static __device__ __forceinline__ void store(void* p, int k0, const Val* v)
     {
         uint32_t* q = reinterpret_cast<uint32_t*>(static_cast<_Float16*>(p) + k0);
@@ -253,6 +258,7 @@ struct ModeT<PF_F16> {
             q[i] = __builtin_bit_cast(uint32_t, h);
         }
     }
+    template <int PPT>
     static __device__ __forceinline__ void propagate(Val* x, Val* y, const Prop& pr, const StepArgs& a,
                                                      int k0)
     {
@@ -286,12 +292,12 @@ struct ModeT<PF_F16> {
 // rounding reaches the next step's ancestors.
 template <>
 struct ModeT<PF_BF16> {
-    static constexpr int PPT = kPPT;
     using Store = uint16_t;
     using Val = float;  // widened on load
     struct Prop {
         float dx, dy, sx, sy;
     };
+    template <int PPT>
     static __device__ __forceinline__ void load(const void* p, int k0, Val* v)
     {
         const uint32_t* q = reinterpret_cast<const uint32_t*>(static_cast<const uint16_t*>(p) + k0);
@@ -307,12 +313,14 @@ struct ModeT<PF_BF16> {
         const __bf16 a = (__bf16)lo, b = (__bf16)hi;
         return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
     }
+    template <int PPT>
     static __device__ __forceinline__ void store(void* p, int k0, const Val* v)
     {
         uint32_t* q = reinterpret_cast<uint32_t*>(static_cast<uint16_t*>(p) + k0);
 #pragma unroll
         for (int i = 0; i < PPT / 2; ++i) q[i] = pack(v[2 * i], v[2 * i + 1]);
     }
+    template <int PPT>
     static __device__ __forceinline__ void propagate(Val* x, Val* y, const Prop& pr, const StepArgs& a,
                                                      int k0)
     {
@@ -352,21 +360,25 @@ __device__ __forceinline__ typename ModeT<DT>::Prop make_prop(const StepArgs& a,
 // ---------------------------------------------------------------------------
 // Pass A.
 
+constexpr int kMaxWavesA = 8;  // pass A runs 128, 256 or 512 threads per tile
+
 struct PassALds {
     uint16_t pref[kPrefPitch * kPrefRows];
-    int box[kWavesA][4];
-    double red_d[3][kWavesA];
-    float red_f[3][kWavesA];
-    int red_i[kWavesA];
+    int box[kMaxWavesA][4];
+    double red_d[3][kMaxWavesA];
+    float red_f[3][kMaxWavesA];
+    int red_i[kMaxWavesA];
 };
 
-// Pass A of tile `tile` of the filter described by `a`.
-template <int DT, int RC>
+// Pass A of tile `tile` of the filter described by `a`, PPT particles per
+// thread (kTile / PPT threads).
+template <int DT, int RC, int PPT>
 __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALds& lds)
 {
     using M = ModeT<DT>;
-    constexpr int PPT = M::PPT;
-    static_assert(kBlockA * PPT == kTile, "tile size");
+    constexpr int kBlockA = kTile / PPT;
+    constexpr int kWavesA = kBlockA / 64;
+    static_assert(kWavesA >= 1 && kWavesA <= kMaxWavesA && kBlockA * PPT == kTile, "tile shape");
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
@@ -388,11 +400,11 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
     const typename M::Prop pr = make_prop<DT>(a, ddx, ddy);
 
     typename M::Val x[PPT], y[PPT];
-    M::load(a.sx, k0, x);
-    M::load(a.sy, k0, y);
-    M::propagate(x, y, pr, a, k0);
-    M::store(a.px, k0, x);
-    M::store(a.py, k0, y);
+    M::template load<PPT>(a.sx, k0, x);
+    M::template load<PPT>(a.sy, k0, y);
+    M::template propagate<PPT>(x, y, pr, a, k0);
+    M::template store<PPT>(a.px, k0, x);
+    M::template store<PPT>(a.py, k0, y);
 
     // Pixel cells, clamped to where clamping the disk pixels changes nothing.
     const int lox = -(r - 1), hix = a.W - 1 + (r - 1);
@@ -426,16 +438,24 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
     // Disk sums over the frame window of the tile: the window's row-prefix
     // table is built in LDS.  A window row is split over LPR lanes (16 for
     // windows up to 64 columns, else 32), four columns per lane, so a wave
-    // covers 64 / LPR rows per round; every byte load of the wave is issued
-    // before the first scan, and each lane writes its four prefix values as
-    // two 32-bit LDS stores.
+    // covers 64 / LPR rows per round; every load of the wave is issued before
+    // the first scan, and each lane writes its four prefix values as two
+    // 32-bit LDS stores.  When the frame's rows are 4-byte aligned the table
+    // starts at the window's first column rounded down to a multiple of 4, so
+    // a lane whose four columns lie inside the frame reads them with one
+    // aligned 32-bit load (edge lanes read bytes, clamped to the frame).
+    // Columns past the window only reach prefix entries no disk reads.
     const int wx0 = bx0 - (r - 1), wy0 = by0 - (r - 1);
     const int ww = bx1 - bx0 + 2 * r - 1, wh = by1 - by0 + 2 * r - 1;
-    const bool in_lds = ww <= kWinMaxW && wh <= kPrefRows;
+    const bool aligned = ((reinterpret_cast<uintptr_t>(a.frame) | (uintptr_t)a.pitch) & 3) == 0;
+    const int xs = aligned ? (wx0 & ~3) : wx0;  // frame column of table column 0
+    const int sh = wx0 - xs;
+    const int tw = ww + sh;                     // table columns
+    const bool in_lds = !a.naive_lik && tw <= kWinMaxW && wh <= kPrefRows;
     int S[PPT];
     if (in_lds) {
         constexpr int kMaxRounds = kPrefRows / (kWavesA * 2);  // 32-lane rows: 2 per wave per round
-        const bool narrow = ww <= 64;
+        const bool narrow = tw <= 64;
         const int lpr = narrow ? 16 : 32;
         const int rpr = 64 / lpr;                 // rows per wave per round
         const int sub = lane / lpr, l = lane - sub * lpr;
@@ -447,14 +467,17 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
         for (int it = 0; it < kMaxRounds; ++it) {
             const int yy = (it * kWavesA + wv) * rpr + sub;
             v[it] = 0;
-            if (it < rounds && yy < wh) {
+            if (it < rounds && yy < wh && c0 < tw) {
                 const int row = min(max(wy0 + yy, 0), a.H - 1);
                 const uint8_t* rp = a.frame + (int64_t)row * a.pitch;
+                const int x = xs + c0;
                 uint32_t pk = 0;
+                if (aligned && x >= 0 && x + 3 < a.W) {
+                    pk = *reinterpret_cast<const uint32_t*>(rp + x);
+                } else {
 #pragma unroll
-                for (int bb = 0; bb < 4; ++bb) {
-                    const int col = c0 + bb;
-                    if (col < ww) pk |= (uint32_t)rp[min(max(wx0 + col, 0), a.W - 1)] << (8 * bb);
+                    for (int bb = 0; bb < 4; ++bb)
+                        pk |= (uint32_t)rp[min(max(x + bb, 0), a.W - 1)] << (8 * bb);
                 }
                 v[it] = pk;
             }
@@ -487,7 +510,7 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
-            const int ox = valid[i] ? cx[i] - bx0 : 0, oy = valid[i] ? cy[i] - by0 : 0;
+            const int ox = valid[i] ? cx[i] - bx0 + sh : 0, oy = valid[i] ? cy[i] - by0 : 0;
             S[i] = disk_sum_prefix<RC>(lds.pref + oy * kPrefPitch + ox, r);
         }
     } else {
@@ -548,7 +571,7 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
     sw = wave_incl_max(sw, lane);
     ex = wave_sum(ex);
     ey = wave_sum(ey);
-    Acc (*red)[kWavesA];
+    Acc (*red)[kMaxWavesA];
     if constexpr (DT == PF_F64) red = lds.red_d; else red = lds.red_f;
     if (lane == 63) {
         red[0][wv] = sw;
@@ -585,6 +608,10 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
             a.dg_w[k0 + i] = (double)wt[i];
         }
     }
+    if (a.s_all) {
+#pragma unroll
+        for (int i = 0; i < PPT; ++i) a.s_all[k0 + i] = S[i];
+    }
     if (tid == kBlockA - 1) {
         // the tile total is the last thread's inclusive value
         Acc tx = red[1][0], ty = red[2][0];
@@ -600,11 +627,11 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
     }
 }
 
-template <int DT, int RC>
-__global__ __launch_bounds__(kBlockA) void pass_a_kernel(StepArgs a)
+template <int DT, int RC, int PPT>
+__global__ __launch_bounds__(kTile / PPT) void pass_a_kernel(StepArgs a)
 {
     __shared__ PassALds lds;
-    pass_a_tile<DT, RC>(a, blockIdx.x, lds);
+    pass_a_tile<DT, RC, PPT>(a, blockIdx.x, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -985,7 +1012,7 @@ __global__ __launch_bounds__(NT) void combine_kernel(StepArgs a)
 // that owns many slots takes several rounds of at most kDiagRound diagonals;
 // the work never depends on how the slots are spread inside the tile.
 
-constexpr int kDiagRound = 16 * kBlock;  // merge diagonals per round (16 per thread)
+constexpr int kDiagRound = 4096;  // merge diagonals per round
 
 template <int DT>
 struct PassCLds {
@@ -1008,8 +1035,8 @@ __device__ __forceinline__ int merge_cut(const int32_t* e, int tt, int d)
     return lo;
 }
 
-// Pass C of tile `t` of the filter described by `a`.
-template <int DT>
+// Pass C of tile `t` of the filter described by `a`, BC threads.
+template <int DT, int BC>
 __device__ __forceinline__ void pass_c_tile(const StepArgs& a, int t, PassCLds<DT>& lds)
 {
     using Store = typename ModeT<DT>::Store;
@@ -1026,8 +1053,8 @@ __device__ __forceinline__ void pass_c_tile(const StepArgs& a, int t, PassCLds<D
     const Store* px = static_cast<const Store*>(a.px);
     const Store* py = static_cast<const Store*>(a.py);
 #pragma unroll
-    for (int r = 0; r < kTile / kBlock; ++r) {
-        const int k = tid + r * kBlock;
+    for (int r = 0; r < kTile / BC; ++r) {
+        const int k = tid + r * BC;
         if (k < tt) {
             const int e = k == tt - 1 ? ts.E : ts(a.q, first + k, n);
             s_e[k] = e - ts.Eprev;
@@ -1039,8 +1066,8 @@ __device__ __forceinline__ void pass_c_tile(const StepArgs& a, int t, PassCLds<D
     const int slots = ts.E - ts.Eprev;
     if (slots <= 0) return;  // uniform over the workgroup
     const int total = tt + slots;
-    const int ipt = min((total + kBlock - 1) / kBlock, kDiagRound / kBlock);
-    const int round = ipt * kBlock;
+    const int ipt = min((total + BC - 1) / BC, kDiagRound / BC);
+    const int round = ipt * BC;
     Store* sx = static_cast<Store*>(a.sx) + ts.Eprev;
     Store* sy = static_cast<Store*>(a.sy) + ts.Eprev;
     int32_t* anc_out = a.dg_anc ? a.dg_anc + ts.Eprev : nullptr;
@@ -1062,7 +1089,7 @@ __device__ __forceinline__ void pass_c_tile(const StepArgs& a, int t, PassCLds<D
             }
         }
         __syncthreads();
-        for (int i = tid; i < j1 - j0; i += kBlock) {
+        for (int i = tid; i < j1 - j0; i += BC) {
             const int kk = lds.anc[i];
             sx[j0 + i] = s_x[kk];
             sy[j0 + i] = s_y[kk];
@@ -1072,11 +1099,110 @@ __device__ __forceinline__ void pass_c_tile(const StepArgs& a, int t, PassCLds<D
     }
 }
 
-template <int DT>
-__global__ __launch_bounds__(kBlock) void pass_c_kernel(StepArgs a)
+template <int DT, int BC>
+__global__ __launch_bounds__(BC) void pass_c_kernel(StepArgs a)
 {
     __shared__ PassCLds<DT> lds;
-    pass_c_tile<DT>(a, blockIdx.x, lds);
+    pass_c_tile<DT, BC>(a, blockIdx.x, lds);
+}
+
+// ---------------------------------------------------------------------------
+// The straightforward resampler, kept for measuring what pass C gains:
+// a normalising kernel writes the normalised cumulative distribution
+// C_k = P_k / Z (one division per particle, C_{N-1} = 1), then one thread per
+// slot j finds its ancestor, the first k with C_k >= (j + u0) / N, by binary
+// search over C in global memory.  Double in the FP64 mode, float otherwise.
+
+template <int DT>
+__global__ __launch_bounds__(kBlock) void normalize_naive_kernel(StepArgs a)
+{
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    const int n = (int)a.n;
+    if (k >= n) return;
+    const int t = k / kTile;
+    if constexpr (DT == PF_F64) {
+        const TileTab64* tab = static_cast<const TileTab64*>(a.tab);
+        const double P = tab[t].off + tab[t].f * static_cast<const double*>(a.q)[k];
+        static_cast<double*>(a.cdf)[k] = k == n - 1 ? 1.0 : P / a.blk->Z;
+    } else {
+        const TileTab32* tab = static_cast<const TileTab32*>(a.tab);
+        const float P = (tab[t].off_hi + tab[t].off_lo) + tab[t].f * static_cast<const float*>(a.q)[k];
+        static_cast<float*>(a.cdf)[k] = k == n - 1 ? 1.0f : P / a.blk->Zf;
+    }
+}
+
+template <int DT, int TPB>
+__global__ __launch_bounds__(TPB) void resample_naive_kernel(StepArgs a)
+{
+    using Store = typename ModeT<DT>::Store;
+    const int j = blockIdx.x * TPB + threadIdx.x;
+    const int n = (int)a.n;
+    if (j >= n) return;
+    int lo = 0, hi = n - 1;
+    if constexpr (DT == PF_F64) {
+        const double u = ((double)j + a.blk->u0) / (double)n;
+        const double* C = static_cast<const double*>(a.cdf);
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (C[mid] >= u) hi = mid; else lo = mid + 1;
+        }
+    } else {
+        const float u = ((float)j + (a.blk->u0_hi + a.blk->u0_lo)) / (float)n;
+        const float* C = static_cast<const float*>(a.cdf);
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (C[mid] >= u) hi = mid; else lo = mid + 1;
+        }
+    }
+    static_cast<Store*>(a.sx)[j] = static_cast<const Store*>(a.px)[lo];
+    static_cast<Store*>(a.sy)[j] = static_cast<const Store*>(a.py)[lo];
+    if (a.dg_anc) a.dg_anc[j] = lo;
+}
+
+// ---------------------------------------------------------------------------
+// Metropolis resampling (Murray, Lee & Jacob, 2016), one thread per slot: a
+// chain of B steps from particle j, each proposing a uniform particle i and
+// moving when u <= exp(L_i - L_k) (always when L_i >= L_k).  The log-weights
+// are the integer disk terms S of pass A over the likelihood's denominator:
+// L = S / denom in double in the FP64 mode; the reduced modes compare
+// exp2((S_i - S_k) beta) in float.  Proposals gather S from global memory.
+
+template <int DT>
+__global__ __launch_bounds__(kBlock) void metropolis_kernel(StepArgs a)
+{
+    using Store = typename ModeT<DT>::Store;
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    const int n = (int)a.n;
+    if (j >= n) return;
+    const int32_t* S = a.s_all;
+    int k = j;
+    int Sk = S[k];
+    double Lk = (double)Sk / a.denom;
+    u32x4 w{0u, 0u, 0u, 0u};
+    for (int b = 0; b < a.mh_steps; ++b) {
+        if ((b & 1) == 0)
+            w = philox4x32_10((uint32_t)j, a.t, a.stream_id, 2u + (uint32_t)(b >> 1), a.key0, a.key1);
+        const uint32_t wi = (b & 1) ? w.v2 : w.v0;
+        const uint32_t wu = (b & 1) ? w.v3 : w.v1;
+        const int i = (int)(((uint64_t)wi * (uint64_t)(uint32_t)n) >> 32);
+        const int Si = S[i];
+        if constexpr (DT == PF_F64) {
+            const double Li = (double)Si / a.denom;
+            if (Li >= Lk || ((double)wu + 0.5) * 0x1.0p-32 <= exp(Li - Lk)) {
+                k = i;
+                Lk = Li;
+            }
+        } else {
+            if (Si >= Sk ||
+                ((float)(wu >> 8) + 0.5f) * 0x1.0p-24f <= __builtin_amdgcn_exp2f((float)(Si - Sk) * a.beta)) {
+                k = i;
+                Sk = Si;
+            }
+        }
+    }
+    static_cast<Store*>(a.sx)[j] = static_cast<const Store*>(a.px)[k];
+    static_cast<Store*>(a.sy)[j] = static_cast<const Store*>(a.py)[k];
+    if (a.dg_anc) a.dg_anc[j] = k;
 }
 
 // ---------------------------------------------------------------------------
@@ -1130,7 +1256,7 @@ __global__ __launch_bounds__(kBlockA) void pass_a_batch_kernel(BatchArgs b)
     __shared__ PassALds lds;
     const int e = b.tile_entry[blockIdx.x];
     const StepArgs a = batch_args(b, e);
-    pass_a_tile<DT, RC>(a, (int)blockIdx.x - b.entries[e].tile_base, lds);
+    pass_a_tile<DT, RC, kPPT>(a, (int)blockIdx.x - b.entries[e].tile_base, lds);
 }
 
 template <int DT, int KPER, int NT>
@@ -1146,7 +1272,7 @@ __global__ __launch_bounds__(kBlock) void pass_c_batch_kernel(BatchArgs b)
     __shared__ PassCLds<DT> lds;
     const int e = b.tile_entry[blockIdx.x];
     const StepArgs a = batch_args(b, e);
-    pass_c_tile<DT>(a, (int)blockIdx.x - b.entries[e].tile_base, lds);
+    pass_c_tile<DT, kBlock>(a, (int)blockIdx.x - b.entries[e].tile_base, lds);
 }
 
 __global__ __launch_bounds__(kBlock) void gather_est_kernel(const StepArgs* args, int n, double* out)
@@ -1177,16 +1303,53 @@ static hipError_t launch1(void (*kernel)(Arg), dim3 g, dim3 b, hipStream_t s, co
 template <int DT>
 static hipError_t launch_pass_a_t(const StepArgs& a, hipStream_t s, const KTiming& tm)
 {
-    const dim3 g((unsigned)a.ntiles), blk(kBlockA);
-    if (a.r == 5) return launch1(pass_a_kernel<DT, 5>, g, blk, s, tm, a);
-    if (a.r == 8) return launch1(pass_a_kernel<DT, 8>, g, blk, s, tm, a);
-    return launch1(pass_a_kernel<DT, 0>, g, blk, s, tm, a);
+    const dim3 g((unsigned)a.ntiles);
+    if (a.threads_a == 128) {  // 8 particles per thread
+        if (a.r == 5) return launch1(pass_a_kernel<DT, 5, 8>, g, dim3(128), s, tm, a);
+        return launch1(pass_a_kernel<DT, 0, 8>, g, dim3(128), s, tm, a);
+    }
+    if (a.threads_a == 512) {  // 2 particles per thread
+        if (a.r == 5) return launch1(pass_a_kernel<DT, 5, 2>, g, dim3(512), s, tm, a);
+        return launch1(pass_a_kernel<DT, 0, 2>, g, dim3(512), s, tm, a);
+    }
+    const dim3 blk(kBlockA);
+    if (a.r == 5) return launch1(pass_a_kernel<DT, 5, kPPT>, g, blk, s, tm, a);
+    if (a.r == 8) return launch1(pass_a_kernel<DT, 8, kPPT>, g, blk, s, tm, a);
+    return launch1(pass_a_kernel<DT, 0, kPPT>, g, blk, s, tm, a);
+}
+
+template <int DT, int TPB>
+static hipError_t launch_naive_res(const StepArgs& a, hipStream_t s, const KTiming& tm)
+{
+    const unsigned gn = (unsigned)((a.n + kBlock - 1) / kBlock);
+    normalize_naive_kernel<DT><<<dim3(gn), dim3(kBlock), 0, s>>>(a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch1(resample_naive_kernel<DT, TPB>, dim3((unsigned)((a.n + TPB - 1) / TPB)), dim3(TPB), s, tm, a);
 }
 
 template <int DT>
 static hipError_t launch_pass_c_t(const StepArgs& a, hipStream_t s, const KTiming& tm)
 {
-    return launch1(pass_c_kernel<DT>, dim3((unsigned)a.ntiles), dim3(kBlock), s, tm, a);
+    const dim3 g((unsigned)a.ntiles);
+    if (a.mh_steps > 0)
+        return launch1(metropolis_kernel<DT>, dim3((unsigned)((a.n + kBlock - 1) / kBlock)), dim3(kBlock), s, tm, a);
+    if (a.naive_res) {
+        switch (a.threads_c) {
+        case 64: return launch_naive_res<DT, 64>(a, s, tm);
+        case 128: return launch_naive_res<DT, 128>(a, s, tm);
+        case 512: return launch_naive_res<DT, 512>(a, s, tm);
+        case 1024: return launch_naive_res<DT, 1024>(a, s, tm);
+        default: return launch_naive_res<DT, 256>(a, s, tm);
+        }
+    }
+    switch (a.threads_c) {
+    case 64: return launch1(pass_c_kernel<DT, 64>, g, dim3(64), s, tm, a);
+    case 128: return launch1(pass_c_kernel<DT, 128>, g, dim3(128), s, tm, a);
+    case 512: return launch1(pass_c_kernel<DT, 512>, g, dim3(512), s, tm, a);
+    case 1024: return launch1(pass_c_kernel<DT, 1024>, g, dim3(1024), s, tm, a);
+    default: return launch1(pass_c_kernel<DT, kBlock>, g, dim3(kBlock), s, tm, a);
+    }
 }
 
 template <int DT>

@@ -75,7 +75,7 @@ struct TileTab32 {
 struct Layout {
     int64_t n, n_pad;
     int tile, ntiles;
-    size_t blk, rec, tab, sx, sy, px, py, q, dg_s, dg_w, dg_anc, total;
+    size_t blk, rec, tab, sx, sy, px, py, q, dg_s, dg_w, dg_anc, cdf, s_all, total;
 };
 
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -107,6 +107,16 @@ inline Layout make_layout(const pf_params& p)
     } else {
         L.dg_s = L.dg_w = L.dg_anc = 0;
     }
+    if (p.flags & PF_FLAG_NAIVE_RESAMPLE) {
+        L.cdf = o; o = align256(o + qel * (size_t)L.n_pad);
+    } else {
+        L.cdf = 0;
+    }
+    if (p.flags & PF_FLAG_METROPOLIS) {
+        L.s_all = o; o = align256(o + 4 * (size_t)L.n_pad);
+    } else {
+        L.s_all = 0;
+    }
     L.total = o;
     return L;
 }
@@ -134,6 +144,14 @@ struct StepArgs {
     int32_t* dg_s;      // diagnostics (may be null)
     double* dg_w;
     int32_t* dg_anc;
+    // implementation variants (measurement of the straightforward step)
+    int32_t naive_lik;  // disk sums read every pixel from the frame
+    int32_t naive_res;  // normalised CDF + per-slot binary search instead of pass C
+    int32_t threads_a;  // pass A threads per tile: 128, 256 (default) or 512
+    int32_t threads_c;  // pass C / naive resampler threads per workgroup: 64 .. 1024
+    void* cdf;          // naive resampler: normalised cumulative weights
+    int32_t mh_steps;   // Metropolis resampling: steps per slot (0: systematic)
+    int32_t* s_all;     // Metropolis resampling: integer disk terms of all particles
 };
 
 // One filter of a batched step: the per-step part of its arguments.

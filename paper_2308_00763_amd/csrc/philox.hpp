@@ -20,10 +20,18 @@ struct u32x4 {
     uint32_t v0, v1, v2, v3;
 };
 
+// Three-way exclusive or in one gfx950 instruction (v_bitop3_b32 with the
+// truth table 0x96).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 // Ten rounds; each multiplies two counter words by the Philox constants,
 // swaps the halves and mixes in the round key, which advances by the Weyl
 // increments (0x9E3779B9, 0xBB67AE85) between rounds.  The key words are
-// uniform across the wave, so their updates stay scalar.
+// uniform across the wave, so their updates stay scalar; per round and lane
+// the work is two 32x32->64 multiplies and two three-way exclusive ors.
 __device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                uint32_t k0, uint32_t k1)
 {
@@ -31,9 +39,9 @@ __device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
         const uint32_t n1 = (uint32_t)p1;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
         const uint32_t n3 = (uint32_t)p0;
         c0 = n0; c1 = n1; c2 = n2; c3 = n3;
         k0 += 0x9E3779B9u;

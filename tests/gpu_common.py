@@ -96,7 +96,8 @@ def tv(a, b):
 
 
 def make_filter(dtype, n, W, H, r, x0, y0, drift=(1.0, -2.0), sigma=(5.0, 2.0), seed=0,
-                stream_id=0, diagnostics=True, lik_norm=0):
+                stream_id=0, diagnostics=True, lik_norm=0, **variant):
     p = pf.make_params(n, W, H, dtype, radius=r, x0=x0, y0=y0, drift=drift, sigma=sigma,
-                       seed=seed, stream_id=stream_id, diagnostics=diagnostics, lik_norm=lik_norm)
+                       seed=seed, stream_id=stream_id, diagnostics=diagnostics, lik_norm=lik_norm,
+                       **variant)
     return pf.Filter(p)

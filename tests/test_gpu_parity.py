@@ -144,6 +144,42 @@ def test_reduced_modes_one_tile_takes_every_slot(dtype):
     assert out[0][0]["anc"].max() < 1024
 
 
+def _padded_frames(frames, extra, offset):
+    """The frames on the device at row pitch W + extra, starting `offset`
+    bytes into a buffer: (T, H, W) views with that stride."""
+    T, H, W = frames.shape
+    P = W + extra
+    buf = torch.zeros(offset + T * H * P, dtype=torch.uint8, device="cuda:0")
+    v = buf[offset:].view(T, H, P)
+    v[:, :, :W] = torch.from_numpy(np.ascontiguousarray(frames)).to("cuda:0")
+    return v[:, :, :W]
+
+
+@pytest.mark.parametrize("W,extra,offset,start,vel", [
+    (125, 3, 1, (118, 50), (2, 0)),   # odd pitch, misaligned rows, right border
+    (128, 0, 0, (4, 40), (-1, 1)),    # aligned rows, left border
+    (128, 4, 2, (120, 3), (1, -1)),   # pitch multiple of 4, misaligned base, corner
+])
+def test_f64_window_at_frame_borders_and_unaligned_rows(W, extra, offset, start, vel):
+    H = 96
+    n = 3000
+    vid = pfsynth.moving_disk(W, H, 5, 5, start, vel, 2.0, seed=41)
+    fr = _padded_frames(vid.frames, extra, offset)
+    assert fr.stride(1) == W + extra
+    f = make_filter("f64", n, W, H, 5, *vid.centres[0], drift=vel)
+    op = oracle_params(n, W, H, 5, drift=vel)
+    x, y = np.full(n, vid.centres[0][0]), np.full(n, vid.centres[0][1])
+    for t in range(1, 5):
+        print(f"[parity] borders W={W} pitch={W + extra} offset={offset} step={t}", flush=True)
+        f.load(x, y, t - 1)
+        f.step(fr[t])
+        got, gs, est = f.export(), f.export_step(), f.estimate()
+        ref = oracle_step_parts(op, t, vid.frames[t], x, y)
+        compare_f64_step(got, gs, est, ref, n)
+        x, y = ref["x"], ref["y"]
+    f.close()
+
+
 def test_f64_uniform_frame_gives_uniform_weights():
     vid = pfsynth.moving_disk(64, 64, 3, 5, (32, 32), (0, 0), 0.0, seed=0)
     vid.frames[:] = 100
