@@ -117,11 +117,11 @@ def run_mode(pf, torch, frames_dev, centres, w, dtype, steps, warmup, profile, *
     return (t1 - t0), prof
 
 
-def track(pf, frames_dev, centres, w, dtype, nsteps):
+def track(pf, frames_dev, centres, w, dtype, nsteps, **variant):
     """Free-running estimates over frames 1..nsteps (untimed)."""
     x0, y0 = centres[0]
     p = pf.make_params(w.n_particles, w.width, w.height, dtype, radius=w.radius, x0=x0, y0=y0,
-                       drift=w.drift, sigma=w.sigma, seed=w.filter_seed)
+                       drift=w.drift, sigma=w.sigma, seed=w.filter_seed, **variant)
     f = pf.Filter(p)
     est = [(x0, y0)]
     for t in range(1, nsteps + 1):
@@ -296,6 +296,32 @@ def run_ablation(pf, torch, frames_dev, centres, w, steps, warmup, dtypes=("f16"
     return res
 
 
+def run_resamplers(pf, torch, frames_dev, centres, w, steps, warmup, dtypes=("f16", "f64")):
+    """Systematic resampling against Metropolis (B = 8, 32, 128) at the
+    headline size, and against Gumbel-max multinomial resampling at N = 65536
+    (its limit): ms per step, resampling kernel time, and the RMS distance of
+    the free-running track to the ground truth over the timed frames."""
+    import dataclasses
+    nsteps = warmup + steps
+    cases = [(w, "systematic", {}), (w, "metropolis B=8", dict(metropolis_steps=8)),
+             (w, "metropolis B=32", dict(metropolis_steps=32)),
+             (w, "metropolis B=128", dict(metropolis_steps=128))]
+    w64 = dataclasses.replace(w, n_particles=65536, name=w.name + "_n65536")
+    cases += [(w64, "systematic", {}), (w64, "gumbel-max", dict(gumbel_max=True))]
+    res = {}
+    for dt in dtypes:
+        rows = []
+        for wl, name, var in cases:
+            secs, _ = run_mode(pf, torch, frames_dev, centres, wl, dt, steps, warmup, False, **var)
+            _, prof = run_mode(pf, torch, frames_dev, centres, wl, dt, steps, warmup, True, **var)
+            est = track(pf, frames_dev, centres, wl, dt, nsteps, **var)
+            rms = float(np.sqrt(np.mean(np.sum((est - centres[:nsteps + 1]) ** 2, axis=1))))
+            rows.append(dict(resampler=name, n_particles=wl.n_particles, ms_per_step=1e3 * secs / steps,
+                             resample_us=1e3 * prof[2] / prof[3], track_rms_vs_truth_px=rms))
+        res[dt] = rows
+    return res
+
+
 def run_accuracy(pf, torch, pfsynth, modes):
     """The paper's accuracy video (512x512, 100 frames, bounce off y = 0,
     128 particles): per mode the RMS distance of the free-running estimates to
@@ -460,6 +486,10 @@ def main():
         out["ablation"] = run_ablation(pf, torch, frames_dev, vid.centres, w, min(args.steps, 40),
                                        args.warmup)
         log(f"[bench] ablation: {json.dumps(out['ablation'])}")
+    if not args.no_ablation:
+        out["resamplers"] = run_resamplers(pf, torch, frames_dev, vid.centres, w, min(args.steps, 40),
+                                           args.warmup)
+        log(f"[bench] resamplers: {json.dumps(out['resamplers'])}")
     if not args.no_track:
         out["accuracy"] = run_accuracy(pf, torch, pfsynth, modes)
         log(f"[bench] accuracy: {out['accuracy']}")

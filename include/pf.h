@@ -109,6 +109,17 @@ typedef enum pf_lik_norm { PF_LIK_MEAN = 0, PF_LIK_SUM = 1 } pf_lik_norm;
 #define PF_FLAG_METROPOLIS (1u << 16)
 #define PF_METROPOLIS_STEPS_SHIFT 18
 
+/* Multinomial resampling by the Gumbel-max scheme (the alternative weighed
+ * in the paper, Sec. 4, numerical-stability paragraph) instead of systematic
+ * resampling: slot i takes argmax_j (L_j + G_ij) with G_ij = -ln(-ln u)
+ * standard Gumbel noise, u = (word + 1/2) 2^-32 (the top 24 bits in the
+ * reduced modes), the word j mod 4 of Philox at counter (floor(j/4), i, t,
+ * stream_id) under key (seed low, seed high xor 0x47756D62).  It works on
+ * the unnormalised log weights but draws N^2 noise values per step, so it
+ * accepts N <= 65536 (the paper's particle limit).  Costs 4 bytes per
+ * particle of workspace.  Not accepted by the batch calls. */
+#define PF_FLAG_GUMBEL_MAX (1u << 17)
+
 typedef struct pf_params {
     uint32_t struct_size;  /* must be sizeof(pf_params) */
     int32_t dtype;         /* pf_dtype */

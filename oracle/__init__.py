@@ -93,6 +93,8 @@ def lib():
                              ctypes.c_double, dp, dp, dp]
         L.or_metropolis.argtypes = [ctypes.c_int64, dp, ctypes.c_int32, ctypes.c_uint64,
                                     ctypes.c_uint32, ctypes.c_uint32, ip, dp]
+        L.or_gumbel_max.argtypes = [ctypes.c_int64, dp, ctypes.c_uint64, ctypes.c_uint32,
+                                    ctypes.c_uint32, ip, dp]
         _lib = L
     return _lib
 
@@ -246,5 +248,17 @@ def metropolis(L, B: int, seed: int, stream_id: int, t: int):
     anc = np.zeros(n, dtype=np.int32)
     margin = np.zeros(n)
     lib().or_metropolis(n, _ptr(L, ctypes.c_double), int(B), int(seed), int(stream_id), int(t),
+                        _ptr(anc, ctypes.c_int32), _ptr(margin, ctypes.c_double))
+    return anc, margin
+
+
+def gumbel_max(L, seed: int, stream_id: int, t: int):
+    """Gumbel-max multinomial resampling of log-likelihoods L (pf_oracle.c,
+    or_gumbel_max).  Returns (ancestors, margins)."""
+    L = np.ascontiguousarray(L, dtype=np.float64)
+    n = L.size
+    anc = np.zeros(n, dtype=np.int32)
+    margin = np.zeros(n)
+    lib().or_gumbel_max(n, _ptr(L, ctypes.c_double), int(seed), int(stream_id), int(t),
                         _ptr(anc, ctypes.c_int32), _ptr(margin, ctypes.c_double))
     return anc, margin

@@ -329,6 +329,48 @@ void or_metropolis(int64_t n, const double *L, int32_t B, uint64_t seed, uint32_
     }
 }
 
+/* ------------------------------------------------------------------ */
+/* Multinomial resampling by the Gumbel-max scheme (the alternative the
+ * paper weighs in Sec. 4, numerical-stability paragraph): slot i takes
+ * a_i = argmax_j (L_j + G_ij) with G_ij independent standard Gumbel
+ * variables, so P(a_i = j) is the normalised weight of j; it works on the
+ * unnormalised log weights (no maximum, normaliser or cumulative
+ * distribution) and costs n^2 noise draws.
+ * G_ij = -ln(-ln u), u = (word + 1/2) 2^-32, word j mod 4 of Philox at
+ * counter (floor(j / 4), i, t, stream_id) with key (low 32 bits of seed,
+ * high 32 bits of seed xor 0x47756D62) -- a key of its own, so these words
+ * never coincide with the other streams of the filter.  Ties go to the lower
+ * index.  margin (optional): for slot i the gap between the best and the
+ * second-best score. */
+void or_gumbel_max(int64_t n, const double *L, uint64_t seed, uint32_t stream_id, uint32_t t,
+                   int32_t *anc, double *margin)
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32) ^ 0x47756D62u};
+    for (int64_t i = 0; i < n; ++i) {
+        double best = -INFINITY, second = -INFINITY;
+        int64_t arg = 0;
+        uint32_t w[4] = {0, 0, 0, 0};
+        for (int64_t j = 0; j < n; ++j) {
+            if (j % 4 == 0) {
+                uint32_t ctr[4] = {(uint32_t)(j / 4), (uint32_t)i, t, stream_id};
+                or_philox4x32_10(ctr, key, w);
+            }
+            double u = ((double)w[j % 4] + 0.5) * 0x1.0p-32;
+            double g = -log(-log(u));
+            double v = L[j] + g;
+            if (v > best) {
+                second = best;
+                best = v;
+                arg = j;
+            } else if (v > second) {
+                second = v;
+            }
+        }
+        anc[i] = (int32_t)arg;
+        if (margin) margin[i] = best - second;
+    }
+}
+
 /* One whole SIR step t (t = 1, 2, ...) on frame `frame`.
  * In:  x, y -- the particles after the previous resampling (all weights 1/n).
  * Out: x, y -- the particles after this step's resampling;

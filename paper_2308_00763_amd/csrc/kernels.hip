@@ -1206,6 +1206,67 @@ __global__ __launch_bounds__(kBlock) void metropolis_kernel(StepArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// Gumbel-max multinomial resampling: thread per slot i, the argmax over all
+// particles j of L_j + G_ij with G_ij = -ln(-ln u) from Philox at counter
+// (j / 4, i, t, stream_id) under the key (seed low, seed high ^ 0x47756D62);
+// the log weights of 1024 particles at a time are staged in LDS.  Double in
+// the FP64 mode; float with the hardware log2 otherwise.  Ties keep the lower
+// index.
+
+template <int DT>
+__global__ __launch_bounds__(kBlock) void gumbel_kernel(StepArgs a)
+{
+    using Store = typename ModeT<DT>::Store;
+    using Acc = typename std::conditional<DT == PF_F64, double, float>::type;
+    __shared__ Acc s_L[kTile];
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int n = (int)a.n;
+    const uint32_t key1 = a.key1 ^ 0x47756D62u;
+    const float inv = (float)(1.0 / a.denom);
+    Acc best = -INFINITY;
+    int arg = 0;
+    for (int c0 = 0; c0 < n; c0 += kTile) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < kTile; k += kBlock) {
+            const int j = c0 + k;
+            if constexpr (DT == PF_F64) s_L[k] = j < n ? (double)a.s_all[j] / a.denom : -INFINITY;
+            else s_L[k] = j < n ? (float)a.s_all[j] * inv : -INFINITY;
+        }
+        __syncthreads();
+        if (i < n) {
+            const int m = min(kTile, n - c0);
+            for (int k = 0; k < m; k += 4) {
+                const u32x4 w = philox4x32_10((uint32_t)((c0 + k) >> 2), (uint32_t)i, a.t, a.stream_id, a.key0, key1);
+                const uint32_t ws[4] = {w.v0, w.v1, w.v2, w.v3};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (k + q < m) {
+                        Acc g;
+                        if constexpr (DT == PF_F64) {
+                            g = -log(-log(((double)ws[q] + 0.5) * 0x1.0p-32));
+                        } else {
+                            const float u = ((float)(ws[q] >> 8) + 0.5f) * 0x1.0p-24f;
+                            const float e = -0.6931471805599453f * __builtin_amdgcn_logf(u);  // -ln u
+                            g = -0.6931471805599453f * __builtin_amdgcn_logf(e);
+                        }
+                        const Acc v = s_L[k + q] + g;
+                        if (v > best) {
+                            best = v;
+                            arg = c0 + k + q;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (i < n) {
+        static_cast<Store*>(a.sx)[i] = static_cast<const Store*>(a.px)[arg];
+        static_cast<Store*>(a.sy)[i] = static_cast<const Store*>(a.py)[arg];
+        if (a.dg_anc) a.dg_anc[i] = arg;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Normalised weights of the latest step for diagnostics: w_k = wt_k f_t / Z.
 template <int DT>
 __global__ __launch_bounds__(kBlock) void diag_weights_kernel(StepArgs a)
@@ -1334,6 +1395,8 @@ static hipError_t launch_pass_c_t(const StepArgs& a, hipStream_t s, const KTimin
     const dim3 g((unsigned)a.ntiles);
     if (a.mh_steps > 0)
         return launch1(metropolis_kernel<DT>, dim3((unsigned)((a.n + kBlock - 1) / kBlock)), dim3(kBlock), s, tm, a);
+    if (a.gumbel)
+        return launch1(gumbel_kernel<DT>, dim3((unsigned)((a.n + kBlock - 1) / kBlock)), dim3(kBlock), s, tm, a);
     if (a.naive_res) {
         switch (a.threads_c) {
         case 64: return launch_naive_res<DT, 64>(a, s, tm);

@@ -112,7 +112,7 @@ inline Layout make_layout(const pf_params& p)
     } else {
         L.cdf = 0;
     }
-    if (p.flags & PF_FLAG_METROPOLIS) {
+    if (p.flags & (PF_FLAG_METROPOLIS | PF_FLAG_GUMBEL_MAX)) {
         L.s_all = o; o = align256(o + 4 * (size_t)L.n_pad);
     } else {
         L.s_all = 0;
@@ -151,7 +151,8 @@ struct StepArgs {
     int32_t threads_c;  // pass C / naive resampler threads per workgroup: 64 .. 1024
     void* cdf;          // naive resampler: normalised cumulative weights
     int32_t mh_steps;   // Metropolis resampling: steps per slot (0: systematic)
-    int32_t* s_all;     // Metropolis resampling: integer disk terms of all particles
+    int32_t gumbel;     // Gumbel-max multinomial resampling
+    int32_t* s_all;     // Metropolis / Gumbel-max: integer disk terms of all particles
 };
 
 // One filter of a batched step: the per-step part of its arguments.
