@@ -230,6 +230,8 @@ void setup_filter(pf_filter* h, const pf_params& pr, uint8_t* ws, hipStream_t st
     a.blk = (DevBlock*)at(h, L.blk);
     a.rec = at(h, L.rec);
     a.tab = at(h, L.tab);
+    a.grec = at(h, L.grec);
+    a.gtab = at(h, L.gtab);
     a.sx = at(h, L.sx);
     a.sy = at(h, L.sy);
     a.px = at(h, L.px);
@@ -750,11 +752,18 @@ int pf_batch_step(pf_batch* b, const uint8_t* const* d_frames, const int64_t* pi
     ba.tile_entry = b->d_tile_entry;
     ba.entry0 = 0;
     if (e == hipSuccess) e = launch_batch_pass_a(b->dtype, b->rc, ba, tiles, b->stream);
-    for (int c = 0; c < kCombClasses && e == hipSuccess; ++c) {
+    for (int c = 0; c < kCombClasses - 1 && e == hipSuccess; ++c) {
         const int32_t cnt = cls_begin[c + 1] - cls_begin[c];
         if (cnt == 0) continue;
         ba.entry0 = cls_begin[c];
         e = launch_batch_combine(b->dtype, c, ba, cnt, b->stream);
+    }
+    // the largest filters (class 3) combine with the grouped kernels, one
+    // filter at a time, exactly as they do alone
+    for (int32_t i = cls_begin[kCombClasses - 1]; i < cls_begin[kCombClasses] && e == hipSuccess; ++i) {
+        StepArgs a = b->f[ent[i].fid]->args;
+        a.t = ent[i].t;
+        e = launch_combine(b->dtype, a, b->stream);
     }
     ba.entry0 = 0;
     if (e == hipSuccess) e = launch_batch_pass_c(b->dtype, ba, tiles, b->stream);

@@ -776,6 +776,86 @@ struct CombAcc<PF_F32> {
     static __device__ T up1(T v, T fill) { return ff{wave_shift_up1(v.hi, fill.hi), wave_shift_up1(v.lo, fill.lo)}; }
 };
 
+// The map from a cumulative weight P to its end slot, floor(R P - u0) + 1
+// with R = N / Z, and the step's resampling offset u0 (counter (0, t,
+// stream_id, 1)): double in the FP64 mode, two-float in the reduced modes.
+template <bool F64>
+struct SlotMap;
+
+template <>
+struct SlotMap<true> {
+    double R, mu0, u0;
+    __device__ SlotMap(const StepArgs& a, double Z)
+    {
+        const u32x4 wu = philox4x32_10(0u, a.t, a.stream_id, 1u, a.key0, a.key1);
+        u0 = uniform53(wu.v0, wu.v1);
+        R = (double)(int)a.n / Z;
+        mu0 = -u0;
+    }
+    __device__ int end_of(double o, int n) const { return slot_end_of(R * o + mu0, n); }
+};
+
+template <>
+struct SlotMap<false> {
+    ff R, mu0, u0;
+    __device__ SlotMap(const StepArgs& a, ff Z)
+    {
+        const int n = (int)a.n;
+        const u32x4 wu = philox4x32_10(0u, a.t, a.stream_id, 1u, a.key0, a.key1);
+        const uint64_t bits = ((uint64_t)wu.v0 << 21) | (uint64_t)(wu.v1 >> 11);
+        u0 = fast_two_sum((float)(uint32_t)(bits >> 29) * 0x1.0p-24f,
+                          (float)(uint32_t)(bits & 0x1FFFFFFFu) * 0x1.0p-53f);
+        mu0 = ff{-u0.hi, -u0.lo};
+        const ff Nff = fast_two_sum((float)n, (float)(n - (int)(float)n));
+        R = ff_div(Nff, Z);
+    }
+    __device__ int end_of(ff o, int n) const { return slot_end_of(ff_add(ff_mul(R, o), mu0), n); }
+};
+
+// The per-filter block after a combine: normaliser, maximum, u0, R, the
+// estimate (sx, sy: weighted position sums relative to the maximum) and, in
+// the reduced modes, the origin of the next propagation.  One thread.
+template <int DT>
+__device__ __forceinline__ void write_block(const StepArgs& a,
+                                           typename std::conditional<DT == PF_F64, double, ff>::type Z,
+                                           typename std::conditional<DT == PF_F64, double, int>::type gm,
+                                           typename std::conditional<DT == PF_F64, double, float>::type sx,
+                                           typename std::conditional<DT == PF_F64, double, float>::type sy,
+                                           const SlotMap<DT == PF_F64>& sm)
+{
+    DevBlock* b = a.blk;
+    if constexpr (DT == PF_F64) {
+        b->M = gm;
+        b->Z = Z;
+        b->u0 = sm.u0;
+        b->R = sm.R;
+        b->est_x = sx / Z;
+        b->est_y = sy / Z;
+    } else {
+        const float Zf = Z.hi + Z.lo;
+        const int cnx = b->cn_x, cny = b->cn_y;
+        const float ox = (float)cnx + sx / Zf;
+        const float oy = (float)cny + sy / Zf;
+        // the estimate leaves the device as double (conversion only)
+        b->est_x = (double)ox;
+        b->est_y = (double)oy;
+        b->Zf = Zf;
+        b->Smax = gm;
+        b->R_hi = sm.R.hi;
+        b->R_lo = sm.R.lo;
+        b->u0_hi = sm.u0.hi;
+        b->u0_lo = sm.u0.lo;
+        // the stored positions become relative to this step's origin; the
+        // next propagation is centred on the predicted position
+        b->ci_x = cnx;
+        b->ci_y = cny;
+        const float px_ = fminf(fmaxf(ox + (float)a.drift_x, -1.0e6f), 1.0e6f);
+        const float py_ = fminf(fmaxf(oy + (float)a.drift_y, -1.0e6f), 1.0e6f);
+        b->cn_x = offset_cell(px_, 0, -2000000, 2000000);
+        b->cn_y = offset_cell(py_, 0, -2000000, 2000000);
+    }
+}
+
 // Combine of the filter described by `a`, run by one workgroup of NT threads.
 template <int DT, int KPER, int NT>
 __device__ __forceinline__ void combine_filter(const StepArgs& a)
@@ -800,7 +880,6 @@ __device__ __forceinline__ void combine_filter(const StepArgs& a)
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int nt = a.ntiles;
     const int n = (int)a.n;
-    DevBlock* b = a.blk;
     const Rec* rec = static_cast<const Rec*>(a.rec);
     Tab* tab = static_cast<Tab*>(a.tab);
 
@@ -826,7 +905,6 @@ __device__ __forceinline__ void combine_filter(const StepArgs& a)
 
     // carried offsets: kPER consecutive tiles per thread, a wave scan, then a
     // scan of the wave totals by wave 0; the total is the normaliser
-    const u32x4 wu = philox4x32_10(0u, a.t, a.stream_id, 1u, a.key0, a.key1);
     T carry = A::zero();
     Fv ex = 0, ey = 0;
     constexpr bool KEEP = KPER <= 4;  // keep offsets in registers for the end slots
@@ -894,26 +972,8 @@ __device__ __forceinline__ void combine_filter(const StepArgs& a)
     // its tiles with), made non-decreasing by a prefix maximum so that the
     // tiles' slot ranges [E_{t-1}, E_t) partition [0, N) whatever the
     // rounding of the offsets; the last tile ends at N.
-    using Y = typename std::conditional<F64, double, ff>::type;
-    Y Rr, mu0;
-    double u0d = 0.0;
-    ff u0f{0.f, 0.f};
-    if constexpr (F64) {
-        u0d = uniform53(wu.v0, wu.v1);
-        Rr = (double)n / Z;
-        mu0 = -u0d;
-    } else {
-        const uint64_t bits = ((uint64_t)wu.v0 << 21) | (uint64_t)(wu.v1 >> 11);
-        u0f = fast_two_sum((float)(uint32_t)(bits >> 29) * 0x1.0p-24f,
-                           (float)(uint32_t)(bits & 0x1FFFFFFFu) * 0x1.0p-53f);
-        mu0 = ff{-u0f.hi, -u0f.lo};
-        const ff Nff = fast_two_sum((float)n, (float)(n - (int)(float)n));
-        Rr = ff_div(Nff, Z);
-    }
-    auto end_of = [&](T o) -> int {
-        if constexpr (F64) return slot_end_of(Rr * o + mu0, n);
-        else return slot_end_of(ff_add(ff_mul(Rr, o), mu0), n);
-    };
+    const SlotMap<F64> smap(a, Z);
+    auto end_of = [&](T o) -> int { return smap.end_of(o, n); };
     const bool one_round = KEEP && nt <= CHUNK;
     int carry_e = 0;
     for (int base = 0; base < nt; base += CHUNK) {
@@ -956,37 +1016,11 @@ __device__ __forceinline__ void combine_filter(const StepArgs& a)
     if (tid == 0) {
         if constexpr (F64) {
             tab[0].off = 0.0;
-            b->M = gm;
-            b->Z = Z;
-            b->u0 = u0d;
-            b->R = Rr;
-            b->est_x = sx / Z;
-            b->est_y = sy / Z;
         } else {
             tab[0].off_hi = 0.f;
             tab[0].off_lo = 0.f;
-            const float Zf = Z.hi + Z.lo;
-            const int cnx = b->cn_x, cny = b->cn_y;
-            const float ox = (float)cnx + sx / Zf;
-            const float oy = (float)cny + sy / Zf;
-            // the estimate leaves the device as double (conversion only)
-            b->est_x = (double)ox;
-            b->est_y = (double)oy;
-            b->Zf = Zf;
-            b->Smax = gm;
-            b->R_hi = Rr.hi;
-            b->R_lo = Rr.lo;
-            b->u0_hi = u0f.hi;
-            b->u0_lo = u0f.lo;
-            // the stored positions become relative to this step's origin; the
-            // next propagation is centred on the predicted position
-            b->ci_x = cnx;
-            b->ci_y = cny;
-            const float px_ = fminf(fmaxf(ox + (float)a.drift_x, -1.0e6f), 1.0e6f);
-            const float py_ = fminf(fmaxf(oy + (float)a.drift_y, -1.0e6f), 1.0e6f);
-            b->cn_x = offset_cell(px_, 0, -2000000, 2000000);
-            b->cn_y = offset_cell(py_, 0, -2000000, 2000000);
         }
+        write_block<DT>(a, Z, gm, sx, sy, smap);
     }
 }
 
@@ -994,6 +1028,270 @@ template <int DT, int KPER, int NT>
 __global__ __launch_bounds__(NT) void combine_kernel(StepArgs a)
 {
     combine_filter<DT, KPER, NT>(a);
+}
+
+// ---------------------------------------------------------------------------
+// Grouped combine for filters of more than 4096 tiles (combine class 3): the
+// tiles form groups of kGroupTiles, and three launches replace the single
+// workgroup.
+//   group:  one workgroup per group: the group maximum m_g, the tile factors
+//           f_t^g = e^{m_t - m_g}, the group-relative exclusive prefix W_t of
+//           f_t^g s_t (into the tile table), the group sum S_g and the group's
+//           estimate sums;
+//   top:    one workgroup over the groups: M = max m_g, c_g = e^{m_g - M},
+//           the group offsets O_g (exclusive scan of c_g S_g; Z is the total),
+//           the estimate, u0, R, and the groups' end slots EB_g (the end slot
+//           of O_{g+1}, made non-decreasing; the last group ends at N);
+//   finish: one workgroup per group: off_t = O_g + c_g W_t, f_t = c_g f_t^g,
+//           and the tiles' end slots from off_{t+1}, made non-decreasing from
+//           EB_{g-1} and capped at EB_g (the group's last tile ends at EB_g).
+
+constexpr int kGroupTiles = 1024;
+constexpr int kGroupWaves = kGroupTiles / 64;
+constexpr int kTopThreads = 256;  // groups of at most 2^28 / 2^20 filters' tiles
+
+template <int DT>
+__global__ __launch_bounds__(kGroupTiles) void combine_group_kernel(StepArgs a)
+{
+    constexpr bool F64 = DT == PF_F64;
+    using A = CombAcc<F64 ? PF_F64 : PF_F32>;
+    using T = typename A::T;
+    using Rec = typename std::conditional<F64, TileRec64, TileRec32>::type;
+    using Tab = typename std::conditional<F64, TileTab64, TileTab32>::type;
+    using GRec = typename std::conditional<F64, GroupRec64, GroupRec32>::type;
+    using Fv = typename std::conditional<F64, double, float>::type;
+    using Mx = typename std::conditional<F64, double, int>::type;
+    __shared__ Mx red_m[kGroupWaves];
+    __shared__ T red_s[kGroupWaves];
+    __shared__ T wave_off[kGroupWaves + 1];
+    __shared__ Fv red_x[kGroupWaves], red_y[kGroupWaves];
+
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int g = blockIdx.x, t = g * kGroupTiles + tid;
+    const bool valid = t < a.ntiles;
+    Rec rr{};
+    if (valid) rr = static_cast<const Rec*>(a.rec)[t];
+    Mx m = F64 ? (Mx)-INFINITY : (Mx)INT32_MIN;
+    if (valid) {
+        if constexpr (F64) m = rr.m; else m = rr.smax;
+    }
+    m = wave_max(m);
+    if (lane == 0) red_m[wv] = m;
+    __syncthreads();
+    Mx gm = red_m[0];
+#pragma unroll
+    for (int w = 1; w < kGroupWaves; ++w) gm = red_m[w] > gm ? red_m[w] : gm;
+
+    Fv f = 0, ex = 0, ey = 0;
+    T v = A::zero();
+    if (valid) {
+        if constexpr (F64) {
+            f = exp(rr.m - gm);
+            v = f * rr.s;
+        } else {
+            f = __builtin_amdgcn_exp2f((float)(rr.smax - gm) * a.beta);
+            v = two_prod(f, rr.s);
+        }
+        ex = f * rr.sx;
+        ey = f * rr.sy;
+    }
+    const T sw = A::sum_scan(v);
+    if (lane == 63) red_s[wv] = sw;
+    __syncthreads();
+    if (wv == 0) {
+        T tv = lane < kGroupWaves ? red_s[lane] : A::zero();
+        tv = A::sum_scan(tv);
+        if (lane < kGroupWaves) wave_off[lane + 1] = tv;
+        if (lane == 0) wave_off[0] = A::zero();
+    }
+    __syncthreads();
+    const T off = wave_off[wv];
+    const T excl = A::up1(A::add(off, sw), off);
+    if (valid) {
+        Tab* tab = static_cast<Tab*>(a.tab);
+        tab[t].f = f;
+        if constexpr (F64) tab[t].off = excl;
+        else { tab[t].off_hi = excl.hi; tab[t].off_lo = excl.lo; }
+    }
+    ex = wave_sum(ex);
+    ey = wave_sum(ey);
+    if (lane == 0) { red_x[wv] = ex; red_y[wv] = ey; }
+    __syncthreads();
+    if (tid == 0) {
+        Fv sx = red_x[0], sy = red_y[0];
+        for (int w = 1; w < kGroupWaves; ++w) { sx = sx + red_x[w]; sy = sy + red_y[w]; }
+        const T S = wave_off[kGroupWaves];
+        GRec gr{};
+        if constexpr (F64) {
+            gr.m = gm; gr.s = S;
+        } else {
+            gr.smax = gm; gr.s_hi = S.hi; gr.s_lo = S.lo;
+        }
+        gr.sx = sx;
+        gr.sy = sy;
+        static_cast<GRec*>(a.grec)[g] = gr;
+    }
+}
+
+template <int DT>
+__global__ __launch_bounds__(kTopThreads) void combine_top_kernel(StepArgs a)
+{
+    constexpr bool F64 = DT == PF_F64;
+    constexpr int NW = kTopThreads / 64;
+    using A = CombAcc<F64 ? PF_F64 : PF_F32>;
+    using T = typename A::T;
+    using Tab = typename std::conditional<F64, TileTab64, TileTab32>::type;
+    using GRec = typename std::conditional<F64, GroupRec64, GroupRec32>::type;
+    using GTab = typename std::conditional<F64, GroupTab64, GroupTab32>::type;
+    using Fv = typename std::conditional<F64, double, float>::type;
+    using Mx = typename std::conditional<F64, double, int>::type;
+    __shared__ Mx red_m[NW];
+    __shared__ T red_s[NW];
+    __shared__ T wave_off[NW + 1];
+    __shared__ Fv red_x[NW], red_y[NW];
+    __shared__ int red_e[NW];
+
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int n = (int)a.n;
+    const int ng = (a.ntiles + kGroupTiles - 1) / kGroupTiles;
+    const bool valid = tid < ng;
+    GRec gr{};
+    if (valid) gr = static_cast<const GRec*>(a.grec)[tid];
+    Mx m = F64 ? (Mx)-INFINITY : (Mx)INT32_MIN;
+    if (valid) {
+        if constexpr (F64) m = gr.m; else m = gr.smax;
+    }
+    m = wave_max(m);
+    if (lane == 0) red_m[wv] = m;
+    __syncthreads();
+    Mx gm = red_m[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) gm = red_m[w] > gm ? red_m[w] : gm;
+
+    Fv c = 0, ex = 0, ey = 0;
+    T v = A::zero();
+    if (valid) {
+        if constexpr (F64) {
+            c = exp(gr.m - gm);
+            v = c * gr.s;
+        } else {
+            c = __builtin_amdgcn_exp2f((float)(gr.smax - gm) * a.beta);
+            v = ff_mul_f(ff{gr.s_hi, gr.s_lo}, c);
+        }
+        ex = c * gr.sx;
+        ey = c * gr.sy;
+    }
+    const T sw = A::sum_scan(v);
+    if (lane == 63) red_s[wv] = sw;
+    __syncthreads();
+    if (wv == 0) {
+        T tv = lane < NW ? red_s[lane] : A::zero();
+        tv = A::sum_scan(tv);
+        if (lane < NW) wave_off[lane + 1] = tv;
+        if (lane == 0) wave_off[0] = A::zero();
+    }
+    __syncthreads();
+    const T off = wave_off[wv];
+    const T incl = A::add(off, sw);
+    const T excl = A::up1(incl, off);
+    const T Z = wave_off[NW];
+    const SlotMap<F64> smap(a, Z);
+    // end slot of every group (from the next group's offset), made
+    // non-decreasing; the last group ends at N
+    int e = 0;
+    if (valid) e = tid == ng - 1 ? n : smap.end_of(incl, n);
+    int sm = wave_incl_scan<OpMax>(e);
+    if (lane == 63) red_e[wv] = sm;
+    ex = wave_sum(ex);
+    ey = wave_sum(ey);
+    if (lane == 0) { red_x[wv] = ex; red_y[wv] = ey; }
+    __syncthreads();
+    int carry = 0;  // end slot of the previous waves' groups
+    for (int w = 0; w < wv; ++w) carry = max(carry, red_e[w]);
+    sm = max(sm, carry);
+    const int ep = wave_shift_up1(sm, carry);  // end slot of the previous group
+    if (valid) {
+        GTab gt{};
+        if constexpr (F64) gt.off = excl;
+        else { gt.off_hi = excl.hi; gt.off_lo = excl.lo; }
+        gt.c = c;
+        gt.Eprev = ep;
+        gt.E = sm;
+        static_cast<GTab*>(a.gtab)[tid] = gt;
+    }
+    if (tid == 0) {
+        Fv sx = red_x[0], sy = red_y[0];
+        for (int w = 1; w < NW; ++w) { sx = sx + red_x[w]; sy = sy + red_y[w]; }
+        Tab* tab = static_cast<Tab*>(a.tab);
+        if constexpr (F64) tab[a.ntiles].off = Z;
+        else { tab[a.ntiles].off_hi = Z.hi; tab[a.ntiles].off_lo = Z.lo; }
+        write_block<DT>(a, Z, gm, sx, sy, smap);
+    }
+}
+
+template <int DT>
+__global__ __launch_bounds__(kGroupTiles) void combine_finish_kernel(StepArgs a)
+{
+    constexpr bool F64 = DT == PF_F64;
+    using A = CombAcc<F64 ? PF_F64 : PF_F32>;
+    using T = typename A::T;
+    using Tab = typename std::conditional<F64, TileTab64, TileTab32>::type;
+    using GTab = typename std::conditional<F64, GroupTab64, GroupTab32>::type;
+    using Fv = typename std::conditional<F64, double, float>::type;
+    __shared__ T s_off[kGroupTiles];
+    __shared__ int red_e[kGroupWaves];
+
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int n = (int)a.n;
+    const int g = blockIdx.x, t0 = g * kGroupTiles, t = t0 + tid;
+    const int mt = min(kGroupTiles, a.ntiles - t0);
+    const bool valid = tid < mt;
+    const GTab gt = static_cast<const GTab*>(a.gtab)[g];
+    Tab* tab = static_cast<Tab*>(a.tab);
+    T W = A::zero();
+    Fv fg = 0;
+    if (valid) {
+        if constexpr (F64) W = tab[t].off; else W = ff{tab[t].off_hi, tab[t].off_lo};
+        fg = tab[t].f;
+    }
+    T off;
+    Fv f;
+    if constexpr (F64) {
+        off = gt.off + gt.c * W;
+        f = gt.c * fg;
+    } else {
+        off = ff_add(ff{gt.off_hi, gt.off_lo}, ff_mul_f(W, gt.c));
+        f = gt.c * fg;
+    }
+    s_off[tid] = off;
+    __syncthreads();
+    // the end slot of tile t comes from off_{t+1}; the group's last tile
+    // ends where the group does
+    const DevBlock* b = a.blk;
+    int e = 0;
+    if (valid) {
+        if (tid == mt - 1) {
+            e = gt.E;
+        } else {
+            if constexpr (F64) {
+                e = slot_end_of(b->R * s_off[tid + 1] + (-b->u0), n);
+            } else {
+                const ff R{b->R_hi, b->R_lo}, mu0{-b->u0_hi, -b->u0_lo};
+                e = slot_end_of(ff_add(ff_mul(R, s_off[tid + 1]), mu0), n);
+            }
+        }
+        e = min(max(e, gt.Eprev), gt.E);
+    }
+    int sm = wave_incl_scan<OpMax>(e);
+    if (lane == 63) red_e[wv] = sm;
+    __syncthreads();
+    for (int w = 0; w < wv; ++w) sm = max(sm, red_e[w]);
+    if (valid) {
+        tab[t].f = f;
+        tab[t].E = sm;
+        if constexpr (F64) tab[t].off = off;
+        else { tab[t].off_hi = off.hi; tab[t].off_lo = off.lo; }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1353,7 +1651,7 @@ __global__ __launch_bounds__(kBlock) void gather_est_kernel(const StepArgs* args
 template <typename Arg>
 static hipError_t launch1(void (*kernel)(Arg), dim3 g, dim3 b, hipStream_t s, const KTiming& tm, Arg arg)
 {
-    if (tm.start) {
+    if (tm.start || tm.stop) {
         void* args[] = {&arg};
         return hipExtLaunchKernel(reinterpret_cast<const void*>(kernel), g, b, args, 0, s, tm.start, tm.stop, 0);
     }
@@ -1416,13 +1714,26 @@ static hipError_t launch_pass_c_t(const StepArgs& a, hipStream_t s, const KTimin
 }
 
 template <int DT>
+static hipError_t launch_combine_grouped(const StepArgs& a, hipStream_t s, const KTiming& tm)
+{
+    const dim3 gg((unsigned)((a.ntiles + kGroupTiles - 1) / kGroupTiles));
+    KTiming t0, t2;
+    t0.start = tm.start;
+    t2.stop = tm.stop;
+    hipError_t e = launch1(combine_group_kernel<DT>, gg, dim3(kGroupTiles), s, t0, a);
+    if (e == hipSuccess) e = launch1(combine_top_kernel<DT>, dim3(1), dim3(kTopThreads), s, KTiming(), a);
+    if (e == hipSuccess) e = launch1(combine_finish_kernel<DT>, gg, dim3(kGroupTiles), s, t2, a);
+    return e;
+}
+
+template <int DT>
 static hipError_t launch_combine_t(const StepArgs& a, hipStream_t s, const KTiming& tm)
 {
     switch (comb_class(a.ntiles)) {
     case 0: return launch1(combine_kernel<DT, 1, 256>, dim3(1), dim3(256), s, tm, a);
     case 1: return launch1(combine_kernel<DT, 1, 1024>, dim3(1), dim3(1024), s, tm, a);
     case 2: return launch1(combine_kernel<DT, 4, 1024>, dim3(1), dim3(1024), s, tm, a);
-    default: return launch1(combine_kernel<DT, 16, 1024>, dim3(1), dim3(1024), s, tm, a);
+    default: return launch_combine_grouped<DT>(a, s, tm);
     }
 }
 
@@ -1467,7 +1778,7 @@ static hipError_t launch_batch_combine_t(int cls, const BatchArgs& b, int count,
     case 0: return launch1(combine_batch_kernel<DT, 1, 256>, g, dim3(256), s, tm, b);
     case 1: return launch1(combine_batch_kernel<DT, 1, 1024>, g, dim3(1024), s, tm, b);
     case 2: return launch1(combine_batch_kernel<DT, 4, 1024>, g, dim3(1024), s, tm, b);
-    default: return launch1(combine_batch_kernel<DT, 16, 1024>, g, dim3(1024), s, tm, b);
+    default: return hipErrorInvalidValue;  // class 3 combines per filter (launch_combine)
     }
 }
 

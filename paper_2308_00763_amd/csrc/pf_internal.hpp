@@ -71,11 +71,33 @@ struct TileTab32 {
     int32_t E;
 };
 
+// Grouped combine (filters of more than 4096 tiles, groups of 1024 tiles):
+// per group, its maximum and sums relative to it, then its carried offset,
+// factor e^{m_g - M} and end slots.
+struct GroupRec64 {
+    double m, s, sx, sy;
+};
+struct GroupRec32 {
+    int32_t smax;
+    float s_hi, s_lo, sx, sy;
+    int32_t pad[3];
+};
+struct GroupTab64 {
+    double off, c;
+    int32_t Eprev, E;
+    int32_t pad[2];
+};
+struct GroupTab32 {
+    float off_hi, off_lo, c;
+    int32_t Eprev, E;
+    int32_t pad[3];
+};
+
 // Workspace layout; offsets in bytes from the workspace base.
 struct Layout {
     int64_t n, n_pad;
     int tile, ntiles;
-    size_t blk, rec, tab, sx, sy, px, py, q, dg_s, dg_w, dg_anc, cdf, s_all, total;
+    size_t blk, rec, tab, grec, gtab, sx, sy, px, py, q, dg_s, dg_w, dg_anc, cdf, s_all, total;
 };
 
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -95,6 +117,9 @@ inline Layout make_layout(const pf_params& p)
     L.blk = o; o += 256;
     L.rec = o; o = align256(o + rec * (size_t)L.ntiles);
     L.tab = o; o = align256(o + tab * (size_t)(L.ntiles + 1));
+    const size_t ngroups = ((size_t)L.ntiles + 1023) / 1024;
+    L.grec = o; o = align256(o + 32 * ngroups);
+    L.gtab = o; o = align256(o + 32 * ngroups);
     L.sx = o; o = align256(o + elt * (size_t)L.n_pad);
     L.sy = o; o = align256(o + elt * (size_t)L.n_pad);
     L.px = o; o = align256(o + elt * (size_t)L.n_pad);
@@ -136,6 +161,8 @@ struct StepArgs {
     DevBlock* blk;
     void* rec;
     void* tab;
+    void* grec;         // grouped combine: per-group records and table
+    void* gtab;
     void* sx;
     void* sy;
     void* px;
