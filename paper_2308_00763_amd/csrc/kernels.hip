@@ -641,9 +641,10 @@ __global__ __launch_bounds__(kTile / PPT) void pass_a_kernel(StepArgs a)
 // the slot coordinate is the affine y = (R off_t - u0) + (R f_t) q, capped at
 // y_max = R off_{t+1} - u0, whose end slot is the tile's end slot E_t (the
 // combine evaluates exactly that expression), so tiles join without gaps.
-// The reduced modes evaluate y in two-float arithmetic (about 44 bits); the
-// double mode in double (the slot coordinate of N <= 2^28 strata then carries
-// an error far below the 1e-12 resolution of the distribution).
+// The double mode evaluates y in double (the slot coordinate of N <= 2^28
+// strata then carries an error far below the 1e-12 resolution of the
+// distribution); the reduced modes form the tile's base in two-float
+// arithmetic (about 44 bits) and each particle's offset from it in float.
 
 __device__ __forceinline__ int slot_end_of(double y, int n)
 {
@@ -682,25 +683,31 @@ struct TileSlots<PF_F64> {
     }
 };
 
+// Reduced modes: the tile's base coordinate R off_t - u0 (two-float, up to N)
+// is split once into its integer part B and a float fraction; a particle's
+// coordinate relative to B, frac + (R f_t) q, is at most the tile's slot count,
+// so float resolves it to ~1e-4 of a slot, and its end slot is B plus the
+// floor, capped at the tile's end slot.
 template <>
 struct TileSlots<PF_F32> {
-    ff base, scale, ymax;
-    int E, Eprev;
+    float frac, scale;
+    int B, cap, E, Eprev;
     __device__ TileSlots(const StepArgs& a, int t)
     {
         const TileTab32* tab = static_cast<const TileTab32*>(a.tab);
         const ff R{a.blk->R_hi, a.blk->R_lo}, mu0{-a.blk->u0_hi, -a.blk->u0_lo};
-        base = ff_add(ff_mul(R, ff{tab[t].off_hi, tab[t].off_lo}), mu0);
-        scale = ff_mul_f(R, tab[t].f);
-        ymax = ff_add(ff_mul(R, ff{tab[t + 1].off_hi, tab[t + 1].off_lo}), mu0);
+        const ff base = ff_add(ff_mul(R, ff{tab[t].off_hi, tab[t].off_lo}), mu0);
+        B = (int)ff_floor(base);
+        frac = (base.hi - (float)B) + base.lo;
+        scale = ff_mul_f(R, tab[t].f).hi;
         E = tab[t].E;
         Eprev = t > 0 ? tab[t - 1].E : 0;
+        cap = E - B;
     }
-    __device__ int operator()(const void* q, int i, int n) const
+    __device__ int operator()(const void* q, int i, int /*n*/) const
     {
-        ff y = ff_add(base, ff_mul_f(scale, static_cast<const float*>(q)[i]));
-        y = ff_min(y, ymax);
-        return slot_end_of(y, n);
+        const float y = __builtin_fmaf(scale, static_cast<const float*>(q)[i], frac);
+        return B + min((int)floorf(y) + 1, cap);
     }
 };
 
@@ -1716,7 +1723,9 @@ static hipError_t launch_pass_c_t(const StepArgs& a, hipStream_t s, const KTimin
 template <int DT>
 static hipError_t launch_combine_grouped(const StepArgs& a, hipStream_t s, const KTiming& tm)
 {
-    const dim3 gg((unsigned)((a.ntiles + kGroupTiles - 1) / kGroupTiles));
+    const int ng = (a.ntiles + kGroupTiles - 1) / kGroupTiles;
+    if (ng > kTopThreads) return hipErrorInvalidValue;  // N <= 2^28 keeps ng <= 256
+    const dim3 gg((unsigned)ng);
     KTiming t0, t2;
     t0.start = tm.start;
     t2.stop = tm.stop;
