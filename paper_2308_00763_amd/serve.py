@@ -10,7 +10,9 @@ The server:
     budget check); otherwise the stream waits in a FIFO queue (first fit);
   * rejects at submission a stream whose parameters the library refuses;
   * at every tick steps, with one batched launch per slot pool, every admitted
-    stream that has a frame waiting (one frame per stream per tick, in order);
+    stream that has a frame waiting (one frame per stream per tick, in order;
+    a heap of the streams' next frame arrival times finds them without
+    scanning the idle ones);
   * measures per-frame latency: frame arrival to estimate ready;
   * evicts a stream whose frames stop arriving for longer than a timeout, and
     a stream whose step failed, reclaiming the slot either way.
@@ -73,12 +75,15 @@ class StreamResult:
 class Scheduler:
     """Continuous-batching loop over a backend (see module docstring)."""
 
-    def __init__(self, backend, clock=time.perf_counter, stall_timeout: float = 1.0):
+    def __init__(self, backend, clock=time.perf_counter, stall_timeout: float = 1.0,
+                 stall_poll: float = 0.001):
         self.backend = backend
         self.clock = clock
         self.stall_timeout = stall_timeout
+        self.stall_poll = stall_poll
         self.pending = []            # heap of (arrival, sid, request) not yet arrived
         self.queue = deque()         # arrived requests waiting for a slot
+        self.due = []                # heap of (next frame's arrival, sid) of admitted streams
         self.live = {}               # sid -> _Live
         self.results = {}            # sid -> StreamResult
         self.latencies = []          # per processed frame: ready - arrival (seconds)
@@ -114,6 +119,7 @@ class Scheduler:
                 waiting.append(req)
                 continue
             self.live[req.sid] = _Live(req, slot, now)
+            heapq.heappush(self.due, (req.arrival + 1.0 / req.fps, req.sid))
         self.queue = waiting
 
     def _finish(self, lv: _Live, status: str, reason: str = ""):
@@ -129,22 +135,30 @@ class Scheduler:
         now = self.clock()
         self._arrivals(now)
         self._admit(now)
+        # streams whose next frame has arrived, from the heap of due times
         work = []
-        for lv in list(self.live.values()):
+        retry = []
+        while self.due and self.due[0][0] <= now:
+            _, sid = heapq.heappop(self.due)
+            lv = self.live.get(sid)
+            if lv is None:
+                continue
             r = lv.req
             i = lv.next_frame
             if i >= r.n_frames:
                 self._finish(lv, "done")
                 continue
             t_arr = r.arrival + i / r.fps
-            if t_arr > now:
-                continue
             fr = r.frame(i)
             if fr is None:  # the source stalls: evict once it is late by the timeout
                 if now - t_arr > self.stall_timeout:
                     self._finish(lv, "evicted", f"frame {i} late by more than {self.stall_timeout} s")
+                else:
+                    retry.append((now + self.stall_poll, sid))
                 continue
             work.append((lv, fr, t_arr))
+        for item in retry:
+            heapq.heappush(self.due, item)
         if not work:
             return 0
         t0 = self.clock()
@@ -163,6 +177,8 @@ class Scheduler:
             lv.next_frame += 1
             if lv.next_frame >= lv.req.n_frames:
                 self._finish(lv, "done")
+            else:
+                heapq.heappush(self.due, (lv.req.arrival + lv.next_frame / lv.req.fps, lv.req.sid))
         return len(work)
 
     def idle(self):
