@@ -41,6 +41,9 @@ PEAK_HBM = 8.0e12                      # bytes per second
 # and the likelihood division by their double versions.
 PASS_A_SLOTS = {"f64": 277, "f32": 123, "f16": 122, "bf16": 124}
 STATE_BYTES = {"f64": 32, "f32": 16, "f16": 8, "bf16": 8}
+# pass C per update: read the propagated position and the tile-local prefix
+# sum, write the resampled position
+PASS_C_BYTES = {"f64": 16 + 8 + 16, "f32": 8 + 4 + 8, "f16": 4 + 4 + 4, "bf16": 4 + 4 + 4}
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "pass_a_f16_disk1024_n1m_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2308_00763_amd", "csrc", f)
                   for f in ("kernels.hip", "philox.hpp", "wave.hpp", "pf_internal.hpp")]
@@ -343,6 +346,31 @@ def run_accuracy(pf, torch, pfsynth, modes):
                          f"N={w.n_particles}", modes=res)
 
 
+def run_large(pf, torch, pfsynth, args, modes):
+    """The second single-filter workload (default 2^24 particles, r = 8) in
+    every mode, with each mode's track RMS against FP64."""
+    wl = pfsynth.WORKLOADS[args.large]
+    log(f"[bench] generating {wl.name}: {wl.frames} frames {wl.width}x{wl.height}")
+    vl = pfsynth.workload_video(wl)
+    fl = torch.from_numpy(vl.frames).to("cuda:0")
+    ls, lw = min(args.steps, wl.frames - 6), 5
+    lres = {}
+    for dt in modes:
+        secs, _ = run_mode(pf, torch, fl, vl.centres, wl, dt, ls, lw, profile=False)
+        _, prof = run_mode(pf, torch, fl, vl.centres, wl, dt, ls, lw, profile=True)
+        lres[dt] = dict(ms_per_step=1e3 * secs / ls, updates_per_s=wl.n_particles * ls / secs,
+                        pass_a_us=1e3 * prof[0] / prof[3], combine_us=1e3 * prof[1] / prof[3],
+                        pass_c_us=1e3 * prof[2] / prof[3])
+    if not args.no_track and "f64" in modes:
+        ref = track(pf, fl, vl.centres, wl, "f64", wl.frames - 1)
+        for dt in modes:
+            est = ref if dt == "f64" else track(pf, fl, vl.centres, wl, dt, wl.frames - 1)
+            lres[dt]["track_rms_vs_f64_px"] = float(np.sqrt(np.mean(np.sum((est - ref) ** 2, axis=1))))
+    return dict(workload=f"{wl.name}: {wl.width}x{wl.height}, {wl.frames} frames, disk r={wl.radius}, "
+                         f"noise sigma {wl.noise_sigma}, N={wl.n_particles}, one filter",
+                steps=ls, warmup=lw, modes=lres)
+
+
 def cpu_baseline(w, vid, budget_s):
     """The FP64 oracle (sequential C, one thread) on the first steps of the
     same video at the same N, as many steps as fit in about budget_s."""
@@ -454,10 +482,10 @@ def main():
                     work_per_update=PASS_A_SLOTS[head], work_unit="VALU lane slots")
     else:
         c_s = r["pass_c_us"] * 1e-6
-        byts = STATE_BYTES[head] * w.n_particles / 2  # pass C's share: read + write of positions
-        achieved = byts / c_s
+        achieved = PASS_C_BYTES[head] * w.n_particles / c_s
         roof = dict(bound="hbm", kernel="pass_c", achieved=achieved / 1e9, peak=PEAK_HBM / 1e9,
-                    unit="GB/s", frac=achieved / PEAK_HBM, traffic=None, kernel_us=r["pass_c_us"])
+                    unit="GB/s", frac=achieved / PEAK_HBM, traffic=None, kernel_us=r["pass_c_us"],
+                    work_per_update=PASS_C_BYTES[head], work_unit="bytes")
 
     out = {
         "metric": "particle-updates/sec FP16 vs FP64 at <=0.5px track error; p99 frame latency",
@@ -482,50 +510,34 @@ def main():
         out["speedup_f16_vs_f64"] = res["f64"]["seconds"] / res.get("f16", res["f64"])["seconds"]
     if "f32" in res and "f16" in res:
         out["speedup_f16_vs_f32"] = res["f32"]["seconds"] / res["f16"]["seconds"]
+    def section(key, fn):
+        # an optional section that fails is recorded, and the headline line
+        # is still printed
+        try:
+            out[key] = fn()
+            log(f"[bench] {key}: {json.dumps(out[key])}")
+        except Exception as e:
+            log(f"[bench] {key} failed: {e!r}")
+            out[key] = {"error": repr(e)}
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+
     if not args.no_ablation:
-        out["ablation"] = run_ablation(pf, torch, frames_dev, vid.centres, w, min(args.steps, 40),
-                                       args.warmup)
-        log(f"[bench] ablation: {json.dumps(out['ablation'])}")
-    if not args.no_ablation:
-        out["resamplers"] = run_resamplers(pf, torch, frames_dev, vid.centres, w, min(args.steps, 40),
-                                           args.warmup)
-        log(f"[bench] resamplers: {json.dumps(out['resamplers'])}")
+        section("ablation", lambda: run_ablation(pf, torch, frames_dev, vid.centres, w,
+                                                 min(args.steps, 40), args.warmup))
+        section("resamplers", lambda: run_resamplers(pf, torch, frames_dev, vid.centres, w,
+                                                     min(args.steps, 40), args.warmup))
     if not args.no_track:
-        out["accuracy"] = run_accuracy(pf, torch, pfsynth, modes)
-        log(f"[bench] accuracy: {out['accuracy']}")
+        section("accuracy", lambda: run_accuracy(pf, torch, pfsynth, modes))
     if args.large and args.large != "none":
-        wl = pfsynth.WORKLOADS[args.large]
-        log(f"[bench] generating {wl.name}: {wl.frames} frames {wl.width}x{wl.height}")
-        vl = pfsynth.workload_video(wl)
-        fl = torch.from_numpy(vl.frames).to("cuda:0")
-        ls, lw = min(args.steps, wl.frames - 6), 5
-        lres = {}
-        for dt in modes:
-            secs, _ = run_mode(pf, torch, fl, vl.centres, wl, dt, ls, lw, profile=False)
-            lres[dt] = dict(ms_per_step=1e3 * secs / ls, updates_per_s=wl.n_particles * ls / secs)
-        if not args.no_track and "f64" in modes:
-            ref = track(pf, fl, vl.centres, wl, "f64", wl.frames - 1)
-            for dt in modes:
-                est = ref if dt == "f64" else track(pf, fl, vl.centres, wl, dt, wl.frames - 1)
-                lres[dt]["track_rms_vs_f64_px"] = float(np.sqrt(np.mean(np.sum((est - ref) ** 2, axis=1))))
-        log(f"[bench] {wl.name}: {lres}")
-        out["large"] = dict(workload=f"{wl.name}: {wl.width}x{wl.height}, {wl.frames} frames, disk r={wl.radius}, "
-                                     f"noise sigma {wl.noise_sigma}, N={wl.n_particles}, one filter",
-                            steps=ls, warmup=lw, modes=lres)
-        del fl
+        section("large", lambda: run_large(pf, torch, pfsynth, args, modes))
     if args.fleet:
-        fr = run_fleet(pf, torch, pfsynth, args.fleet, 256, 50, 40, 5)
-        log(f"[bench] fleet: {fr}")
-        out["fleet"] = fr
-        torch.cuda.empty_cache()
+        section("fleet", lambda: run_fleet(pf, torch, pfsynth, args.fleet, 256, 50, 40, 5))
     if args.serve_seconds > 0:
-        sv = run_serving(pf, torch, pfsynth, args.serve_seconds, 10.0)
-        log(f"[bench] serving: {sv}")
-        out["serving"] = sv
-        torch.cuda.empty_cache()
+        section("serving", lambda: run_serving(pf, torch, pfsynth, args.serve_seconds, 10.0))
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(w, vid, args.cpu_budget)
+        section("cpu_baseline", lambda: cpu_baseline(w, vid, args.cpu_budget))
     print(json.dumps(out), flush=True)
 
 
