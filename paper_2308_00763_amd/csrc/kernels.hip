@@ -684,10 +684,11 @@ struct TileSlots<PF_F64> {
 };
 
 // Reduced modes: the tile's base coordinate R off_t - u0 (two-float, up to N)
-// is split once into its integer part B and a float fraction; a particle's
-// coordinate relative to B, frac + (R f_t) q, is at most the tile's slot count,
-// so float resolves it to ~1e-4 of a slot, and its end slot is B plus the
-// floor, capped at the tile's end slot.
+// is split once into B = floor(hi), an integer that float holds exactly, and
+// the float remainder frac = (hi - B) + lo (within about one of zero); a
+// particle's coordinate relative to B, frac + (R f_t) q, is at most the
+// tile's slot count plus one, so float resolves it to ~1e-4 of a slot, and
+// its end slot is B plus the floor, capped at the tile's end slot.
 template <>
 struct TileSlots<PF_F32> {
     float frac, scale;
@@ -697,8 +698,9 @@ struct TileSlots<PF_F32> {
         const TileTab32* tab = static_cast<const TileTab32*>(a.tab);
         const ff R{a.blk->R_hi, a.blk->R_lo}, mu0{-a.blk->u0_hi, -a.blk->u0_lo};
         const ff base = ff_add(ff_mul(R, ff{tab[t].off_hi, tab[t].off_lo}), mu0);
-        B = (int)ff_floor(base);
-        frac = (base.hi - (float)B) + base.lo;
+        const float bh = floorf(base.hi);
+        B = (int)bh;
+        frac = (base.hi - bh) + base.lo;
         scale = ff_mul_f(R, tab[t].f).hi;
         E = tab[t].E;
         Eprev = t > 0 ? tab[t - 1].E : 0;
@@ -1361,8 +1363,11 @@ __device__ __forceinline__ void pass_c_tile(const StepArgs& a, int t, PassCLds<D
     for (int r = 0; r < kTile / BC; ++r) {
         const int k = tid + r * BC;
         if (k < tt) {
+            // local end slot, at least 0: a particle whose end slot precedes
+            // the tile's first slot (the combine's prefix maximum can raise
+            // it) owns no slot, and the merge's first cut stays at 0
             const int e = k == tt - 1 ? ts.E : ts(a.q, first + k, n);
-            s_e[k] = e - ts.Eprev;
+            s_e[k] = max(e - ts.Eprev, 0);
             s_x[k] = px[first + k];
             s_y[k] = py[first + k];
         }
