@@ -275,9 +275,11 @@ ABLATION = [
     ("naive likelihood + resampling, 128 threads",
      dict(naive_likelihood=True, naive_resample=True, threads_c=128)),
     ("pass A 128 threads (8 particles each)", dict(threads_a=128)),
+    ("pass A 256 threads (4 particles each)", dict(threads_a=256)),
     ("pass A 512 threads (2 particles each)", dict(threads_a=512)),
     ("pass C 64 threads", dict(threads_c=64)),
     ("pass C 128 threads", dict(threads_c=128)),
+    ("pass C 256 threads", dict(threads_c=256)),
     ("pass C 512 threads", dict(threads_c=512)),
     ("pass C 1024 threads", dict(threads_c=1024)),
 ]

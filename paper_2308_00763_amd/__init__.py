@@ -120,12 +120,12 @@ def _check(rc: int):
         raise PfError(rc, lib().pf_last_error().decode())
 
 
-def threads_field(threads: int) -> int:
-    """Field value of a threads-per-workgroup flag (0 for the default 256)."""
-    if threads in (0, 256):
+def threads_field(threads) -> int:
+    """Field value of a threads-per-workgroup flag (None: 0, the default)."""
+    if threads is None:
         return 0
     v = int(threads).bit_length() - 6
-    if threads <= 0 or threads != 1 << (v + 5):
+    if threads <= 0 or threads != 1 << (v + 5) or not 1 <= v <= 5:
         raise ValueError(f"threads per workgroup must be a power of two in [64, 1024], got {threads}")
     return v
 
@@ -133,7 +133,7 @@ def threads_field(threads: int) -> int:
 def make_params(n, width, height, dtype="f64", radius=5, x0=0.0, y0=0.0, drift=(1.0, -2.0),
                 sigma=(5.0, 2.0), seed=0, stream_id=0, fg=228, bg=100, kappa=50.0,
                 lik_norm=PF_LIK_MEAN, diagnostics=False, naive_likelihood=False,
-                naive_resample=False, threads_a=256, threads_c=256,
+                naive_resample=False, threads_a=None, threads_c=None,
                 metropolis_steps=0, gumbel_max=False) -> pf_params:
     dt = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
     if not 0 <= int(metropolis_steps) <= 255:

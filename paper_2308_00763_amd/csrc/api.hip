@@ -142,7 +142,7 @@ int check_params(const pf_params* p)
     return PF_OK;
 }
 
-int threads_of(uint32_t field) { return field == 0 ? 256 : 1 << (field + 5); }
+int threads_of(uint32_t field, int dflt) { return field == 0 ? dflt : 1 << (field + 5); }
 
 int live(pf_filter* h)
 {
@@ -248,8 +248,8 @@ void setup_filter(pf_filter* h, const pf_params& pr, uint8_t* ws, hipStream_t st
     }
     a.naive_lik = (p->flags & PF_FLAG_NAIVE_LIKELIHOOD) ? 1 : 0;
     a.naive_res = (p->flags & PF_FLAG_NAIVE_RESAMPLE) ? 1 : 0;
-    a.threads_a = threads_of((p->flags >> PF_THREADS_A_SHIFT) & 0xF);
-    a.threads_c = threads_of((p->flags >> PF_THREADS_C_SHIFT) & 0xF);
+    a.threads_a = threads_of((p->flags >> PF_THREADS_A_SHIFT) & 0xF, kBlockA);
+    a.threads_c = threads_of((p->flags >> PF_THREADS_C_SHIFT) & 0xF, 0);
     a.cdf = a.naive_res ? at(h, L.cdf) : nullptr;
     a.mh_steps = 0;
     a.gumbel = (p->flags & PF_FLAG_GUMBEL_MAX) ? 1 : 0;

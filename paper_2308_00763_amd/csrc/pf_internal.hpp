@@ -9,7 +9,8 @@
 
 namespace pf {
 
-constexpr int kBlock = 256;        // threads per workgroup of pass C and the small kernels
+constexpr int kBlock = 256;        // threads per workgroup of the small kernels
+constexpr int kBlockC = 256;       // threads per pass-C workgroup in batches (one tile)
 constexpr int kWaves = kBlock / 64;
 constexpr int kTile = 1024;        // particles per tile (one pass-A and one pass-C workgroup)
 constexpr int kPPT = 4;            // particles per pass-A thread
@@ -175,7 +176,7 @@ struct StepArgs {
     int32_t naive_lik;  // disk sums read every pixel from the frame
     int32_t naive_res;  // normalised CDF + per-slot binary search instead of pass C
     int32_t threads_a;  // pass A threads per tile: 128, 256 (default) or 512
-    int32_t threads_c;  // pass C / naive resampler threads per workgroup: 64 .. 1024
+    int32_t threads_c;  // pass C / naive resampler threads per workgroup: 64 .. 1024 (0: by tile count)
     void* cdf;          // naive resampler: normalised cumulative weights
     int32_t mh_steps;   // Metropolis resampling: steps per slot (0: systematic)
     int32_t gumbel;     // Gumbel-max multinomial resampling

@@ -23,6 +23,7 @@ VARIANTS = [
     dict(threads_a=512),
     dict(threads_c=64),
     dict(threads_c=128),
+    dict(threads_c=256),
     dict(threads_c=512),
     dict(threads_c=1024),
     dict(naive_likelihood=True, naive_resample=True, threads_a=128, threads_c=128),
@@ -86,7 +87,8 @@ def _free_run(dtype, n, **variant):
 
 
 @pytest.mark.parametrize("variant", [dict(naive_likelihood=True), dict(threads_c=64),
-                                     dict(threads_c=128), dict(threads_c=512), dict(threads_c=1024)],
+                                     dict(threads_c=128), dict(threads_c=256), dict(threads_c=512),
+                                     dict(threads_c=1024)],
                          ids=lambda v: "-".join(f"{k}={x}" for k, x in v.items()))
 @pytest.mark.parametrize("dtype", ["f64", "f16"])
 def test_variants_with_the_same_arithmetic_are_bit_identical(variant, dtype):
