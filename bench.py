@@ -507,6 +507,7 @@ def main():
                    "n_particles": w.n_particles, "frame": [w.height, w.width], "radius": w.radius},
         "modes": res,
         "roofline": roof,
+        "kernel_source_sha256": kernel_source_hash(),
     }
     if "f64" in res:
         out["speedup_f16_vs_f64"] = res["f64"]["seconds"] / res.get("f16", res["f64"])["seconds"]
