@@ -1638,12 +1638,12 @@ __global__ __launch_bounds__(NT) void combine_batch_kernel(BatchArgs b)
 }
 
 template <int DT>
-__global__ __launch_bounds__(kBlockC) void pass_c_batch_kernel(BatchArgs b)
+__global__ __launch_bounds__(pass_c_threads(DT, 1 << 30)) void pass_c_batch_kernel(BatchArgs b)
 {
     __shared__ PassCLds<DT> lds;
     const int e = b.tile_entry[blockIdx.x];
     const StepArgs a = batch_args(b, e);
-    pass_c_tile<DT, kBlockC>(a, (int)blockIdx.x - b.entries[e].tile_base, lds);
+    pass_c_tile<DT, pass_c_threads(DT, 1 << 30)>(a, (int)blockIdx.x - b.entries[e].tile_base, lds);
 }
 
 __global__ __launch_bounds__(kBlock) void gather_est_kernel(const StepArgs* args, int n, double* out)
@@ -1717,9 +1717,10 @@ static hipError_t launch_pass_c_t(const StepArgs& a, hipStream_t s, const KTimin
         }
     }
     // default: 512 threads while the grid is at most four tiles per CU
-    // (latency-bound), else 256 (more tiles in flight per CU); the result
-    // does not depend on the choice
-    const int bc = a.threads_c ? a.threads_c : (a.ntiles <= 1024 ? 512 : 256);
+    // (latency-bound) and in the FP64 mode (whose 28 KB of LDS per tile
+    // caps the tiles per CU), else 256 (more tiles in flight per CU); the
+    // result does not depend on the choice
+    const int bc = a.threads_c ? a.threads_c : pass_c_threads(DT, a.ntiles);
     switch (bc) {
     case 64: return launch1(pass_c_kernel<DT, 64>, g, dim3(64), s, tm, a);
     case 128: return launch1(pass_c_kernel<DT, 128>, g, dim3(128), s, tm, a);
@@ -1812,7 +1813,8 @@ hipError_t launch_batch_combine(int dtype, int cls, const BatchArgs& b, int coun
 
 hipError_t launch_batch_pass_c(int dtype, const BatchArgs& b, int tiles, hipStream_t s, const KTiming& tm)
 {
-    PF_DISPATCH(dtype, launch1(pass_c_batch_kernel<DT>, dim3((unsigned)tiles), dim3(kBlockC), s, tm, b))
+    PF_DISPATCH(dtype, launch1(pass_c_batch_kernel<DT>, dim3((unsigned)tiles), dim3(pass_c_threads(DT, 1 << 30)),
+                               s, tm, b))
 }
 
 hipError_t launch_gather_est(const StepArgs* args, int n, double* out, hipStream_t s)
