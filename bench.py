@@ -530,6 +530,14 @@ def main():
                                                  min(args.steps, 40), args.warmup))
         section("resamplers", lambda: run_resamplers(pf, torch, frames_dev, vid.centres, w,
                                                      min(args.steps, 40), args.warmup))
+    if not args.no_ablation:
+        def tune_headline():
+            from paper_2308_00763_amd.tune import autotune
+            r = autotune(w.n_particles, w.width, w.height, frames_dev, dtype=head, radius=w.radius,
+                         x0=vid.centres[0][0], y0=vid.centres[0][1], drift=w.drift, sigma=w.sigma)
+            r["default_threads"] = {"pass_a": 256, "pass_c": "512 up to 1024 tiles or FP64, else 256"}
+            return r
+        section("autotune", tune_headline)
     if not args.no_track:
         section("accuracy", lambda: run_accuracy(pf, torch, pfsynth, modes))
     if args.large and args.large != "none":
