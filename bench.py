@@ -39,7 +39,13 @@ PEAK_HBM = 8.0e12                      # bytes per second
 # prefixes 18 + 1, weight 5, maximum / prefix sum / estimate 4.  The double
 # mode replaces the float uniforms, Box-Muller, propagation, rounding, weight
 # and the likelihood division by their double versions.
-PASS_A_SLOTS = {"f64": 277, "f32": 123, "f16": 122, "bf16": 124}
+PASS_A_SLOTS = {"f64": 277, "f32": 123, "f16": 122, "bf16": 124}  # at radius 5
+
+
+def pass_a_slots(dtype, radius):
+    """Algorithmic pass-A slots per update at disk radius r: the radius-5
+    count with its 18 + 1 disk-sum slots replaced by 2 (2r - 1) + 1."""
+    return PASS_A_SLOTS[dtype] - 19 + 2 * (2 * radius - 1) + 1
 STATE_BYTES = {"f64": 32, "f32": 16, "f16": 8, "bf16": 8}
 # pass C per update: read the propagated position and the tile-local prefix
 # sum, write the resampled position
@@ -360,9 +366,12 @@ def run_large(pf, torch, pfsynth, args, modes):
     for dt in modes:
         secs, _ = run_mode(pf, torch, fl, vl.centres, wl, dt, ls, lw, profile=False)
         _, prof = run_mode(pf, torch, fl, vl.centres, wl, dt, ls, lw, profile=True)
+        a_us = 1e3 * prof[0] / prof[3]
         lres[dt] = dict(ms_per_step=1e3 * secs / ls, updates_per_s=wl.n_particles * ls / secs,
-                        pass_a_us=1e3 * prof[0] / prof[3], combine_us=1e3 * prof[1] / prof[3],
-                        pass_c_us=1e3 * prof[2] / prof[3])
+                        pass_a_us=a_us, combine_us=1e3 * prof[1] / prof[3],
+                        pass_c_us=1e3 * prof[2] / prof[3],
+                        pass_a_roofline_frac=pass_a_slots(dt, wl.radius) * wl.n_particles
+                        / (a_us * 1e-6) / PEAK_LANE_OPS)
     if not args.no_track and "f64" in modes:
         ref = track(pf, fl, vl.centres, wl, "f64", wl.frames - 1)
         for dt in modes:
@@ -476,12 +485,12 @@ def main():
     dom = "pass_a" if r["pass_a_us"] >= r["pass_c_us"] else "pass_c"
     a_s = r["pass_a_us"] * 1e-6
     if dom == "pass_a":
-        achieved = PASS_A_SLOTS[head] * w.n_particles / a_s
+        achieved = pass_a_slots(head, w.radius) * w.n_particles / a_s
         roof = dict(bound="alu", kernel="pass_a", achieved=achieved / 1e12, peak=PEAK_LANE_OPS / 1e12,
                     unit="Tlane-op/s", frac=achieved / PEAK_LANE_OPS,
                     traffic=measured_traffic("pass_a", head) if w.name == "disk1024_n1m" else None,
                     kernel_us=r["pass_a_us"],
-                    work_per_update=PASS_A_SLOTS[head], work_unit="VALU lane slots")
+                    work_per_update=pass_a_slots(head, w.radius), work_unit="VALU lane slots")
     else:
         c_s = r["pass_c_us"] * 1e-6
         achieved = PASS_C_BYTES[head] * w.n_particles / c_s
