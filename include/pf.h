@@ -170,8 +170,13 @@ int pf_init(const pf_params* p, void* d_workspace, size_t workspace_bytes, void*
  * normalised cumulative weights are resampled systematically with the offset
  * drawn from stream (0, t, stream_id, purpose 1) (Sec. 4, resampling
  * paragraph).  Asynchronous on the filter's stream; `d_frame` must stay valid
- * until the step has run.  Errors: PF_ERR_INVALID_ARG (NULL frame, pitch < W),
- * PF_ERR_HIP (the handle is then poisoned), PF_ERR_STATE. */
+ * until the step has run.  The call enqueues kernels only (no host wait,
+ * allocation or memset), so it may be captured into a HIP graph by stream
+ * capture on the filter's stream: the step count lives on the device, and
+ * each replay advances the filter by one step on the frame at the pointer
+ * given at capture (refill that buffer between replays).  Errors:
+ * PF_ERR_INVALID_ARG (NULL frame, pitch < W), PF_ERR_HIP (the handle is then
+ * poisoned), PF_ERR_STATE. */
 int pf_step(pf_filter* h, const uint8_t* d_frame, int64_t row_pitch);
 
 /* The estimate of the latest step (x, y in pixels), or (x0, y0) before the
@@ -191,7 +196,8 @@ int pf_estimate_async(pf_filter* h, double* d_out_xy);
  *              particle order of that step (needs PF_FLAG_DIAGNOSTICS);
  *   anc     -- ancestor of every slot of the latest resampling
  *              (needs PF_FLAG_DIAGNOSTICS);
- *   t       -- steps taken.
+ *   t       -- steps taken (the device's count, so replays of a captured
+ *              pf_step are included).
  * Errors: PF_ERR_INVALID_ARG (diagnostics requested without the flag, or no
  * step taken yet for w_norm/anc), PF_ERR_STATE, PF_ERR_HIP. */
 int pf_export(pf_filter* h, double* x, double* y, double* w_norm, int32_t* anc, uint32_t* t);

@@ -395,10 +395,10 @@ int pf_export(pf_filter* h, double* x, double* y, double* w_norm, int32_t* anc, 
     if (int rc = live(h)) return rc;
     const bool diag = (h->p.flags & PF_FLAG_DIAGNOSTICS) != 0;
     if ((w_norm || anc) && !diag) return fail(PF_ERR_INVALID_ARG, "w_norm/anc need PF_FLAG_DIAGNOSTICS");
-    if ((w_norm || anc) && h->t == 0) return fail(PF_ERR_INVALID_ARG, "no step taken yet");
     hipError_t e;
     const DevBlock b = read_block(h, &e);
     if (e != hipSuccess) return hip_fail(h, e, "pf_export");
+    if ((w_norm || anc) && b.t == 0) return fail(PF_ERR_INVALID_ARG, "no step taken yet");
     if (int rc = export_positions(h, h->L.sx, h->L.sy, x, y, b)) return rc;
     const int64_t n = h->p.n_particles;
     if (w_norm) {
@@ -411,19 +411,20 @@ int pf_export(pf_filter* h, double* x, double* y, double* w_norm, int32_t* anc, 
         if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
         if (e != hipSuccess) return hip_fail(h, e, "pf_export anc");
     }
-    if (t) *t = h->t;
+    if (t) *t = b.t;  // the device count (also right after steps replayed from a graph)
+    h->t = b.t;
     return ok();
 }
 
 int pf_export_step(pf_filter* h, double* x_prop, double* y_prop, int32_t* disk_sum)
 {
     if (int rc = live(h)) return rc;
-    if (h->t == 0) return fail(PF_ERR_INVALID_ARG, "no step taken yet");
     if (disk_sum && !(h->p.flags & PF_FLAG_DIAGNOSTICS))
         return fail(PF_ERR_INVALID_ARG, "disk_sum needs PF_FLAG_DIAGNOSTICS");
     hipError_t e;
     const DevBlock b = read_block(h, &e);
     if (e != hipSuccess) return hip_fail(h, e, "pf_export_step");
+    if (b.t == 0) return fail(PF_ERR_INVALID_ARG, "no step taken yet");
     if (int rc = export_positions(h, h->L.px, h->L.py, x_prop, y_prop, b)) return rc;
     if (disk_sum) {
         e = hipMemcpyAsync(disk_sum, at(h, h->L.dg_s), (size_t)h->p.n_particles * 4, hipMemcpyDeviceToHost,
@@ -463,6 +464,7 @@ int pf_import(pf_filter* h, const double* x, const double* y, uint32_t t)
     }
     b.est_x = mx;
     b.est_y = my;
+    b.t = t;
     const int elt = elt_of(dt);
     std::vector<uint8_t> bx((size_t)n * elt), by((size_t)n * elt);
     for (int64_t k = 0; k < n; ++k) {

@@ -167,11 +167,11 @@ struct ModeT<PF_F64> {
     // contraction), as Eq. (1)-(2) are written.
     template <int PPT>
     static __device__ __forceinline__ void propagate(Val* x, Val* y, const Prop& pr, const StepArgs& a,
-                                                     int k0)
+                                                     int k0, uint32_t t)
     {
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
-            const u32x4 w = philox4x32_10((uint32_t)(k0 + i), a.t, a.stream_id, 0u, a.key0, a.key1);
+            const u32x4 w = philox4x32_10((uint32_t)(k0 + i), t, a.stream_id, 0u, a.key0, a.key1);
             double zx, zy;
             normal_pair_f64(w, zx, zy);
             x[i] = x[i] + (pr.dx + pr.sx * zx);
@@ -212,11 +212,11 @@ struct ModeT<PF_F32> {
     }
     template <int PPT>
     static __device__ __forceinline__ void propagate(Val* x, Val* y, const Prop& pr, const StepArgs& a,
-                                                     int k0)
+                                                     int k0, uint32_t t)
     {
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
-            const u32x4 w = philox4x32_10((uint32_t)(k0 + i), a.t, a.stream_id, 0u, a.key0, a.key1);
+            const u32x4 w = philox4x32_10((uint32_t)(k0 + i), t, a.stream_id, 0u, a.key0, a.key1);
             float zx, zy;
             normal_pair_f32(w, zx, zy);
             x[i] = x[i] + __builtin_fmaf(pr.sx, zx, pr.dx);
@@ -260,12 +260,12 @@ struct ModeT<PF_F16> {
     }
     template <int PPT>
     static __device__ __forceinline__ void propagate(Val* x, Val* y, const Prop& pr, const StepArgs& a,
-                                                     int k0)
+                                                     int k0, uint32_t t)
     {
 #pragma unroll
         for (int i = 0; i < PPT; i += 2) {
-            const u32x4 w0 = philox4x32_10((uint32_t)(k0 + i), a.t, a.stream_id, 0u, a.key0, a.key1);
-            const u32x4 w1 = philox4x32_10((uint32_t)(k0 + i + 1), a.t, a.stream_id, 0u, a.key0, a.key1);
+            const u32x4 w0 = philox4x32_10((uint32_t)(k0 + i), t, a.stream_id, 0u, a.key0, a.key1);
+            const u32x4 w1 = philox4x32_10((uint32_t)(k0 + i + 1), t, a.stream_id, 0u, a.key0, a.key1);
             float zx0, zy0, zx1, zy1;
             normal_pair_f32(w0, zx0, zy0);
             normal_pair_f32(w1, zx1, zy1);
@@ -322,11 +322,11 @@ struct ModeT<PF_BF16> {
     }
     template <int PPT>
     static __device__ __forceinline__ void propagate(Val* x, Val* y, const Prop& pr, const StepArgs& a,
-                                                     int k0)
+                                                     int k0, uint32_t t)
     {
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
-            const u32x4 w = philox4x32_10((uint32_t)(k0 + i), a.t, a.stream_id, 0u, a.key0, a.key1);
+            const u32x4 w = philox4x32_10((uint32_t)(k0 + i), t, a.stream_id, 0u, a.key0, a.key1);
             float zx, zy;
             normal_pair_f32(w, zx, zy);
             x[i] = x[i] + __builtin_fmaf(pr.sx, zx, pr.dx);
@@ -388,7 +388,9 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
 
     // Origins (reduced modes): stored offsets are relative to ci, the
     // propagated ones to cn; the drift is applied minus the origin change.
+    // The step's index is one past the block's count (the combine advances it).
     const DevBlock* blk = a.blk;
+    const uint32_t tn = blk->t + 1u;
     int cnx = 0, cny = 0;
     float ddx = 0.f, ddy = 0.f;
     if constexpr (DT != PF_F64) {
@@ -402,7 +404,7 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
     typename M::Val x[PPT], y[PPT];
     M::template load<PPT>(a.sx, k0, x);
     M::template load<PPT>(a.sy, k0, y);
-    M::template propagate<PPT>(x, y, pr, a, k0);
+    M::template propagate<PPT>(x, y, pr, a, k0, tn);
     M::template store<PPT>(a.px, k0, x);
     M::template store<PPT>(a.py, k0, y);
 
@@ -794,9 +796,9 @@ struct SlotMap;
 template <>
 struct SlotMap<true> {
     double R, mu0, u0;
-    __device__ SlotMap(const StepArgs& a, double Z)
+    __device__ SlotMap(const StepArgs& a, double Z, uint32_t t)
     {
-        const u32x4 wu = philox4x32_10(0u, a.t, a.stream_id, 1u, a.key0, a.key1);
+        const u32x4 wu = philox4x32_10(0u, t, a.stream_id, 1u, a.key0, a.key1);
         u0 = uniform53(wu.v0, wu.v1);
         R = (double)(int)a.n / Z;
         mu0 = -u0;
@@ -807,10 +809,10 @@ struct SlotMap<true> {
 template <>
 struct SlotMap<false> {
     ff R, mu0, u0;
-    __device__ SlotMap(const StepArgs& a, ff Z)
+    __device__ SlotMap(const StepArgs& a, ff Z, uint32_t t)
     {
         const int n = (int)a.n;
-        const u32x4 wu = philox4x32_10(0u, a.t, a.stream_id, 1u, a.key0, a.key1);
+        const u32x4 wu = philox4x32_10(0u, t, a.stream_id, 1u, a.key0, a.key1);
         const uint64_t bits = ((uint64_t)wu.v0 << 21) | (uint64_t)(wu.v1 >> 11);
         u0 = fast_two_sum((float)(uint32_t)(bits >> 29) * 0x1.0p-24f,
                           (float)(uint32_t)(bits & 0x1FFFFFFFu) * 0x1.0p-53f);
@@ -830,9 +832,10 @@ __device__ __forceinline__ void write_block(const StepArgs& a,
                                            typename std::conditional<DT == PF_F64, double, int>::type gm,
                                            typename std::conditional<DT == PF_F64, double, float>::type sx,
                                            typename std::conditional<DT == PF_F64, double, float>::type sy,
-                                           const SlotMap<DT == PF_F64>& sm)
+                                           const SlotMap<DT == PF_F64>& sm, uint32_t t)
 {
     DevBlock* b = a.blk;
+    b->t = t;
     if constexpr (DT == PF_F64) {
         b->M = gm;
         b->Z = Z;
@@ -891,6 +894,7 @@ __device__ __forceinline__ void combine_filter(const StepArgs& a)
     const int n = (int)a.n;
     const Rec* rec = static_cast<const Rec*>(a.rec);
     Tab* tab = static_cast<Tab*>(a.tab);
+    const uint32_t tn = a.blk->t + 1u;  // this step (thread 0 advances the count at the end)
 
     // global maximum of the tile maxima
     Mx m = F64 ? (Mx)-INFINITY : (Mx)INT32_MIN;
@@ -981,7 +985,7 @@ __device__ __forceinline__ void combine_filter(const StepArgs& a)
     // its tiles with), made non-decreasing by a prefix maximum so that the
     // tiles' slot ranges [E_{t-1}, E_t) partition [0, N) whatever the
     // rounding of the offsets; the last tile ends at N.
-    const SlotMap<F64> smap(a, Z);
+    const SlotMap<F64> smap(a, Z, tn);
     auto end_of = [&](T o) -> int { return smap.end_of(o, n); };
     const bool one_round = KEEP && nt <= CHUNK;
     int carry_e = 0;
@@ -1029,7 +1033,7 @@ __device__ __forceinline__ void combine_filter(const StepArgs& a)
             tab[0].off_hi = 0.f;
             tab[0].off_lo = 0.f;
         }
-        write_block<DT>(a, Z, gm, sx, sy, smap);
+        write_block<DT>(a, Z, gm, sx, sy, smap, tn);
     }
 }
 
@@ -1164,6 +1168,7 @@ __global__ __launch_bounds__(kTopThreads) void combine_top_kernel(StepArgs a)
     const int n = (int)a.n;
     const int ng = (a.ntiles + kGroupTiles - 1) / kGroupTiles;
     const bool valid = tid < ng;
+    const uint32_t tn = a.blk->t + 1u;  // this step (thread 0 advances the count at the end)
     GRec gr{};
     if (valid) gr = static_cast<const GRec*>(a.grec)[tid];
     Mx m = F64 ? (Mx)-INFINITY : (Mx)INT32_MIN;
@@ -1204,7 +1209,7 @@ __global__ __launch_bounds__(kTopThreads) void combine_top_kernel(StepArgs a)
     const T incl = A::add(off, sw);
     const T excl = A::up1(incl, off);
     const T Z = wave_off[NW];
-    const SlotMap<F64> smap(a, Z);
+    const SlotMap<F64> smap(a, Z, tn);
     // end slot of every group (from the next group's offset), made
     // non-decreasing; the last group ends at N
     int e = 0;
@@ -1234,7 +1239,7 @@ __global__ __launch_bounds__(kTopThreads) void combine_top_kernel(StepArgs a)
         Tab* tab = static_cast<Tab*>(a.tab);
         if constexpr (F64) tab[a.ntiles].off = Z;
         else { tab[a.ntiles].off_hi = Z.hi; tab[a.ntiles].off_lo = Z.lo; }
-        write_block<DT>(a, Z, gm, sx, sy, smap);
+        write_block<DT>(a, Z, gm, sx, sy, smap, tn);
     }
 }
 
@@ -1485,13 +1490,14 @@ __global__ __launch_bounds__(kBlock) void metropolis_kernel(StepArgs a)
     const int n = (int)a.n;
     if (j >= n) return;
     const int32_t* S = a.s_all;
+    const uint32_t t = a.blk->t;  // this step's index (the combine has advanced the count)
     int k = j;
     int Sk = S[k];
     double Lk = (double)Sk / a.denom;
     u32x4 w{0u, 0u, 0u, 0u};
     for (int b = 0; b < a.mh_steps; ++b) {
         if ((b & 1) == 0)
-            w = philox4x32_10((uint32_t)j, a.t, a.stream_id, 2u + (uint32_t)(b >> 1), a.key0, a.key1);
+            w = philox4x32_10((uint32_t)j, t, a.stream_id, 2u + (uint32_t)(b >> 1), a.key0, a.key1);
         const uint32_t wi = (b & 1) ? w.v2 : w.v0;
         const uint32_t wu = (b & 1) ? w.v3 : w.v1;
         const int i = (int)(((uint64_t)wi * (uint64_t)(uint32_t)n) >> 32);
@@ -1532,6 +1538,7 @@ __global__ __launch_bounds__(kBlock) void gumbel_kernel(StepArgs a)
     const int i = blockIdx.x * kBlock + threadIdx.x;
     const int n = (int)a.n;
     const uint32_t key1 = a.key1 ^ 0x47756D62u;
+    const uint32_t t = a.blk->t;  // this step's index (the combine has advanced the count)
     const float inv = (float)(1.0 / a.denom);
     Acc best = -INFINITY;
     int arg = 0;
@@ -1546,7 +1553,7 @@ __global__ __launch_bounds__(kBlock) void gumbel_kernel(StepArgs a)
         if (i < n) {
             const int m = min(kTile, n - c0);
             for (int k = 0; k < m; k += 4) {
-                const u32x4 w = philox4x32_10((uint32_t)((c0 + k) >> 2), (uint32_t)i, a.t, a.stream_id, a.key0, key1);
+                const u32x4 w = philox4x32_10((uint32_t)((c0 + k) >> 2), (uint32_t)i, t, a.stream_id, a.key0, key1);
                 const uint32_t ws[4] = {w.v0, w.v1, w.v2, w.v3};
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {

@@ -43,7 +43,9 @@ __host__ __device__ constexpr int elt_of(int dtype) { return dtype == PF_F64 ? 8
 
 // Per-filter scalars in device memory (first 256 bytes of the workspace).
 struct DevBlock {
-    uint32_t pad0[2];
+    uint32_t t;           // steps taken; the combine advances it, so a step
+                          // replayed from a captured graph draws fresh streams
+    uint32_t pad0;
     int32_t ci_x, ci_y;   // reduced modes: origin cell of the stored positions
     int32_t cn_x, cn_y;   // reduced modes: origin cell of the next propagation
     double est_x, est_y;  // estimate of the latest step
@@ -160,7 +162,7 @@ struct StepArgs {
     int32_t W, H, r, nd;
     int64_t n;
     int32_t ntiles;
-    uint32_t t, stream_id, key0, key1;
+    uint32_t t, stream_id, key0, key1;  // t: host copy of the steps taken (kernels read the block's)
     int32_t fg, bg;
     double drift_x, drift_y, sigma_x, sigma_y;
     double denom;       // kappa * N_d (MEAN) or kappa (SUM)
