@@ -257,8 +257,8 @@ int pf_batch_workspace_bytes(const pf_params* ps, int32_t n, size_t* out_bytes);
  * owned workspace (device memory, 256-byte aligned, at least
  * pf_batch_workspace_bytes() bytes; the batch must not outlive it).  The
  * batch allocates pinned host memory for staging each step's plan (32 bytes
- * per filter plus 4 bytes per tile, three copies) and frees it in
- * pf_batch_destroy.  All device work is ordered on `hip_stream`; waits for
+ * per filter plus 4 bytes per tile, four copies: three for eager steps, one
+ * for a captured step) and frees it in pf_batch_destroy.  All device work is ordered on `hip_stream`; waits for
  * the initialisation to finish.  Errors: PF_ERR_INVALID_ARG,
  * PF_ERR_WORKSPACE, PF_ERR_HIP. */
 int pf_batch_init(const pf_params* ps, int32_t n, void* d_workspace, size_t workspace_bytes,
@@ -269,9 +269,18 @@ int pf_batch_init(const pf_params* ps, int32_t n, void* d_workspace, size_t work
  * pitches[k] >= W_k).  d_frames and pitches are host arrays of n entries;
  * entries of inactive filters are not read.  Continuous batching: the active
  * set may change from call to call.  Asynchronous on the batch's stream; the
- * frames must stay valid until the step has run.  Errors: PF_ERR_INVALID_ARG
- * (nothing is stepped), PF_ERR_HIP (the batch and its filters are then
- * poisoned), PF_ERR_STATE. */
+ * frames must stay valid until the step has run.
+ * HIP graphs: called while the batch's stream is being captured, the step is
+ * recorded instead of run (no host wait, allocation or memset): the plan
+ * (frame pointers, pitches, active set) goes to the staging copy kept for
+ * captured steps, and every replay uploads it and advances each active
+ * filter by one step on the frames at those pointers (refill them between
+ * replays).  The batch keeps one captured plan: a later capture replaces the
+ * plan that earlier captured graphs read, and so does a re-capture after
+ * pf_batch_reinit (a graph captured before it steps the new filter with the
+ * old plan: tiles past its new size are skipped, its results are
+ * meaningless).  Eager steps and replays may be interleaved.  Errors: PF_ERR_INVALID_ARG (nothing is stepped), PF_ERR_HIP
+ * (the batch and its filters are then poisoned), PF_ERR_STATE. */
 int pf_batch_step(pf_batch* b, const uint8_t* const* d_frames, const int64_t* pitches,
                   const uint8_t* active);
 

@@ -49,6 +49,8 @@ struct pf_batch {
     StepArgs* d_args;
     BatchEntry* d_entries;
     int32_t* d_tile_entry;
+    BatchEntry* d_g_entries;          // plan of a captured step (replays write only these)
+    int32_t* d_g_tile_entry;
     double* d_est;
     std::vector<pf_filter*> f;
     std::vector<int> cls;            // combine class of every filter
@@ -56,6 +58,7 @@ struct pf_batch {
     std::vector<int> slot_tiles;     // tiles of every filter at creation (the most it may have)
     std::vector<StepArgs> args_host; // host copy of the filters' StepArgs
     uint8_t* h_stage[kRing];
+    uint8_t* h_graph;                 // staging read by the copies of a captured step
     hipEvent_t ev[kRing];
     bool ev_used[kRing];
     int ring;
@@ -540,7 +543,7 @@ int pf_destroy(pf_filter* h)
 // Batches.
 
 struct BatchLayout {
-    size_t args, entries, tile_entry, est, filters, total;
+    size_t args, entries, tile_entry, g_entries, g_tile_entry, est, filters, total;
     int64_t tiles;
 };
 
@@ -566,6 +569,8 @@ static int check_batch(const pf_params* ps, int32_t n, BatchLayout* bl, std::vec
     bl->args = o; o = align256(o + sizeof(StepArgs) * (size_t)n);
     bl->entries = o; o = align256(o + sizeof(BatchEntry) * (size_t)n);
     bl->tile_entry = o; o = align256(o + 4 * (size_t)tiles);
+    bl->g_entries = o; o = align256(o + sizeof(BatchEntry) * (size_t)n);  // captured steps' plan
+    bl->g_tile_entry = o; o = align256(o + 4 * (size_t)tiles);
     bl->est = o; o = align256(o + 16 * (size_t)n);
     bl->filters = o; o += fbytes;
     bl->total = o;
@@ -592,6 +597,7 @@ static void batch_free(pf_batch* b)
         if (b->ev[i]) (void)hipEventDestroy(b->ev[i]);
         if (b->h_stage[i]) (void)hipHostFree(b->h_stage[i]);
     }
+    if (b->h_graph) (void)hipHostFree(b->h_graph);
     delete b;
 }
 
@@ -627,6 +633,8 @@ int pf_batch_init(const pf_params* ps, int32_t n, void* d_workspace, size_t work
     b->d_args = (StepArgs*)(b->ws + bl.args);
     b->d_entries = (BatchEntry*)(b->ws + bl.entries);
     b->d_tile_entry = (int32_t*)(b->ws + bl.tile_entry);
+    b->d_g_entries = (BatchEntry*)(b->ws + bl.g_entries);
+    b->d_g_tile_entry = (int32_t*)(b->ws + bl.g_tile_entry);
     b->d_est = (double*)(b->ws + bl.est);
     b->map_valid = false;
     b->poisoned = false;
@@ -666,6 +674,7 @@ int pf_batch_init(const pf_params* ps, int32_t n, void* d_workspace, size_t work
         e = hipHostMalloc((void**)&b->h_stage[i], b->stage_bytes, hipHostMallocDefault);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming);
     }
+    if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_graph, b->stage_bytes, hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->d_args, args.data(), sizeof(StepArgs) * (size_t)n, hipMemcpyHostToDevice, b->stream);
     for (int32_t k = 0; k < n && e == hipSuccess; ++k) {
@@ -709,18 +718,30 @@ int pf_batch_step(pf_batch* b, const uint8_t* const* d_frames, const int64_t* pi
     }
     if (n_act == 0) return ok();
 
+    // Under stream capture the step is recorded, not run: its entries and tile
+    // map go through the staging buffer kept for captured steps to device
+    // buffers of their own (copies that every replay repeats, leaving the
+    // eager steps' plan alone), and no host wait or event is recorded.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(b->stream, &cap);
+    if (e != hipSuccess) return batch_fail(b, e, "pf_batch_step");
+    const bool capturing = cap != hipStreamCaptureStatusNone;
+
     // the stepped set, and whether the uploaded tile map still describes it
-    bool same = b->map_valid && (int32_t)b->map_active.size() == n;
+    bool same = !capturing && b->map_valid && (int32_t)b->map_active.size() == n;
     if (same)
         for (int32_t k = 0; k < n && same; ++k) same = b->map_active[k] == (uint8_t)(active ? active[k] != 0 : 1);
 
     const int slot = b->ring;
-    b->ring = (b->ring + 1) % kRing;
-    hipError_t e = hipSuccess;
-    if (b->ev_used[slot]) e = hipEventSynchronize(b->ev[slot]);
-    if (e != hipSuccess) return batch_fail(b, e, "pf_batch_step");
-    BatchEntry* ent = reinterpret_cast<BatchEntry*>(b->h_stage[slot]);
-    int32_t* tmap = reinterpret_cast<int32_t*>(b->h_stage[slot] + sizeof(BatchEntry) * (size_t)n);
+    uint8_t* stage = b->h_graph;
+    if (!capturing) {
+        b->ring = (b->ring + 1) % kRing;
+        if (b->ev_used[slot]) e = hipEventSynchronize(b->ev[slot]);
+        if (e != hipSuccess) return batch_fail(b, e, "pf_batch_step");
+        stage = b->h_stage[slot];
+    }
+    BatchEntry* ent = reinterpret_cast<BatchEntry*>(stage);
+    int32_t* tmap = reinterpret_cast<int32_t*>(stage + sizeof(BatchEntry) * (size_t)n);
     int32_t cls_begin[kCombClasses + 1];
     int32_t ne = 0, tiles = 0;
     for (int c = 0; c < kCombClasses; ++c) {
@@ -743,15 +764,17 @@ int pf_batch_step(pf_batch* b, const uint8_t* const* d_frames, const int64_t* pi
     }
     cls_begin[kCombClasses] = ne;
 
-    e = hipMemcpyAsync(b->d_entries, ent, sizeof(BatchEntry) * (size_t)ne, hipMemcpyHostToDevice, b->stream);
+    BatchEntry* d_ent = capturing ? b->d_g_entries : b->d_entries;
+    int32_t* d_map = capturing ? b->d_g_tile_entry : b->d_tile_entry;
+    e = hipMemcpyAsync(d_ent, ent, sizeof(BatchEntry) * (size_t)ne, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess && !same)
-        e = hipMemcpyAsync(b->d_tile_entry, tmap, 4 * (size_t)tiles, hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess) e = hipEventRecord(b->ev[slot], b->stream);
-    if (e == hipSuccess) b->ev_used[slot] = true;
+        e = hipMemcpyAsync(d_map, tmap, 4 * (size_t)tiles, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess && !capturing) e = hipEventRecord(b->ev[slot], b->stream);
+    if (e == hipSuccess && !capturing) b->ev_used[slot] = true;
     BatchArgs ba;
     ba.args = b->d_args;
-    ba.entries = b->d_entries;
-    ba.tile_entry = b->d_tile_entry;
+    ba.entries = d_ent;
+    ba.tile_entry = d_map;
     ba.entry0 = 0;
     if (e == hipSuccess) e = launch_batch_pass_a(b->dtype, b->rc, ba, tiles, b->stream);
     for (int c = 0; c < kCombClasses - 1 && e == hipSuccess; ++c) {
@@ -777,6 +800,7 @@ int pf_batch_step(pf_batch* b, const uint8_t* const* d_frames, const int64_t* pi
         e = launch_diag_weights(b->dtype, a, b->stream);
     }
     if (e != hipSuccess) return batch_fail(b, e, "pf_batch_step launch");
+    if (capturing) return ok();
     if (!same) {
         b->map_active.resize((size_t)n);
         for (int32_t k = 0; k < n; ++k) b->map_active[k] = (uint8_t)(active ? active[k] != 0 : 1);

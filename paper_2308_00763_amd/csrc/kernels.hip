@@ -1634,7 +1634,9 @@ __global__ __launch_bounds__(kBlockA) void pass_a_batch_kernel(BatchArgs b)
     __shared__ PassALds lds;
     const int e = b.tile_entry[blockIdx.x];
     const StepArgs a = batch_args(b, e);
-    pass_a_tile<DT, RC, kPPT>(a, (int)blockIdx.x - b.entries[e].tile_base, lds);
+    const int lt = (int)blockIdx.x - b.entries[e].tile_base;
+    if (lt >= a.ntiles) return;  // a plan captured before the filter was re-initialised smaller
+    pass_a_tile<DT, RC, kPPT>(a, lt, lds);
 }
 
 template <int DT, int KPER, int NT>
@@ -1650,7 +1652,9 @@ __global__ __launch_bounds__(pass_c_threads(DT, 1 << 30)) void pass_c_batch_kern
     __shared__ PassCLds<DT> lds;
     const int e = b.tile_entry[blockIdx.x];
     const StepArgs a = batch_args(b, e);
-    pass_c_tile<DT, pass_c_threads(DT, 1 << 30)>(a, (int)blockIdx.x - b.entries[e].tile_base, lds);
+    const int lt = (int)blockIdx.x - b.entries[e].tile_base;
+    if (lt >= a.ntiles) return;
+    pass_c_tile<DT, pass_c_threads(DT, 1 << 30)>(a, lt, lds);
 }
 
 __global__ __launch_bounds__(kBlock) void gather_est_kernel(const StepArgs* args, int n, double* out)
