@@ -776,6 +776,7 @@ int pf_batch_step(pf_batch* b, const uint8_t* const* d_frames, const int64_t* pi
     ba.entries = d_ent;
     ba.tile_entry = d_map;
     ba.entry0 = 0;
+    ba.tiles = tiles;
     if (e == hipSuccess) e = launch_batch_pass_a(b->dtype, b->rc, ba, tiles, b->stream);
     for (int c = 0; c < kCombClasses - 1 && e == hipSuccess; ++c) {
         const int32_t cnt = cls_begin[c + 1] - cls_begin[c];

@@ -667,6 +667,7 @@ template <>
 struct TileSlots<PF_F64> {
     double base, scale, ymax;
     int E, Eprev;
+    TileSlots() = default;
     __device__ TileSlots(const StepArgs& a, int t)
     {
         const TileTab64* tab = static_cast<const TileTab64*>(a.tab);
@@ -677,9 +678,10 @@ struct TileSlots<PF_F64> {
         E = tab[t].E;
         Eprev = t > 0 ? tab[t - 1].E : 0;
     }
-    __device__ int operator()(const void* q, int i, int n) const
+    __device__ int operator()(const void* q, int i, int n) const { return of(static_cast<const double*>(q)[i], n); }
+    __device__ int of(double qv, int n) const
     {
-        double y = __builtin_fma(scale, static_cast<const double*>(q)[i], base);
+        double y = __builtin_fma(scale, qv, base);
         y = y < ymax ? y : ymax;
         return slot_end_of(y, n);
     }
@@ -695,6 +697,7 @@ template <>
 struct TileSlots<PF_F32> {
     float frac, scale;
     int B, cap, E, Eprev;
+    TileSlots() = default;
     __device__ TileSlots(const StepArgs& a, int t)
     {
         const TileTab32* tab = static_cast<const TileTab32*>(a.tab);
@@ -708,9 +711,10 @@ struct TileSlots<PF_F32> {
         Eprev = t > 0 ? tab[t - 1].E : 0;
         cap = E - B;
     }
-    __device__ int operator()(const void* q, int i, int /*n*/) const
+    __device__ int operator()(const void* q, int i, int n) const { return of(static_cast<const float*>(q)[i], n); }
+    __device__ int of(float qv, int /*n*/) const
     {
-        const float y = __builtin_fmaf(scale, static_cast<const float*>(q)[i], frac);
+        const float y = __builtin_fmaf(scale, qv, frac);
         return B + min((int)floorf(y) + 1, cap);
     }
 };
@@ -1347,9 +1351,42 @@ __device__ __forceinline__ int merge_cut(const int32_t* e, int tt, int d)
     return lo;
 }
 
-// Pass C of tile `t` of the filter described by `a`, BC threads.
+// One tile's pass-C inputs in registers: its particles' cumulative weights
+// and propagated positions, thread tid holding particles tid + r BC.  Loaded
+// one tile ahead by the streaming kernels.
 template <int DT, int BC>
-__device__ __forceinline__ void pass_c_tile(const StepArgs& a, int t, PassCLds<DT>& lds)
+struct PassCIn {
+    using Store = typename ModeT<DT>::Store;
+    using Q = typename std::conditional<DT == PF_F64, double, float>::type;
+    static constexpr int R = kTile / BC;
+    Q q[R];
+    Store x[R], y[R];
+
+    __device__ void load(const StepArgs& a, int t)
+    {
+        const int first = t * kTile, tt = min(kTile, (int)a.n - first);
+        const Q* qp = static_cast<const Q*>(a.q) + first;
+        const Store* xp = static_cast<const Store*>(a.px) + first;
+        const Store* yp = static_cast<const Store*>(a.py) + first;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int k = threadIdx.x + r * BC;
+            if (k < tt) {
+                q[r] = qp[k];
+                x[r] = xp[k];
+                y[r] = yp[k];
+            }
+        }
+    }
+};
+
+// Pass C of tile `t` of the filter described by `a`, BC threads, from its
+// inputs `in` and slot map `ts`: end slots and positions to LDS, then the
+// merge-path scatter.  Every thread takes part; the workgroup is free for the
+// next tile when it returns.
+template <int DT, int BC>
+__device__ __forceinline__ void pass_c_run(const StepArgs& a, int t, PassCLds<DT>& lds, const PassCIn<DT, BC>& in,
+                                           const TileSlotsT<DT>& ts)
 {
     using Store = typename ModeT<DT>::Store;
     int32_t* s_e = lds.e;
@@ -1357,13 +1394,9 @@ __device__ __forceinline__ void pass_c_tile(const StepArgs& a, int t, PassCLds<D
     Store* s_y = lds.y;
 
     const int n = (int)a.n;
-    const TileSlotsT<DT> ts(a, t);
     const int first = t * kTile;
     const int tt = min(kTile, n - first);
     const int tid = threadIdx.x;
-
-    const Store* px = static_cast<const Store*>(a.px);
-    const Store* py = static_cast<const Store*>(a.py);
 #pragma unroll
     for (int r = 0; r < kTile / BC; ++r) {
         const int k = tid + r * BC;
@@ -1371,54 +1404,76 @@ __device__ __forceinline__ void pass_c_tile(const StepArgs& a, int t, PassCLds<D
             // local end slot, at least 0: a particle whose end slot precedes
             // the tile's first slot (the combine's prefix maximum can raise
             // it) owns no slot, and the merge's first cut stays at 0
-            const int e = k == tt - 1 ? ts.E : ts(a.q, first + k, n);
+            const int e = k == tt - 1 ? ts.E : ts.of(in.q[r], n);
             s_e[k] = max(e - ts.Eprev, 0);
-            s_x[k] = px[first + k];
-            s_y[k] = py[first + k];
+            s_x[k] = in.x[r];
+            s_y[k] = in.y[r];
         }
     }
     __syncthreads();
     const int slots = ts.E - ts.Eprev;
-    if (slots <= 0) return;  // uniform over the workgroup
-    const int total = tt + slots;
-    const int ipt = min((total + BC - 1) / BC, kDiagRound / BC);
-    const int round = ipt * BC;
-    Store* sx = static_cast<Store*>(a.sx) + ts.Eprev;
-    Store* sy = static_cast<Store*>(a.sy) + ts.Eprev;
-    int32_t* anc_out = a.dg_anc ? a.dg_anc + ts.Eprev : nullptr;
-    for (int d0 = 0; d0 < total; d0 += round) {
-        // slots of this round: [j0, j1), the slot coordinates of its two cuts
-        const int d1 = min(d0 + round, total);
-        const int j0 = d0 == 0 ? 0 : d0 - merge_cut(s_e, tt, d0);
-        const int j1 = d1 == total ? slots : d1 - merge_cut(s_e, tt, d1);
-        const int ds = min(d0 + tid * ipt, d1), de = min(ds + ipt, d1);
-        if (ds < de) {
-            int k = merge_cut(s_e, tt, ds), j = ds - k;
-            for (int d = ds; d < de; ++d) {
-                if (k < tt && s_e[k] <= j) {
-                    ++k;  // particle k has no slot left: the merge takes it
-                } else {
-                    lds.anc[j - j0] = (uint16_t)min(k, tt - 1);
-                    ++j;
+    if (slots > 0) {  // uniform over the workgroup
+        const int total = tt + slots;
+        const int ipt = min((total + BC - 1) / BC, kDiagRound / BC);
+        const int round = ipt * BC;
+        Store* sx = static_cast<Store*>(a.sx) + ts.Eprev;
+        Store* sy = static_cast<Store*>(a.sy) + ts.Eprev;
+        int32_t* anc_out = a.dg_anc ? a.dg_anc + ts.Eprev : nullptr;
+        for (int d0 = 0; d0 < total; d0 += round) {
+            // slots of this round: [j0, j1), the slot coordinates of its two cuts
+            const int d1 = min(d0 + round, total);
+            const int j0 = d0 == 0 ? 0 : d0 - merge_cut(s_e, tt, d0);
+            const int j1 = d1 == total ? slots : d1 - merge_cut(s_e, tt, d1);
+            const int ds = min(d0 + tid * ipt, d1), de = min(ds + ipt, d1);
+            if (ds < de) {
+                int k = merge_cut(s_e, tt, ds), j = ds - k;
+                for (int d = ds; d < de; ++d) {
+                    if (k < tt && s_e[k] <= j) {
+                        ++k;  // particle k has no slot left: the merge takes it
+                    } else {
+                        lds.anc[j - j0] = (uint16_t)min(k, tt - 1);
+                        ++j;
+                    }
                 }
             }
+            __syncthreads();
+            for (int i = tid; i < j1 - j0; i += BC) {
+                const int kk = lds.anc[i];
+                sx[j0 + i] = s_x[kk];
+                sy[j0 + i] = s_y[kk];
+                if (anc_out) anc_out[j0 + i] = first + kk;
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        for (int i = tid; i < j1 - j0; i += BC) {
-            const int kk = lds.anc[i];
-            sx[j0 + i] = s_x[kk];
-            sy[j0 + i] = s_y[kk];
-            if (anc_out) anc_out[j0 + i] = first + kk;
-        }
-        __syncthreads();
     }
 }
 
+// Pass C of one filter over a grid of G <= ntiles workgroups: workgroup g
+// takes tiles g, g + G, ... and loads each tile's inputs while it scatters
+// the one before, so a workgroup's memory latency overlaps its own merge.
 template <int DT, int BC>
 __global__ __launch_bounds__(BC) void pass_c_kernel(StepArgs a)
 {
     __shared__ PassCLds<DT> lds;
-    pass_c_tile<DT, BC>(a, blockIdx.x, lds);
+    const int nt = a.ntiles, G = gridDim.x;
+    int t = blockIdx.x;
+    PassCIn<DT, BC> cur;
+    cur.load(a, t);
+    TileSlotsT<DT> ts(a, t);
+    for (;;) {
+        const int tn = t + G;
+        PassCIn<DT, BC> nxt;
+        TileSlotsT<DT> tsn;
+        if (tn < nt) {  // uniform
+            nxt.load(a, tn);
+            tsn = TileSlotsT<DT>(a, tn);
+        }
+        pass_c_run<DT, BC>(a, t, lds, cur, ts);
+        if (tn >= nt) break;
+        t = tn;
+        cur = nxt;
+        ts = tsn;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1646,15 +1701,55 @@ __global__ __launch_bounds__(NT) void combine_batch_kernel(BatchArgs b)
     combine_filter<DT, KPER, NT>(a);
 }
 
+// Batched pass C over a grid of G <= b.tiles workgroups, streaming as the
+// single-filter kernel does: workgroup g takes grid tiles g, g + G, ... of
+// whatever filters they belong to, loading each tile's arguments and inputs
+// while it scatters the one before.
 template <int DT>
 __global__ __launch_bounds__(pass_c_threads(DT, 1 << 30)) void pass_c_batch_kernel(BatchArgs b)
 {
+    constexpr int BC = pass_c_threads(DT, 1 << 30);
     __shared__ PassCLds<DT> lds;
-    const int e = b.tile_entry[blockIdx.x];
-    const StepArgs a = batch_args(b, e);
-    const int lt = (int)blockIdx.x - b.entries[e].tile_base;
-    if (lt >= a.ntiles) return;
-    pass_c_tile<DT, pass_c_threads(DT, 1 << 30)>(a, lt, lds);
+    const int G = gridDim.x;
+    // a grid tile's filter arguments and tile index in its filter
+    // (past the filter's tiles: a plan captured before a smaller
+    // re-initialisation; such a tile is skipped)
+    auto resolve = [&](int gt, StepArgs& a, int& lt) {
+        const int e = b.tile_entry[gt];
+        a = batch_args(b, e);
+        lt = gt - b.entries[e].tile_base;
+    };
+    int gt = blockIdx.x;
+    StepArgs a;
+    int lt;
+    resolve(gt, a, lt);
+    PassCIn<DT, BC> cur;
+    TileSlotsT<DT> ts;
+    if (lt < a.ntiles) {
+        cur.load(a, lt);
+        ts = TileSlotsT<DT>(a, lt);
+    }
+    for (;;) {
+        const int gn = gt + G;
+        StepArgs an;
+        int ln = 0;
+        PassCIn<DT, BC> nxt;
+        TileSlotsT<DT> tsn;
+        if (gn < b.tiles) {  // uniform
+            resolve(gn, an, ln);
+            if (ln < an.ntiles) {
+                nxt.load(an, ln);
+                tsn = TileSlotsT<DT>(an, ln);
+            }
+        }
+        if (lt < a.ntiles) pass_c_run<DT, BC>(a, lt, lds, cur, ts);
+        if (gn >= b.tiles) break;
+        gt = gn;
+        a = an;
+        lt = ln;
+        cur = nxt;
+        ts = tsn;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void gather_est_kernel(const StepArgs* args, int n, double* out)
@@ -1710,6 +1805,26 @@ static hipError_t launch_naive_res(const StepArgs& a, hipStream_t s, const KTimi
     return launch1(resample_naive_kernel<DT, TPB>, dim3((unsigned)((a.n + TPB - 1) / TPB)), dim3(TPB), s, tm, a);
 }
 
+// Workgroups of `kernel` (BC threads) resident on the whole device: the
+// grid of a streaming pass C (more would only queue behind the first ones).
+template <typename K>
+static int resident_cap(K kernel, int threads)
+{
+    int dev = 0, cus = 0, occ = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, threads, 0) != hipSuccess || occ < 1 || cus < 1)
+        return 1 << 30;  // unknown: one tile per workgroup
+    return occ * cus;
+}
+
+template <int DT, int BC>
+static hipError_t launch_pass_c_stream(const StepArgs& a, hipStream_t s, const KTiming& tm)
+{
+    static const int cap = resident_cap(pass_c_kernel<DT, BC>, BC);
+    return launch1(pass_c_kernel<DT, BC>, dim3((unsigned)min(a.ntiles, cap)), dim3(BC), s, tm, a);
+}
+
 template <int DT>
 static hipError_t launch_pass_c_t(const StepArgs& a, hipStream_t s, const KTiming& tm)
 {
@@ -1733,11 +1848,11 @@ static hipError_t launch_pass_c_t(const StepArgs& a, hipStream_t s, const KTimin
     // result does not depend on the choice
     const int bc = a.threads_c ? a.threads_c : pass_c_threads(DT, a.ntiles);
     switch (bc) {
-    case 64: return launch1(pass_c_kernel<DT, 64>, g, dim3(64), s, tm, a);
-    case 128: return launch1(pass_c_kernel<DT, 128>, g, dim3(128), s, tm, a);
-    case 512: return launch1(pass_c_kernel<DT, 512>, g, dim3(512), s, tm, a);
-    case 1024: return launch1(pass_c_kernel<DT, 1024>, g, dim3(1024), s, tm, a);
-    default: return launch1(pass_c_kernel<DT, 256>, g, dim3(256), s, tm, a);
+    case 64: return launch_pass_c_stream<DT, 64>(a, s, tm);
+    case 128: return launch_pass_c_stream<DT, 128>(a, s, tm);
+    case 512: return launch_pass_c_stream<DT, 512>(a, s, tm);
+    case 1024: return launch_pass_c_stream<DT, 1024>(a, s, tm);
+    default: return launch_pass_c_stream<DT, 256>(a, s, tm);
     }
 }
 
@@ -1822,10 +1937,19 @@ hipError_t launch_batch_combine(int dtype, int cls, const BatchArgs& b, int coun
     PF_DISPATCH(dtype, launch_batch_combine_t<DT>(cls, b, count, s, tm))
 }
 
+template <int DT>
+static hipError_t launch_batch_pass_c_t(const BatchArgs& b, int tiles, hipStream_t s, const KTiming& tm)
+{
+    constexpr int BC = pass_c_threads(DT, 1 << 30);
+    static const int cap = resident_cap(pass_c_batch_kernel<DT>, BC);
+    BatchArgs bb = b;
+    bb.tiles = tiles;
+    return launch1(pass_c_batch_kernel<DT>, dim3((unsigned)min(tiles, cap)), dim3(BC), s, tm, bb);
+}
+
 hipError_t launch_batch_pass_c(int dtype, const BatchArgs& b, int tiles, hipStream_t s, const KTiming& tm)
 {
-    PF_DISPATCH(dtype, launch1(pass_c_batch_kernel<DT>, dim3((unsigned)tiles), dim3(pass_c_threads(DT, 1 << 30)),
-                               s, tm, b))
+    PF_DISPATCH(dtype, launch_batch_pass_c_t<DT>(b, tiles, s, tm))
 }
 
 hipError_t launch_gather_est(const StepArgs* args, int n, double* out, hipStream_t s)

@@ -210,6 +210,7 @@ struct BatchArgs {
     const BatchEntry* entries;
     const int32_t* tile_entry;
     int32_t entry0;     // combine: entry of the launch's first workgroup
+    int32_t tiles;      // pass C: tiles of the step's grid (set by its launcher)
 };
 
 // Optional timing of one launch: events stamped by the kernel's own dispatch
