@@ -50,6 +50,17 @@ STATE_BYTES = {"f64": 32, "f32": 16, "f16": 8, "bf16": 8}
 # pass C per update: read the propagated position and the tile-local prefix
 # sum, write the resampled position
 PASS_C_BYTES = {"f64": 16 + 8 + 16, "f32": 8 + 4 + 8, "f16": 4 + 4 + 4, "bf16": 4 + 4 + 4}
+# pass A per update: read the state, write the propagated position and the
+# tile-local prefix sum
+PASS_A_BYTES = {"f64": 16 + 16 + 8, "f32": 8 + 8 + 4, "f16": 4 + 4 + 4, "bf16": 4 + 4 + 4}
+
+
+def step_bound_s(dtype, radius, n):
+    """Roofline time of one step of n particles: pass A at the larger of its
+    VALU and HBM times, then pass C at its HBM time (the combine's work is
+    per tile, negligible); the passes run one after the other."""
+    a = max(pass_a_slots(dtype, radius) / PEAK_LANE_OPS, PASS_A_BYTES[dtype] / PEAK_HBM)
+    return n * (a + PASS_C_BYTES[dtype] / PEAK_HBM)
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "pass_a_f16_disk1024_n1m_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2308_00763_amd", "csrc", f)
                   for f in ("kernels.hip", "philox.hpp", "wave.hpp", "pf_internal.hpp")]
@@ -183,6 +194,7 @@ def run_fleet(pf, torch, pfsynth, n_streams, side, frames, steps, warmup, dtype=
                          f"N log-uniform in [256, 65536]",
                 dtype=dtype, filters=n_streams, particles=total, steps=steps, warmup=warmup,
                 ms_per_step=1e3 * secs / steps, updates_per_s=total * steps / secs,
+                step_roofline_frac=step_bound_s(dtype, 5, total) / (secs / steps),
                 final_error_median_px=float(np.median(err)),
                 final_error_p99_px=float(np.percentile(err, 99)))
 
@@ -368,6 +380,7 @@ def run_large(pf, torch, pfsynth, args, modes):
         _, prof = run_mode(pf, torch, fl, vl.centres, wl, dt, ls, lw, profile=True)
         a_us = 1e3 * prof[0] / prof[3]
         lres[dt] = dict(ms_per_step=1e3 * secs / ls, updates_per_s=wl.n_particles * ls / secs,
+                        step_roofline_frac=step_bound_s(dt, wl.radius, wl.n_particles) / (secs / ls),
                         pass_a_us=a_us, combine_us=1e3 * prof[1] / prof[3],
                         pass_c_us=1e3 * prof[2] / prof[3],
                         pass_a_roofline_frac=pass_a_slots(dt, wl.radius) * wl.n_particles
@@ -466,6 +479,7 @@ def main():
         a_ms, m_ms, c_ms, n = prof
         res[dt] = dict(seconds=secs, ms_per_step=1e3 * secs / args.steps,
                        updates_per_s=w.n_particles * args.steps / secs,
+                       step_roofline_frac=step_bound_s(dt, w.radius, w.n_particles) / (secs / args.steps),
                        pass_a_us=1e3 * a_ms / n, combine_us=1e3 * m_ms / n, pass_c_us=1e3 * c_ms / n,
                        ms_per_step_with_events=1e3 * psecs / args.steps)
         log(f"[bench] {dt}: {res[dt]}")
