@@ -156,7 +156,7 @@ def run_fleet(pf, torch, pfsynth, n_streams, side, frames, steps, warmup, dtype=
     [256, 65536]) on their own side x side videos, drawn on the device and
     resident before timing; one pf_batch_step per frame index."""
     import ctypes
-    assert warmup + steps <= frames - 1
+    assert warmup + steps <= frames - 2
     streams = pfsynth.stream_mix(n_streams, side=side, frames=frames)
     log(f"[bench] fleet: drawing {frames} frames of {n_streams} streams ({side}x{side}) on the device")
     vids = torch.stack([pfsynth.render_fleet_torch(streams, t, side, 5, "cuda:0", seed=4_000_000)
@@ -164,7 +164,8 @@ def run_fleet(pf, torch, pfsynth, n_streams, side, frames, steps, warmup, dtype=
     params = [pf.make_params(s.n_particles, side, side, dtype, radius=5, x0=s.start[0],
                              y0=s.start[1], drift=s.velocity, seed=0, stream_id=s.stream_id)
               for s in streams]
-    b = pf.Batch(params)
+    side_stream = torch.cuda.Stream()  # a stream that can be captured
+    b = pf.Batch(params, stream=side_stream)
     base = int(vids.data_ptr())
     fstride, sstride = int(vids.stride(0)), int(vids.stride(1))
     ptrs = [np.array([base + t * fstride + k * sstride for k in range(n_streams)], dtype=np.uint64)
@@ -187,6 +188,21 @@ def run_fleet(pf, torch, pfsynth, n_streams, side, frames, steps, warmup, dtype=
     truth = np.array([[s.start[0] + s.velocity[0] * t_end, s.start[1] + s.velocity[1] * t_end]
                       for s in streams])
     err = np.hypot(*(est - truth).T)
+    # the same step captured in a HIP graph and replayed (on the next frame
+    # index's frames, the same ones at every replay)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side_stream):
+        if step(h, ctypes.c_void_p(ptrs[t_end + 1].ctypes.data), pp, None):
+            raise pf.PfError(-1, pf.pf_last_error())
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    gsecs = time.perf_counter() - t0
+    assert np.all(np.isfinite(b.estimates()))
+    del g
     b.close()
     total = sum(p.n_particles for p in params)
     return dict(workload=f"{n_streams} streams, {side}x{side} uint8 video each (drawn on the device), "
@@ -195,6 +211,7 @@ def run_fleet(pf, torch, pfsynth, n_streams, side, frames, steps, warmup, dtype=
                 dtype=dtype, filters=n_streams, particles=total, steps=steps, warmup=warmup,
                 ms_per_step=1e3 * secs / steps, updates_per_s=total * steps / secs,
                 step_roofline_frac=step_bound_s(dtype, 5, total) / (secs / steps),
+                graph_ms_per_step=1e3 * gsecs / steps,
                 final_error_median_px=float(np.median(err)),
                 final_error_p99_px=float(np.percentile(err, 99)))
 
