@@ -362,6 +362,27 @@ def run_resamplers(pf, torch, frames_dev, centres, w, steps, warmup, dtypes=("f1
     return res
 
 
+# The paper's FP16 speedups (whole application, 32k and 64k particles, on
+# V100, A100, A40 and T4): context for this GPU's ratios, not a target.
+PAPER_SPEEDUPS = {"fp16_vs_fp32": "1.5-2x", "fp16_vs_fp64": "2.5-4.6x",
+                  "hardware": "V100, A100, A40, T4", "particles": "32768 and 65536"}
+
+
+def run_paper_sizes(pf, torch, frames_dev, centres, w, steps, warmup):
+    """FP16, FP32 and FP64 steps at the paper's particle counts on the
+    headline video, with the FP16 speedups the paper reports for them."""
+    import dataclasses
+    out = {"paper": PAPER_SPEEDUPS}
+    for n in (32768, 65536):
+        wl = dataclasses.replace(w, n_particles=n, name=f"{w.name}_n{n}")
+        ms = {}
+        for dt in ("f16", "f32", "f64"):
+            secs, _ = run_mode(pf, torch, frames_dev, centres, wl, dt, steps, warmup, False)
+            ms[dt] = 1e3 * secs / steps
+        out[str(n)] = dict(ms_per_step=ms, fp16_vs_fp32=ms["f32"] / ms["f16"], fp16_vs_fp64=ms["f64"] / ms["f16"])
+    return out
+
+
 def run_accuracy(pf, torch, pfsynth, modes):
     """The paper's accuracy video (512x512, 100 frames, bounce off y = 0,
     128 particles): per mode the RMS distance of the free-running estimates to
@@ -570,6 +591,8 @@ def main():
                                                  min(args.steps, 40), args.warmup))
         section("resamplers", lambda: run_resamplers(pf, torch, frames_dev, vid.centres, w,
                                                      min(args.steps, 40), args.warmup))
+        section("paper_sizes", lambda: run_paper_sizes(pf, torch, frames_dev, vid.centres, w,
+                                                       min(args.steps, 40), args.warmup))
     if not args.no_ablation:
         def tune_headline():
             from paper_2308_00763_amd.tune import autotune
