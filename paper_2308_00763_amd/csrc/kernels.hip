@@ -14,11 +14,11 @@
 //            carried cumulative offset of every tile, normaliser Z, estimate,
 //            resampling offset u0, each tile's end slot and, in the reduced
 //            modes, the origin of the next propagation.
-//   pass C   systematic resampling as a merge of two sorted sequences: the
-//            particles' end slots e_i = #{j : (j + u0)/N <= C_i} and the slots
-//            0..N-1 (merge path: every workgroup takes the same number of
-//            particles + slots whatever the weights), gathering the
-//            propagated position of each slot's ancestor.
+//   pass C   systematic resampling: the particles' end slots
+//            e_i = #{j : (j + u0)/N <= C_i}, each particle's first slot marked,
+//            a maximum scan over the slots giving every slot its ancestor
+//            (the same work whatever the weights), and the gather of the
+//            ancestors' propagated positions.
 //
 // The maximum and weighting are fused into pass A and the cumulative
 // distribution is evaluated on the fly in pass C, so the six kernels of the
@@ -1313,22 +1313,22 @@ __global__ __launch_bounds__(kGroupTiles) void combine_finish_kernel(StepArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// Pass C: merge-path scatter, one workgroup per tile.
+// Pass C: the slot fill, one tile per workgroup at a time.
 //
 // The slots of tile t are [E_{t-1}, E_t); inside the tile, particle k owns
-// the local slots [e_{k-1}, e_k) (local end slots e_k = e_i - E_{t-1},
-// non-decreasing, the last one E_t - E_{t-1}).  The tile's particles and slots
-// form two sorted sequences; their merge (a particle going before local slot
-// j when e_k <= j) is cut into equal pieces, one per thread: with
-// g(k) = e_k + k strictly increasing, the cut at diagonal d is the first k
-// with g(k) >= d.  Each thread finds its cut by a binary search over the
-// tile's end slots in LDS, then walks its piece, noting the ancestor of every
-// slot it meets in LDS; the workgroup then writes the ancestors' propagated
+// the local slots [b_k, e_k), e_k its local end slot (e_i - E_{t-1},
+// non-decreasing, the last one E_t - E_{t-1}) and b_k = e_{k-1} (b_0 = 0).
+// Every particle that owns a slot marks its first slot b_k with k + 1: the
+// marked slots are distinct and increase with k, so the ancestor of slot j is
+// the last mark at or before j, which an inclusive maximum scan over the
+// slots fills in (each thread a run of consecutive slots, then a wave scan
+// and the wave totals).  The workgroup then writes the ancestors' propagated
 // positions to the slots with consecutive lanes on consecutive slots.  A tile
-// that owns many slots takes several rounds of at most kDiagRound diagonals;
-// the work never depends on how the slots are spread inside the tile.
+// that owns more than kSlotRound slots takes several rounds, each carrying
+// the last mark of the one before; the work depends only on the tile's
+// particle and slot counts, never on how the slots are spread.
 
-constexpr int kDiagRound = 4096;  // merge diagonals per round
+constexpr int kSlotRound = 4096;  // slots per round
 
 template <int DT>
 struct PassCLds {
@@ -1336,20 +1336,9 @@ struct PassCLds {
     int32_t e[kTile];
     Store x[kTile];
     Store y[kTile];
-    uint16_t anc[kDiagRound];  // tile-local ancestor of each slot of the round
+    uint16_t anc[kSlotRound];  // marks, then tile-local ancestors, of the round's slots
+    int32_t red[16];           // wave totals of the scan (up to 1024 threads)
 };
-
-// First k in [0, tt] with e[k] + k >= d (k = tt stands for true).
-__device__ __forceinline__ int merge_cut(const int32_t* e, int tt, int d)
-{
-    int lo = 0, hi = tt;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (e[mid] + mid >= d) hi = mid;
-        else lo = mid + 1;
-    }
-    return lo;
-}
 
 // One tile's pass-C inputs in registers: its particles' cumulative weights
 // and propagated positions, thread tid holding particles tid + r BC.  Loaded
@@ -1382,8 +1371,8 @@ struct PassCIn {
 
 // Pass C of tile `t` of the filter described by `a`, BC threads, from its
 // inputs `in` and slot map `ts`: end slots and positions to LDS, then the
-// merge-path scatter.  Every thread takes part; the workgroup is free for the
-// next tile when it returns.
+// slot fill and the scatter.  Every thread takes part; the workgroup is free
+// for the next tile when it returns.
 template <int DT, int BC>
 __device__ __forceinline__ void pass_c_run(const StepArgs& a, int t, PassCLds<DT>& lds, const PassCIn<DT, BC>& in,
                                            const TileSlotsT<DT>& ts)
@@ -1403,7 +1392,7 @@ __device__ __forceinline__ void pass_c_run(const StepArgs& a, int t, PassCLds<DT
         if (k < tt) {
             // local end slot, at least 0: a particle whose end slot precedes
             // the tile's first slot (the combine's prefix maximum can raise
-            // it) owns no slot, and the merge's first cut stays at 0
+            // it) owns no slot
             const int e = k == tt - 1 ? ts.E : ts.of(in.q[r], n);
             s_e[k] = max(e - ts.Eprev, 0);
             s_x[k] = in.x[r];
@@ -1413,36 +1402,50 @@ __device__ __forceinline__ void pass_c_run(const StepArgs& a, int t, PassCLds<DT
     __syncthreads();
     const int slots = ts.E - ts.Eprev;
     if (slots > 0) {  // uniform over the workgroup
-        const int total = tt + slots;
-        const int ipt = min((total + BC - 1) / BC, kDiagRound / BC);
-        const int round = ipt * BC;
+        const int lane = tid & 63, wv = tid >> 6;
         Store* sx = static_cast<Store*>(a.sx) + ts.Eprev;
         Store* sy = static_cast<Store*>(a.sy) + ts.Eprev;
         int32_t* anc_out = a.dg_anc ? a.dg_anc + ts.Eprev : nullptr;
-        for (int d0 = 0; d0 < total; d0 += round) {
-            // slots of this round: [j0, j1), the slot coordinates of its two cuts
-            const int d1 = min(d0 + round, total);
-            const int j0 = d0 == 0 ? 0 : d0 - merge_cut(s_e, tt, d0);
-            const int j1 = d1 == total ? slots : d1 - merge_cut(s_e, tt, d1);
-            const int ds = min(d0 + tid * ipt, d1), de = min(ds + ipt, d1);
-            if (ds < de) {
-                int k = merge_cut(s_e, tt, ds), j = ds - k;
-                for (int d = ds; d < de; ++d) {
-                    if (k < tt && s_e[k] <= j) {
-                        ++k;  // particle k has no slot left: the merge takes it
-                    } else {
-                        lds.anc[j - j0] = (uint16_t)min(k, tt - 1);
-                        ++j;
-                    }
+        int carry = 0;  // the last mark of the previous round (none before the first)
+        for (int j0 = 0; j0 < slots; j0 += kSlotRound) {
+            const int nj = min(kSlotRound, slots - j0);
+            for (int i = tid; i < nj; i += BC) lds.anc[i] = 0;
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < kTile / BC; ++r) {
+                const int k = tid + r * BC;
+                if (k < tt) {
+                    const int b = k == 0 ? 0 : s_e[k - 1];
+                    if (s_e[k] > b && b >= j0 && b < j0 + nj) lds.anc[b - j0] = (uint16_t)(k + 1);
                 }
             }
             __syncthreads();
-            for (int i = tid; i < j1 - j0; i += BC) {
+            // inclusive maximum scan of the marks; thread tid owns the slots
+            // [tid spt, tid spt + spt) of the round
+            const int spt = (nj + BC - 1) / BC;
+            const int s0 = tid * spt;
+            int run = 0;
+            for (int i = 0; i < spt; ++i)
+                if (s0 + i < nj) run = max(run, (int)lds.anc[s0 + i]);
+            const int sc = wave_incl_scan<OpMax>(run);
+            if (lane == 63) lds.red[wv] = sc;
+            __syncthreads();
+            int m = max(carry, wave_shift_up1(sc, 0));
+            for (int w = 0; w < wv; ++w) m = max(m, lds.red[w]);
+            for (int i = 0; i < spt; ++i) {
+                if (s0 + i < nj) {
+                    m = max(m, (int)lds.anc[s0 + i]);
+                    lds.anc[s0 + i] = (uint16_t)(m - 1);
+                }
+            }
+            __syncthreads();
+            for (int i = tid; i < nj; i += BC) {
                 const int kk = lds.anc[i];
                 sx[j0 + i] = s_x[kk];
                 sy[j0 + i] = s_y[kk];
                 if (anc_out) anc_out[j0 + i] = first + kk;
             }
+            carry = (int)lds.anc[nj - 1] + 1;
             __syncthreads();
         }
     }
@@ -1450,9 +1453,9 @@ __device__ __forceinline__ void pass_c_run(const StepArgs& a, int t, PassCLds<DT
 
 // Pass C of one filter over a grid of G <= ntiles workgroups: workgroup g
 // takes tiles g, g + G, ... and loads each tile's inputs while it scatters
-// the one before, so a workgroup's memory latency overlaps its own merge.
+// the one before, so a workgroup's memory latency overlaps its own slot fill.
 template <int DT, int BC>
-__global__ __launch_bounds__(BC) void pass_c_kernel(StepArgs a)
+__global__ __launch_bounds__(BC, BC >= 256 ? 8 : 1) void pass_c_kernel(StepArgs a)
 {
     __shared__ PassCLds<DT> lds;
     const int nt = a.ntiles, G = gridDim.x;
@@ -1706,7 +1709,7 @@ __global__ __launch_bounds__(NT) void combine_batch_kernel(BatchArgs b)
 // whatever filters they belong to, loading each tile's arguments and inputs
 // while it scatters the one before.
 template <int DT>
-__global__ __launch_bounds__(pass_c_threads(DT, 1 << 30)) void pass_c_batch_kernel(BatchArgs b)
+__global__ __launch_bounds__(pass_c_threads(DT, 1 << 30), 8) void pass_c_batch_kernel(BatchArgs b)
 {
     constexpr int BC = pass_c_threads(DT, 1 << 30);
     __shared__ PassCLds<DT> lds;
