@@ -82,7 +82,7 @@ typedef enum pf_lik_norm { PF_LIK_MEAN = 0, PF_LIK_SUM = 1 } pf_lik_norm;
  *   PF_FLAG_NAIVE_RESAMPLE   -- the normalised cumulative distribution is
  *       written out (one division per particle; double in PF_F64, float
  *       otherwise), then one thread per slot binary-searches it, instead of
- *       the tile-wise merge.  Costs N more elements of workspace.
+ *       the tile-wise slot fill.  Costs N more elements of workspace.
  *   Threads per workgroup, as a field value v in 1..5 selecting 2^(v+5)
  *   threads (64, 128, 256, 512, 1024; 0 = the default):
  *     bits 8-11 (PF_THREADS_A_SHIFT)  pass A, 1024 particles per workgroup:
