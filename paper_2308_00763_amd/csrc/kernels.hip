@@ -797,12 +797,18 @@ struct CombAcc<PF_F32> {
 template <bool F64>
 struct SlotMap;
 
+// The Philox words of the step's resampling offset (counter (0, t, stream_id, 1)).
+__device__ __forceinline__ u32x4 u0_words(const StepArgs& a, uint32_t t)
+{
+    return philox4x32_10(0u, t, a.stream_id, 1u, a.key0, a.key1);
+}
+
 template <>
 struct SlotMap<true> {
     double R, mu0, u0;
-    __device__ SlotMap(const StepArgs& a, double Z, uint32_t t)
+    __device__ SlotMap(const StepArgs& a, double Z, uint32_t t) : SlotMap(a, Z, u0_words(a, t)) {}
+    __device__ SlotMap(const StepArgs& a, double Z, const u32x4& wu)
     {
-        const u32x4 wu = philox4x32_10(0u, t, a.stream_id, 1u, a.key0, a.key1);
         u0 = uniform53(wu.v0, wu.v1);
         R = (double)(int)a.n / Z;
         mu0 = -u0;
@@ -813,10 +819,10 @@ struct SlotMap<true> {
 template <>
 struct SlotMap<false> {
     ff R, mu0, u0;
-    __device__ SlotMap(const StepArgs& a, ff Z, uint32_t t)
+    __device__ SlotMap(const StepArgs& a, ff Z, uint32_t t) : SlotMap(a, Z, u0_words(a, t)) {}
+    __device__ SlotMap(const StepArgs& a, ff Z, const u32x4& wu)
     {
         const int n = (int)a.n;
-        const u32x4 wu = philox4x32_10(0u, t, a.stream_id, 1u, a.key0, a.key1);
         const uint64_t bits = ((uint64_t)wu.v0 << 21) | (uint64_t)(wu.v1 >> 11);
         u0 = fast_two_sum((float)(uint32_t)(bits >> 29) * 0x1.0p-24f,
                           (float)(uint32_t)(bits & 0x1FFFFFFFu) * 0x1.0p-53f);
@@ -899,8 +905,15 @@ __device__ __forceinline__ void combine_filter(const StepArgs& a)
     const Rec* rec = static_cast<const Rec*>(a.rec);
     Tab* tab = static_cast<Tab*>(a.tab);
     const uint32_t tn = a.blk->t + 1u;  // this step (thread 0 advances the count at the end)
+    // the resampling offset's random words do not depend on the weights: drawn
+    // first, they overlap the loads of the records
+    const u32x4 wu0 = u0_words(a, tn);
 
-    // global maximum of the tile maxima
+    // global maximum of the tile maxima; with a single round the records stay
+    // in registers for the scan
+    constexpr bool KEEP = KPER <= 4;
+    const bool one_round = KEEP && nt <= CHUNK;
+    Rec r_keep[KEEP ? KPER : 1];
     Mx m = F64 ? (Mx)-INFINITY : (Mx)INT32_MIN;
     for (int base = 0; base < nt; base += CHUNK) {
 #pragma unroll
@@ -908,7 +921,12 @@ __device__ __forceinline__ void combine_filter(const StepArgs& a)
             const int t = base + tid * KPER + k;
             if (t < nt) {
                 Mx mt;
-                if constexpr (F64) mt = rec[t].m; else mt = rec[t].smax;
+                if (one_round) {
+                    r_keep[KEEP ? k : 0] = rec[t];
+                    if constexpr (F64) mt = r_keep[KEEP ? k : 0].m; else mt = r_keep[KEEP ? k : 0].smax;
+                } else {
+                    if constexpr (F64) mt = rec[t].m; else mt = rec[t].smax;
+                }
                 m = mt > m ? mt : m;
             }
         }
@@ -924,8 +942,7 @@ __device__ __forceinline__ void combine_filter(const StepArgs& a)
     // scan of the wave totals by wave 0; the total is the normaliser
     T carry = A::zero();
     Fv ex = 0, ey = 0;
-    constexpr bool KEEP = KPER <= 4;  // keep offsets in registers for the end slots
-    T o_keep[KEEP ? KPER : 1];
+    T o_keep[KEEP ? KPER : 1];  // offsets kept in registers for the end slots
     for (int base = 0; base < nt; base += CHUNK) {
         Fv f[KPER];
         T v[KPER];
@@ -936,7 +953,7 @@ __device__ __forceinline__ void combine_filter(const StepArgs& a)
             f[k] = 0;
             v[k] = A::zero();
             if (t < nt) {
-                const Rec rr = rec[t];
+                const Rec rr = one_round ? r_keep[KEEP ? k : 0] : rec[t];
                 if constexpr (F64) {
                     f[k] = exp(rr.m - gm);
                     v[k] = f[k] * rr.s;
@@ -989,9 +1006,8 @@ __device__ __forceinline__ void combine_filter(const StepArgs& a)
     // its tiles with), made non-decreasing by a prefix maximum so that the
     // tiles' slot ranges [E_{t-1}, E_t) partition [0, N) whatever the
     // rounding of the offsets; the last tile ends at N.
-    const SlotMap<F64> smap(a, Z, tn);
+    const SlotMap<F64> smap(a, Z, wu0);
     auto end_of = [&](T o) -> int { return smap.end_of(o, n); };
-    const bool one_round = KEEP && nt <= CHUNK;
     int carry_e = 0;
     for (int base = 0; base < nt; base += CHUNK) {
         int Ek[KPER];
