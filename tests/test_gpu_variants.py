@@ -100,6 +100,20 @@ def test_variants_with_the_same_arithmetic_are_bit_identical(variant, dtype):
         assert np.array_equal(g0[key], g1[key]), key
 
 
+@pytest.mark.parametrize("threads_c", [64, 1024])
+@pytest.mark.parametrize("dtype", ["f64", "f16"])
+def test_streaming_pass_c_sizes_are_bit_identical_over_many_tiles(threads_c, dtype):
+    # 4097 tiles: each resident pass-C workgroup streams several of them (a
+    # grid of a few hundred 1024-thread workgroups, or of a few thousand
+    # 64-thread ones), and the last tile is ragged
+    n = (1 << 22) + 77
+    e0, g0 = _free_run(dtype, n)
+    e1, g1 = _free_run(dtype, n, threads_c=threads_c)
+    assert np.array_equal(e0, e1)
+    for key in ("x", "y", "w", "anc"):
+        assert np.array_equal(g0[key], g1[key]), key
+
+
 def test_variant_flags_are_checked():
     for bad in (dict(threads_a=64), dict(threads_a=1024)):
         with pytest.raises(pf.PfError):
