@@ -1802,10 +1802,12 @@ static hipError_t launch_pass_a_t(const StepArgs& a, hipStream_t s, const KTimin
     const dim3 g((unsigned)a.ntiles);
     if (a.threads_a == 128) {  // 8 particles per thread
         if (a.r == 5) return launch1(pass_a_kernel<DT, 5, 8>, g, dim3(128), s, tm, a);
+        if (a.r == 8) return launch1(pass_a_kernel<DT, 8, 8>, g, dim3(128), s, tm, a);
         return launch1(pass_a_kernel<DT, 0, 8>, g, dim3(128), s, tm, a);
     }
     if (a.threads_a == 512) {  // 2 particles per thread
         if (a.r == 5) return launch1(pass_a_kernel<DT, 5, 2>, g, dim3(512), s, tm, a);
+        if (a.r == 8) return launch1(pass_a_kernel<DT, 8, 2>, g, dim3(512), s, tm, a);
         return launch1(pass_a_kernel<DT, 0, 2>, g, dim3(512), s, tm, a);
     }
     const dim3 blk(kBlockA);
@@ -1862,9 +1864,8 @@ static hipError_t launch_pass_c_t(const StepArgs& a, hipStream_t s, const KTimin
         }
     }
     // default: 512 threads while the grid is at most four tiles per CU
-    // (latency-bound) and in the FP64 mode (whose 28 KB of LDS per tile
-    // caps the tiles per CU), else 256 (more tiles in flight per CU); the
-    // result does not depend on the choice
+    // (latency-bound), else 256 (more workgroups in flight per CU, each
+    // streaming tiles); the result does not depend on the choice
     const int bc = a.threads_c ? a.threads_c : pass_c_threads(DT, a.ntiles);
     switch (bc) {
     case 64: return launch_pass_c_stream<DT, 64>(a, s, tm);
