@@ -216,6 +216,55 @@ def run_fleet(pf, torch, pfsynth, n_streams, side, frames, steps, warmup, dtype=
                 final_error_p99_px=float(np.percentile(err, 99)))
 
 
+SERVE_SIDES = (64, 128, 256, 512, 1024)
+SERVE_BANK_T = 560
+
+
+def _serving_bank(torch, pfsynth, rng):
+    """Device-resident bank of bouncing-disk videos: four per frame side,
+    560 frames each, noise sigma ~ U[2, 6], velocity in {-3..3}^2."""
+    log("[bench] serving: drawing the video bank on the device")
+    bank = {}
+    for side in SERVE_SIDES:
+        for j in range(4):
+            v = (int(rng.integers(-3, 4)), int(rng.integers(-3, 4)))
+            start = (int(rng.integers(5, side - 5)), int(rng.integers(5, side - 5)))
+            cen = pfsynth.trajectory(SERVE_BANK_T, start, v, side, side, 5, bounce=True)
+            sig = float(rng.uniform(2.0, 6.0))
+            bank[(side, j)] = (cen, pfsynth.render_video_torch(cen, side, 5, sig, "cuda:0",
+                                                                seed=7_000 + 10 * side + j))
+    return bank
+
+
+def _serving_pools(hbm_gb):
+    from paper_2308_00763_amd.serve import GpuPoolBackend, plan_pool, slot_classes
+    caps = slot_classes(1000, 1_000_000)
+    pools = {"f16": plan_pool(int(hbm_gb[0] * 2**30), "f16", caps),
+             "f32": plan_pool(int(hbm_gb[1] * 2**30), "f32", caps)}
+    log(f"[bench] serving: pools {pools}")
+    return GpuPoolBackend(pools)
+
+
+def _serving_request(pf, rng, bank, sid, arrival, fps, frames=None):
+    """One stream of the serving mix: frames ~ U{20..500} (or `frames`), side
+    ~ U{64, ..., 1024}, N = round(exp(U(ln 1e3, ln 1e6))), FP16 or FP32 with
+    probability 1/2, from a random bank video at a random start frame."""
+    from paper_2308_00763_amd.serve import StreamRequest
+    frames = int(rng.integers(20, 501)) if frames is None else frames
+    side = int(rng.choice(SERVE_SIDES))
+    j = int(rng.integers(0, 4))
+    cen, vid = bank[(side, j)]
+    o = int(rng.integers(0, SERVE_BANK_T - frames + 1))
+    n = int(round(float(np.exp(rng.uniform(np.log(1e3), np.log(1e6))))))
+    dtype = "f16" if rng.random() < 0.5 else "f32"
+    d = cen[o + 1] - cen[o]
+    p = pf.make_params(n, side, side, dtype, x0=cen[o][0], y0=cen[o][1], drift=(d[0], d[1]),
+                       seed=5, stream_id=sid)
+    base, fst, pitch = int(vid.data_ptr()), int(vid.stride(0)), int(vid.stride(1))
+    return StreamRequest(sid, arrival, p, frames, fps,
+                         lambda i, b=base + o * fst, s=fst, q=pitch: (b + i * s, q))
+
+
 def run_serving(pf, torch, pfsynth, seconds, warmup_s, rate=200.0, fps=30.0, hbm_gb=(6.0, 12.0)):
     """Continuous batching of arriving streams: Poisson arrivals at `rate`
     streams/s (PCG64(5)); per stream frames ~ U{20..500} at `fps`, side ~
@@ -225,25 +274,10 @@ def run_serving(pf, torch, pfsynth, seconds, warmup_s, rate=200.0, fps=30.0, hbm
     bouncing-disk videos (four per side, 560 frames) at a random start frame.
     Latency is frame arrival to estimate ready, over frames arriving after
     `warmup_s`."""
-    from paper_2308_00763_amd.serve import GpuPoolBackend, Scheduler, StreamRequest, plan_pool, slot_classes
-    sides = [64, 128, 256, 512, 1024]
-    bank_T = 560
+    from paper_2308_00763_amd.serve import Scheduler
     rng = np.random.Generator(np.random.PCG64(5))
-    log("[bench] serving: drawing the video bank on the device")
-    bank = {}
-    for side in sides:
-        for j in range(4):
-            v = (int(rng.integers(-3, 4)), int(rng.integers(-3, 4)))
-            start = (int(rng.integers(5, side - 5)), int(rng.integers(5, side - 5)))
-            cen = pfsynth.trajectory(bank_T, start, v, side, side, 5, bounce=True)
-            sig = float(rng.uniform(2.0, 6.0))
-            bank[(side, j)] = (cen, pfsynth.render_video_torch(cen, side, 5, sig, "cuda:0",
-                                                                seed=7_000 + 10 * side + j))
-    caps = slot_classes(1000, 1_000_000)
-    pools = {"f16": plan_pool(int(hbm_gb[0] * 2**30), "f16", caps),
-             "f32": plan_pool(int(hbm_gb[1] * 2**30), "f32", caps)}
-    log(f"[bench] serving: pools {pools}")
-    be = GpuPoolBackend(pools)
+    bank = _serving_bank(torch, pfsynth, rng)
+    be = _serving_pools(hbm_gb)
     sched = Scheduler(be, stall_timeout=5.0)
     total = warmup_s + seconds
     t = 0.0
@@ -253,19 +287,7 @@ def run_serving(pf, torch, pfsynth, seconds, warmup_s, rate=200.0, fps=30.0, hbm
         t += float(rng.exponential(1.0 / rate))
         if t > total:
             break
-        frames = int(rng.integers(20, 501))
-        side = int(rng.choice(sides))
-        j = int(rng.integers(0, 4))
-        cen, vid = bank[(side, j)]
-        o = int(rng.integers(0, bank_T - frames + 1))
-        n = int(round(float(np.exp(rng.uniform(np.log(1e3), np.log(1e6))))))
-        dtype = "f16" if rng.random() < 0.5 else "f32"
-        d = cen[o + 1] - cen[o]
-        p = pf.make_params(n, side, side, dtype, x0=cen[o][0], y0=cen[o][1], drift=(d[0], d[1]),
-                           seed=5, stream_id=sid)
-        base, fst, pitch = int(vid.data_ptr()), int(vid.stride(0)), int(vid.stride(1))
-        sched.submit(StreamRequest(sid, t_base + t, p, frames, fps,
-                                   lambda i, b=base + o * fst, s=fst, q=pitch: (b + i * s, q)))
+        sched.submit(_serving_request(pf, rng, bank, sid, t_base + t, fps))
         sid += 1
     log(f"[bench] serving: {sid} streams over {total:.0f} s; running")
     while time.perf_counter() < t_base:
@@ -299,25 +321,48 @@ def run_serving(pf, torch, pfsynth, seconds, warmup_s, rate=200.0, fps=30.0, hbm
     return summ
 
 
-ABLATION = [
-    ("optimised", {}),
-    ("naive likelihood (every disk pixel from the frame)", dict(naive_likelihood=True)),
-    ("naive resampling, 64 threads", dict(naive_resample=True, threads_c=64)),
-    ("naive resampling, 128 threads", dict(naive_resample=True, threads_c=128)),
-    ("naive resampling, 256 threads", dict(naive_resample=True, threads_c=256)),
-    ("naive resampling, 512 threads", dict(naive_resample=True, threads_c=512)),
-    ("naive resampling, 1024 threads", dict(naive_resample=True, threads_c=1024)),
-    ("naive likelihood + resampling, 128 threads",
-     dict(naive_likelihood=True, naive_resample=True, threads_c=128)),
-    ("pass A 128 threads (8 particles each)", dict(threads_a=128)),
-    ("pass A 256 threads (4 particles each)", dict(threads_a=256)),
-    ("pass A 512 threads (2 particles each)", dict(threads_a=512)),
-    ("pass C 64 threads", dict(threads_c=64)),
-    ("pass C 128 threads", dict(threads_c=128)),
-    ("pass C 256 threads", dict(threads_c=256)),
-    ("pass C 512 threads", dict(threads_c=512)),
-    ("pass C 1024 threads", dict(threads_c=1024)),
-]
+def run_serving_closed(pf, torch, pfsynth, seconds, n_streams=1770, hbm_gb=(6.0, 12.0)):
+    """Closed-loop serving capacity: a constant population of n_streams
+    streams of the serving mix (500 frames each; a finished stream is
+    replaced at once), every frame already waiting (a frame rate far above
+    what is served), so every tick steps every live stream; ticks, frames and
+    particle-updates per second over `seconds`."""
+    from paper_2308_00763_amd.serve import Scheduler
+    rng = np.random.Generator(np.random.PCG64(6))
+    bank = _serving_bank(torch, pfsynth, rng)
+    be = _serving_pools(hbm_gb)
+    sched = Scheduler(be, stall_timeout=60.0)
+    sid = 0
+
+    def top_up():
+        # streams in the population: admitted, waiting for a slot, or submitted
+        # and not yet arrived (a rejected submission ends the top-up)
+        nonlocal sid
+        now = time.perf_counter()
+        while len(sched.live) + len(sched.queue) + len(sched.pending) < n_streams:
+            ok = sched.submit(_serving_request(pf, rng, bank, sid, now, 1.0e6, frames=500))
+            sid += 1
+            if not ok:
+                break
+
+    top_up()
+    for _ in range(20):  # warm-up ticks
+        sched.tick()
+        top_up()
+    ticks = 0
+    f0, u0 = len(sched.latencies), sched.updates
+    t_start = time.perf_counter()
+    while time.perf_counter() < t_start + seconds:
+        sched.tick()
+        top_up()
+        ticks += 1
+    dt = time.perf_counter() - t_start
+    out = dict(workload=f"{n_streams} live streams of the serving mix, 500 frames each, a finished stream "
+                        f"replaced at once, every frame waiting", seconds=dt, ticks_per_s=ticks / dt,
+               frames_per_s=(len(sched.latencies) - f0) / dt, updates_per_s=(sched.updates - u0) / dt,
+               streams_submitted=sid, live_at_end=len(sched.live), queued_at_end=len(sched.queue))
+    be.close()
+    return out
 
 
 def run_ablation(pf, torch, frames_dev, centres, w, steps, warmup, dtypes=("f16", "f64")):
@@ -609,6 +654,7 @@ def main():
         section("fleet", lambda: run_fleet(pf, torch, pfsynth, args.fleet, 256, 50, 40, 5))
     if args.serve_seconds > 0:
         section("serving", lambda: run_serving(pf, torch, pfsynth, args.serve_seconds, 10.0))
+        section("serving_closed_loop", lambda: run_serving_closed(pf, torch, pfsynth, 10.0))
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         section("cpu_baseline", lambda: cpu_baseline(w, vid, args.cpu_budget))
