@@ -350,7 +350,7 @@ def run_serving_closed(pf, torch, pfsynth, seconds, n_streams=1770, hbm_gb=(6.0,
         sched.tick()
         top_up()
     ticks = 0
-    f0, u0 = len(sched.latencies), sched.updates
+    f0, u0, s0 = len(sched.latencies), sched.updates, sched.step_seconds
     t_start = time.perf_counter()
     while time.perf_counter() < t_start + seconds:
         sched.tick()
@@ -360,7 +360,11 @@ def run_serving_closed(pf, torch, pfsynth, seconds, n_streams=1770, hbm_gb=(6.0,
     out = dict(workload=f"{n_streams} live streams of the serving mix, 500 frames each, a finished stream "
                         f"replaced at once, every frame waiting", seconds=dt, ticks_per_s=ticks / dt,
                frames_per_s=(len(sched.latencies) - f0) / dt, updates_per_s=(sched.updates - u0) / dt,
-               streams_submitted=sid, live_at_end=len(sched.live), queued_at_end=len(sched.queue))
+               # the backend's share of a tick (the batched steps and the
+               # estimates' read-back, which waits for them); the rest is
+               # the scheduler's own per-stream work on the host
+               backend_ms_per_tick=1e3 * (sched.step_seconds - s0) / max(ticks, 1),
+               ms_per_tick=1e3 * dt / max(ticks, 1), streams_submitted=sid, live_at_end=len(sched.live), queued_at_end=len(sched.queue))
     be.close()
     return out
 
