@@ -369,6 +369,27 @@ def run_serving_closed(pf, torch, pfsynth, seconds, n_streams=1770, hbm_gb=(6.0,
     return out
 
 
+ABLATION = [
+    ("optimised", {}),
+    ("naive likelihood (every disk pixel from the frame)", dict(naive_likelihood=True)),
+    ("naive resampling, 64 threads", dict(naive_resample=True, threads_c=64)),
+    ("naive resampling, 128 threads", dict(naive_resample=True, threads_c=128)),
+    ("naive resampling, 256 threads", dict(naive_resample=True, threads_c=256)),
+    ("naive resampling, 512 threads", dict(naive_resample=True, threads_c=512)),
+    ("naive resampling, 1024 threads", dict(naive_resample=True, threads_c=1024)),
+    ("naive likelihood + resampling, 128 threads",
+     dict(naive_likelihood=True, naive_resample=True, threads_c=128)),
+    ("pass A 128 threads (8 particles each)", dict(threads_a=128)),
+    ("pass A 256 threads (4 particles each)", dict(threads_a=256)),
+    ("pass A 512 threads (2 particles each)", dict(threads_a=512)),
+    ("pass C 64 threads", dict(threads_c=64)),
+    ("pass C 128 threads", dict(threads_c=128)),
+    ("pass C 256 threads", dict(threads_c=256)),
+    ("pass C 512 threads", dict(threads_c=512)),
+    ("pass C 1024 threads", dict(threads_c=1024)),
+]
+
+
 def run_ablation(pf, torch, frames_dev, centres, w, steps, warmup, dtypes=("f16", "f64")):
     """The straightforward step against the optimised one, and workgroup
     sizes, at the headline workload: ms per step and per-pass times."""
@@ -647,7 +668,7 @@ def main():
             from paper_2308_00763_amd.tune import autotune
             r = autotune(w.n_particles, w.width, w.height, frames_dev, dtype=head, radius=w.radius,
                          x0=vid.centres[0][0], y0=vid.centres[0][1], drift=w.drift, sigma=w.sigma)
-            r["default_threads"] = {"pass_a": 256, "pass_c": "512 up to 1024 tiles, else 256"}
+            r["default_threads"] = {"pass_a": 256, "pass_c": "512 up to 1024 tiles, else 256; FP64 256"}
             return r
         section("autotune", tune_headline)
     if not args.no_track:

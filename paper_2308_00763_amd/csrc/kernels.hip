@@ -38,6 +38,51 @@ namespace pf {
 
 typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 typedef float float2_t __attribute__((ext_vector_type(2)));
+typedef double double2_t __attribute__((ext_vector_type(2)));
+
+// Global-memory view of a pointer.  The batched kernels read their filters'
+// pointers from memory, where the compiler cannot tell global memory from
+// LDS; it then emits generic (flat) accesses, which also count against the
+// LDS wait counter, so every LDS wait in a kernel would wait for them too (a
+// prefetch would not stay in flight).  Every pointer the kernels take points
+// to device memory.
+template <typename T>
+using gbl_t = __attribute__((address_space(1))) T;
+template <typename T>
+__device__ __forceinline__ gbl_t<T>* gbl(T* p)
+{
+    return (gbl_t<T>*)p;
+}
+// A value the whole wave holds, made explicit (scalar registers).
+__device__ __forceinline__ uint64_t uniform(uint64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+template <typename T>
+__device__ __forceinline__ T* uniform(T* p)
+{
+    return reinterpret_cast<T*>(uniform(reinterpret_cast<uint64_t>(p)));
+}
+// Tile records through such pointers, member by member (a structure's
+// implicit copy does not bind to global-memory references).
+__device__ __forceinline__ TileRec64 load_rec(const gbl_t<const TileRec64>* p)
+{
+    return TileRec64{p->m, p->s, p->sx, p->sy};
+}
+__device__ __forceinline__ TileRec32 load_rec(const gbl_t<const TileRec32>* p)
+{
+    return TileRec32{p->smax, p->s, p->sx, p->sy};
+}
+template <typename Rec>
+__device__ __forceinline__ void store_rec(gbl_t<Rec>* p, const Rec& r)
+{
+    if constexpr (sizeof(Rec) == sizeof(TileRec64)) p->m = r.m; else p->smax = r.smax;
+    p->s = r.s;
+    p->sx = r.sx;
+    p->sy = r.sy;
+}
 
 // ---------------------------------------------------------------------------
 // Disk sums through a row-prefix table.  The disk dx^2 + dy^2 < r^2 is, row by
@@ -111,7 +156,7 @@ __device__ __forceinline__ int disk_sum_global(const uint8_t* frame, int64_t pit
     for (int dy = -(r - 1); dy <= r - 1; ++dy) {
         const int h = disk_half_width(r, dy);
         const int row = min(max(cy + dy, 0), H - 1);
-        const uint8_t* rp = frame + (int64_t)row * pitch;
+        const auto* rp = gbl(frame + (int64_t)row * pitch);
         for (int dx = -h; dx <= h; ++dx) s += rp[min(max(cx + dx, 0), W - 1)];
     }
     return s;
@@ -149,19 +194,19 @@ struct ModeT<PF_F64> {
     template <int PPT>
     static __device__ __forceinline__ void load(const void* p, int k0, Val* v)
     {
-        const double2* q = reinterpret_cast<const double2*>(static_cast<const double*>(p) + k0);
+        const auto* q = gbl(reinterpret_cast<const double2_t*>(static_cast<const double*>(p) + k0));
 #pragma unroll
         for (int i = 0; i < PPT / 2; ++i) {
-            const double2 a = q[i];
+            const double2_t a = q[i];
             v[2 * i] = a.x; v[2 * i + 1] = a.y;
         }
     }
     template <int PPT>
     static __device__ __forceinline__ void store(void* p, int k0, const Val* v)
     {
-        double2* q = reinterpret_cast<double2*>(static_cast<double*>(p) + k0);
+        auto* q = gbl(reinterpret_cast<double2_t*>(static_cast<double*>(p) + k0));
 #pragma unroll
-        for (int i = 0; i < PPT / 2; ++i) q[i] = make_double2(v[2 * i], v[2 * i + 1]);
+        for (int i = 0; i < PPT / 2; ++i) q[i] = double2_t{v[2 * i], v[2 * i + 1]};
     }
     // x <- x + (d + sigma z), each operation rounded (library built without
     // contraction), as Eq. (1)-(2) are written.
@@ -196,19 +241,19 @@ struct ModeT<PF_F32> {
     template <int PPT>
     static __device__ __forceinline__ void load(const void* p, int k0, Val* v)
     {
-        const float2* q = reinterpret_cast<const float2*>(static_cast<const float*>(p) + k0);
+        const auto* q = gbl(reinterpret_cast<const float2_t*>(static_cast<const float*>(p) + k0));
 #pragma unroll
         for (int i = 0; i < PPT / 2; ++i) {
-            const float2 a = q[i];
+            const float2_t a = q[i];
             v[2 * i] = a.x; v[2 * i + 1] = a.y;
         }
     }
     template <int PPT>
     static __device__ __forceinline__ void store(void* p, int k0, const Val* v)
     {
-        float2* q = reinterpret_cast<float2*>(static_cast<float*>(p) + k0);
+        auto* q = gbl(reinterpret_cast<float2_t*>(static_cast<float*>(p) + k0));
 #pragma unroll
-        for (int i = 0; i < PPT / 2; ++i) q[i] = make_float2(v[2 * i], v[2 * i + 1]);
+        for (int i = 0; i < PPT / 2; ++i) q[i] = float2_t{v[2 * i], v[2 * i + 1]};
     }
     template <int PPT>
     static __device__ __forceinline__ void propagate(Val* x, Val* y, const Prop& pr, const StepArgs& a,
@@ -241,7 +286,7 @@ struct ModeT<PF_F16> {
     template <int PPT>
     static __device__ __forceinline__ void load(const void* p, int k0, Val* v)
     {
-        const uint32_t* q = reinterpret_cast<const uint32_t*>(static_cast<const _Float16*>(p) + k0);
+        const auto* q = gbl(reinterpret_cast<const uint32_t*>(static_cast<const _Float16*>(p) + k0));
 #pragma unroll
         for (int i = 0; i < PPT / 2; ++i) {
             const half2_t h = __builtin_bit_cast(half2_t, q[i]);
@@ -251,7 +296,7 @@ struct ModeT<PF_F16> {
     template <int PPT>
     static __device__ __forceinline__ void store(void* p, int k0, const Val* v)
     {
-        uint32_t* q = reinterpret_cast<uint32_t*>(static_cast<_Float16*>(p) + k0);
+        auto* q = gbl(reinterpret_cast<uint32_t*>(static_cast<_Float16*>(p) + k0));
 #pragma unroll
         for (int i = 0; i < PPT / 2; ++i) {
             const half2_t h = {v[2 * i], v[2 * i + 1]};
@@ -300,7 +345,7 @@ struct ModeT<PF_BF16> {
     template <int PPT>
     static __device__ __forceinline__ void load(const void* p, int k0, Val* v)
     {
-        const uint32_t* q = reinterpret_cast<const uint32_t*>(static_cast<const uint16_t*>(p) + k0);
+        const auto* q = gbl(reinterpret_cast<const uint32_t*>(static_cast<const uint16_t*>(p) + k0));
 #pragma unroll
         for (int i = 0; i < PPT / 2; ++i) {
             const uint32_t a = q[i];
@@ -316,7 +361,7 @@ struct ModeT<PF_BF16> {
     template <int PPT>
     static __device__ __forceinline__ void store(void* p, int k0, const Val* v)
     {
-        uint32_t* q = reinterpret_cast<uint32_t*>(static_cast<uint16_t*>(p) + k0);
+        auto* q = gbl(reinterpret_cast<uint32_t*>(static_cast<uint16_t*>(p) + k0));
 #pragma unroll
         for (int i = 0; i < PPT / 2; ++i) q[i] = pack(v[2 * i], v[2 * i + 1]);
     }
@@ -389,7 +434,7 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
     // Origins (reduced modes): stored offsets are relative to ci, the
     // propagated ones to cn; the drift is applied minus the origin change.
     // The step's index is one past the block's count (the combine advances it).
-    const DevBlock* blk = a.blk;
+    const auto* blk = gbl(a.blk);
     const uint32_t tn = blk->t + 1u;
     int cnx = 0, cny = 0;
     float ddx = 0.f, ddy = 0.f;
@@ -471,11 +516,11 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
             v[it] = 0;
             if (it < rounds && yy < wh && c0 < tw) {
                 const int row = min(max(wy0 + yy, 0), a.H - 1);
-                const uint8_t* rp = a.frame + (int64_t)row * a.pitch;
+                const auto* rp = gbl(a.frame + (int64_t)row * a.pitch);
                 const int x = xs + c0;
                 uint32_t pk = 0;
                 if (aligned && x >= 0 && x + 3 < a.W) {
-                    pk = *reinterpret_cast<const uint32_t*>(rp + x);
+                    pk = *reinterpret_cast<const gbl_t<uint32_t>*>(rp + x);
                 } else {
 #pragma unroll
                     for (int bb = 0; bb < 4; ++bb)
@@ -595,13 +640,13 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
         q[i] = v < incl ? v : incl;
     }
     if constexpr (DT == PF_F64) {
-        double2* qp = reinterpret_cast<double2*>(static_cast<double*>(a.q) + k0);
+        auto* qp = gbl(reinterpret_cast<double2_t*>(static_cast<double*>(a.q) + k0));
 #pragma unroll
-        for (int i = 0; i < PPT / 2; ++i) qp[i] = make_double2(q[2 * i], q[2 * i + 1]);
+        for (int i = 0; i < PPT / 2; ++i) qp[i] = double2_t{q[2 * i], q[2 * i + 1]};
     } else {
-        float2* qp = reinterpret_cast<float2*>(static_cast<float*>(a.q) + k0);
+        auto* qp = gbl(reinterpret_cast<float2_t*>(static_cast<float*>(a.q) + k0));
 #pragma unroll
-        for (int i = 0; i < PPT / 2; ++i) qp[i] = make_float2(q[2 * i], q[2 * i + 1]);
+        for (int i = 0; i < PPT / 2; ++i) qp[i] = float2_t{q[2 * i], q[2 * i + 1]};
     }
     if (a.dg_s) {
 #pragma unroll
@@ -622,9 +667,9 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
             ty = ty + red[2][w];
         }
         if constexpr (DT == PF_F64) {
-            static_cast<TileRec64*>(a.rec)[tile] = TileRec64{tile_m, incl, tx, ty};
+            store_rec(gbl(static_cast<TileRec64*>(a.rec)) + tile, TileRec64{tile_m, incl, tx, ty});
         } else {
-            static_cast<TileRec32*>(a.rec)[tile] = TileRec32{tile_smax, incl, tx, ty};
+            store_rec(gbl(static_cast<TileRec32*>(a.rec)) + tile, TileRec32{tile_smax, incl, tx, ty});
         }
     }
 }
@@ -667,16 +712,53 @@ template <>
 struct TileSlots<PF_F64> {
     double base, scale, ymax;
     int E, Eprev;
+    // The words the tile's map is built from, one per lane: 0-4 off, f and
+    // E of table entry t; 5-6 off of entry t + 1; 7 E of entry t - 1 (0 for
+    // the first tile); 8-9 R and 10-11 u0 of the filter's block.  One vector
+    // load fetches them and the constructor reads them out, so a streaming
+    // kernel loads them one tile ahead and needs no wait for them until it
+    // builds the map, after the tile before.
+    struct Raw {
+        uint32_t w;
+        __device__ void load(const StepArgs& a, int t)
+        {
+            constexpr int kW = (int)(sizeof(TileTab64) / 4);
+            const auto* tw = gbl(static_cast<const uint32_t*>(a.tab));
+            const auto* bw = gbl(reinterpret_cast<const uint32_t*>(a.blk));
+            const int lane = threadIdx.x & 63;
+            const gbl_t<const uint32_t>* p = lane < 5 ? tw + ((int64_t)kW * t + lane)
+                              : lane < 7 ? tw + ((int64_t)kW * (t + 1) + (lane - 5))
+                              : lane == 7 ? tw + ((int64_t)kW * (t - 1) + 4)
+                              : lane < 10 ? bw + (offsetof(DevBlock, R) / 4 + (lane - 8))
+                                          : bw + (offsetof(DevBlock, u0) / 4 + (lane - 10));
+            w = 0;
+            if (lane < 12 && (lane != 7 || t > 0)) w = *p;
+        }
+        __device__ int word(int l) const { return __builtin_amdgcn_readlane((int)w, l); }
+        __device__ double dword(int l) const { return __hiloint2double(word(l + 1), word(l)); }
+    };
+    static_assert(offsetof(TileTab64, off) == 0 && offsetof(TileTab64, f) == 8 && offsetof(TileTab64, E) == 16,
+                  "table word layout");
+    static_assert(offsetof(DevBlock, R) % 8 == 0 && offsetof(DevBlock, u0) % 8 == 0, "block word layout");
     TileSlots() = default;
+    // straight from the table (uniform loads)
     __device__ TileSlots(const StepArgs& a, int t)
     {
-        const TileTab64* tab = static_cast<const TileTab64*>(a.tab);
-        const double R = a.blk->R, u0 = a.blk->u0;
-        base = R * tab[t].off - u0;
-        scale = R * tab[t].f;
-        ymax = R * tab[t + 1].off - u0;
-        E = tab[t].E;
-        Eprev = t > 0 ? tab[t - 1].E : 0;
+        const auto* tab = gbl(static_cast<const TileTab64*>(a.tab));
+        const auto* blk = gbl(a.blk);
+        init(blk->R, blk->u0, tab[t].off, tab[t].f, tab[t + 1].off, tab[t].E, t > 0 ? tab[t - 1].E : 0);
+    }
+    __device__ explicit TileSlots(const Raw& r)
+    {
+        init(r.dword(8), r.dword(10), r.dword(0), r.dword(2), r.dword(5), r.word(4), r.word(7));
+    }
+    __device__ void init(double R, double u0, double off, double f, double off1, int e, int eprev)
+    {
+        base = R * off - u0;
+        scale = R * f;
+        ymax = R * off1 - u0;
+        E = e;
+        Eprev = eprev;
     }
     __device__ int operator()(const void* q, int i, int n) const { return of(static_cast<const double*>(q)[i], n); }
     __device__ int of(double qv, int n) const
@@ -697,18 +779,54 @@ template <>
 struct TileSlots<PF_F32> {
     float frac, scale;
     int B, cap, E, Eprev;
+    // The map's words, one per lane as in the double mode: 0-3 table entry
+    // t; 4 E of entry t - 1 (0 for the first tile); 5-6 R and 7-8 u0 (hi,
+    // lo) of the filter's block.
+    struct Raw {
+        uint32_t w;
+        __device__ void load(const StepArgs& a, int t)
+        {
+            const auto* tw = gbl(static_cast<const uint32_t*>(a.tab));
+            const auto* bw = gbl(reinterpret_cast<const uint32_t*>(a.blk));
+            const int lane = threadIdx.x & 63;
+            const gbl_t<const uint32_t>* p = lane < 4 ? tw + (4 * (int64_t)t + lane)
+                              : lane == 4 ? tw + (4 * (int64_t)(t - 1) + 3)
+                              : lane < 7 ? bw + (offsetof(DevBlock, R_hi) / 4 + (lane - 5))
+                                         : bw + (offsetof(DevBlock, u0_hi) / 4 + (lane - 7));
+            w = 0;
+            if (lane < 9 && (lane != 4 || t > 0)) w = *p;
+        }
+        __device__ int word(int l) const { return __builtin_amdgcn_readlane((int)w, l); }
+        __device__ float fword(int l) const { return __int_as_float(word(l)); }
+    };
+    static_assert(sizeof(TileTab32) == 16 && offsetof(TileTab32, off_lo) == 4 && offsetof(TileTab32, f) == 8 &&
+                  offsetof(TileTab32, E) == 12, "table word layout");
+    static_assert(offsetof(DevBlock, R_lo) == offsetof(DevBlock, R_hi) + 4 &&
+                  offsetof(DevBlock, u0_lo) == offsetof(DevBlock, u0_hi) + 4, "block word layout");
     TileSlots() = default;
+    // straight from the table (uniform loads)
     __device__ TileSlots(const StepArgs& a, int t)
     {
-        const TileTab32* tab = static_cast<const TileTab32*>(a.tab);
-        const ff R{a.blk->R_hi, a.blk->R_lo}, mu0{-a.blk->u0_hi, -a.blk->u0_lo};
-        const ff base = ff_add(ff_mul(R, ff{tab[t].off_hi, tab[t].off_lo}), mu0);
+        const auto* tab = gbl(static_cast<const TileTab32*>(a.tab));
+        const auto* blk = gbl(a.blk);
+        init(ff{blk->R_hi, blk->R_lo}, ff{blk->u0_hi, blk->u0_lo}, ff{tab[t].off_hi, tab[t].off_lo},
+             tab[t].f, tab[t].E, t > 0 ? tab[t - 1].E : 0);
+    }
+    __device__ explicit TileSlots(const Raw& r)
+    {
+        init(ff{r.fword(5), r.fword(6)}, ff{r.fword(7), r.fword(8)}, ff{r.fword(0), r.fword(1)}, r.fword(2),
+             r.word(3), r.word(4));
+    }
+    __device__ void init(ff R, ff u0, ff off, float f, int e, int eprev)
+    {
+        const ff mu0{-u0.hi, -u0.lo};
+        const ff base = ff_add(ff_mul(R, off), mu0);
         const float bh = floorf(base.hi);
         B = (int)bh;
         frac = (base.hi - bh) + base.lo;
-        scale = ff_mul_f(R, tab[t].f).hi;
-        E = tab[t].E;
-        Eprev = t > 0 ? tab[t - 1].E : 0;
+        scale = ff_mul_f(R, f).hi;
+        E = e;
+        Eprev = eprev;
         cap = E - B;
     }
     __device__ int operator()(const void* q, int i, int n) const { return of(static_cast<const float*>(q)[i], n); }
@@ -844,7 +962,7 @@ __device__ __forceinline__ void write_block(const StepArgs& a,
                                            typename std::conditional<DT == PF_F64, double, float>::type sy,
                                            const SlotMap<DT == PF_F64>& sm, uint32_t t)
 {
-    DevBlock* b = a.blk;
+    auto* b = gbl(a.blk);
     b->t = t;
     if constexpr (DT == PF_F64) {
         b->M = gm;
@@ -902,9 +1020,9 @@ __device__ __forceinline__ void combine_filter(const StepArgs& a)
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int nt = a.ntiles;
     const int n = (int)a.n;
-    const Rec* rec = static_cast<const Rec*>(a.rec);
-    Tab* tab = static_cast<Tab*>(a.tab);
-    const uint32_t tn = a.blk->t + 1u;  // this step (thread 0 advances the count at the end)
+    const auto* rec = gbl(static_cast<const Rec*>(a.rec));
+    auto* tab = gbl(static_cast<Tab*>(a.tab));
+    const uint32_t tn = gbl(a.blk)->t + 1u;  // this step (thread 0 advances the count at the end)
     // the resampling offset's random words do not depend on the weights: drawn
     // first, they overlap the loads of the records
     const u32x4 wu0 = u0_words(a, tn);
@@ -922,7 +1040,7 @@ __device__ __forceinline__ void combine_filter(const StepArgs& a)
             if (t < nt) {
                 Mx mt;
                 if (one_round) {
-                    r_keep[KEEP ? k : 0] = rec[t];
+                    r_keep[KEEP ? k : 0] = load_rec(rec + t);
                     if constexpr (F64) mt = r_keep[KEEP ? k : 0].m; else mt = r_keep[KEEP ? k : 0].smax;
                 } else {
                     if constexpr (F64) mt = rec[t].m; else mt = rec[t].smax;
@@ -953,7 +1071,7 @@ __device__ __forceinline__ void combine_filter(const StepArgs& a)
             f[k] = 0;
             v[k] = A::zero();
             if (t < nt) {
-                const Rec rr = one_round ? r_keep[KEEP ? k : 0] : rec[t];
+                const Rec rr = one_round ? r_keep[KEEP ? k : 0] : load_rec(rec + t);
                 if constexpr (F64) {
                     f[k] = exp(rr.m - gm);
                     v[k] = f[k] * rr.s;
@@ -1339,21 +1457,28 @@ __global__ __launch_bounds__(kGroupTiles) void combine_finish_kernel(StepArgs a)
 // the last mark at or before j, which an inclusive maximum scan over the
 // slots fills in (each thread a run of consecutive slots, then a wave scan
 // and the wave totals).  The workgroup then writes the ancestors' propagated
-// positions to the slots with consecutive lanes on consecutive slots.  A tile
-// that owns more than kSlotRound slots takes several rounds, each carrying
-// the last mark of the one before; the work depends only on the tile's
-// particle and slot counts, never on how the slots are spread.
+// positions to the slots, each thread four consecutive slots that start at a
+// global slot divisible by four (one vector store per coordinate; the first
+// and last group of a round may be partial): the round's slot i lives at
+// entry i + lead of the LDS slot array, lead = its first global slot mod 4.
+// A tile that owns more than kSlotRound slots takes several rounds, each
+// carrying the last mark of the one before; the work depends only on the
+// tile's particle and slot counts, never on how the slots are spread.
 
 constexpr int kSlotRound = 4096;  // slots per round
+
+typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
 
 template <int DT>
 struct PassCLds {
     using Store = typename ModeT<DT>::Store;
+    struct alignas(2 * sizeof(Store)) XY {
+        Store x, y;
+    };
     int32_t e[kTile];
-    Store x[kTile];
-    Store y[kTile];
-    uint16_t anc[kSlotRound];  // marks, then tile-local ancestors, of the round's slots
-    int32_t red[16];           // wave totals of the scan (up to 1024 threads)
+    XY xy[kTile];                     // propagated positions of the tile
+    alignas(8) uint16_t anc[kSlotRound + 4];  // marks, then tile-local ancestors, of the round's slots
+    int32_t red[16];                  // wave totals of the scan (up to 1024 threads)
 };
 
 // One tile's pass-C inputs in registers: its particles' cumulative weights
@@ -1370,9 +1495,9 @@ struct PassCIn {
     __device__ void load(const StepArgs& a, int t)
     {
         const int first = t * kTile, tt = min(kTile, (int)a.n - first);
-        const Q* qp = static_cast<const Q*>(a.q) + first;
-        const Store* xp = static_cast<const Store*>(a.px) + first;
-        const Store* yp = static_cast<const Store*>(a.py) + first;
+        const auto* qp = gbl(static_cast<const Q*>(a.q) + first);
+        const auto* xp = gbl(static_cast<const Store*>(a.px) + first);
+        const auto* yp = gbl(static_cast<const Store*>(a.py) + first);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int k = threadIdx.x + r * BC;
@@ -1381,6 +1506,17 @@ struct PassCIn {
                 x[r] = xp[k];
                 y[r] = yp[k];
             }
+        }
+    }
+    // Waits for the loads here (an empty use of every register), so that no
+    // wait for them is left to code that later loads the next tile.
+    __device__ void settle()
+    {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            __asm__ volatile("" ::"v"(q[r]));
+            __asm__ volatile("" ::"v"(x[r]));
+            __asm__ volatile("" ::"v"(y[r]));
         }
     }
 };
@@ -1394,9 +1530,9 @@ __device__ __forceinline__ void pass_c_run(const StepArgs& a, int t, PassCLds<DT
                                            const TileSlotsT<DT>& ts)
 {
     using Store = typename ModeT<DT>::Store;
+    using XY = typename PassCLds<DT>::XY;
+    typedef Store Store4 __attribute__((ext_vector_type(4)));
     int32_t* s_e = lds.e;
-    Store* s_x = lds.x;
-    Store* s_y = lds.y;
 
     const int n = (int)a.n;
     const int first = t * kTile;
@@ -1411,57 +1547,88 @@ __device__ __forceinline__ void pass_c_run(const StepArgs& a, int t, PassCLds<DT
             // it) owns no slot
             const int e = k == tt - 1 ? ts.E : ts.of(in.q[r], n);
             s_e[k] = max(e - ts.Eprev, 0);
-            s_x[k] = in.x[r];
-            s_y[k] = in.y[r];
+            lds.xy[k] = XY{in.x[r], in.y[r]};
         }
     }
     __syncthreads();
     const int slots = ts.E - ts.Eprev;
     if (slots > 0) {  // uniform over the workgroup
         const int lane = tid & 63, wv = tid >> 6;
-        Store* sx = static_cast<Store*>(a.sx) + ts.Eprev;
-        Store* sy = static_cast<Store*>(a.sy) + ts.Eprev;
-        int32_t* anc_out = a.dg_anc ? a.dg_anc + ts.Eprev : nullptr;
+        auto* gx = gbl(static_cast<Store*>(a.sx));
+        auto* gy = gbl(static_cast<Store*>(a.sy));
+        auto* anc_out = a.dg_anc ? gbl(a.dg_anc) : nullptr;
         int carry = 0;  // the last mark of the previous round (none before the first)
         for (int j0 = 0; j0 < slots; j0 += kSlotRound) {
             const int nj = min(kSlotRound, slots - j0);
-            for (int i = tid; i < nj; i += BC) lds.anc[i] = 0;
+            const int g0 = ts.Eprev + j0;   // global slot of the round's slot 0
+            const int lead = g0 & 3;        // its entry in the slot array
+            const int span = nj + lead;     // entries in use
+            for (int i = 4 * tid; i < span; i += 4 * BC)
+                *reinterpret_cast<u16x4*>(&lds.anc[i]) = u16x4{0, 0, 0, 0};
             __syncthreads();
 #pragma unroll
             for (int r = 0; r < kTile / BC; ++r) {
                 const int k = tid + r * BC;
                 if (k < tt) {
                     const int b = k == 0 ? 0 : s_e[k - 1];
-                    if (s_e[k] > b && b >= j0 && b < j0 + nj) lds.anc[b - j0] = (uint16_t)(k + 1);
+                    if (s_e[k] > b && b >= j0 && b < j0 + nj) lds.anc[b - j0 + lead] = (uint16_t)(k + 1);
                 }
             }
             __syncthreads();
-            // inclusive maximum scan of the marks; thread tid owns the slots
-            // [tid spt, tid spt + spt) of the round
-            const int spt = (nj + BC - 1) / BC;
+            // inclusive maximum scan of the marks; thread tid owns the
+            // entries [s0, s0 + spt), spt a multiple of four (entries past
+            // the span up to the next multiple of four are cleared)
+            const int spt = 4 * ((span + 4 * BC - 1) / (4 * BC));
             const int s0 = tid * spt;
             int run = 0;
-            for (int i = 0; i < spt; ++i)
-                if (s0 + i < nj) run = max(run, (int)lds.anc[s0 + i]);
+            for (int c = s0; c < s0 + spt && c < span; c += 4) {
+                const u16x4 v = *reinterpret_cast<const u16x4*>(&lds.anc[c]);
+                run = max(run, max(max((int)v.x, (int)v.y), max((int)v.z, (int)v.w)));
+            }
             const int sc = wave_incl_scan<OpMax>(run);
             if (lane == 63) lds.red[wv] = sc;
             __syncthreads();
             int m = max(carry, wave_shift_up1(sc, 0));
             for (int w = 0; w < wv; ++w) m = max(m, lds.red[w]);
-            for (int i = 0; i < spt; ++i) {
-                if (s0 + i < nj) {
-                    m = max(m, (int)lds.anc[s0 + i]);
-                    lds.anc[s0 + i] = (uint16_t)(m - 1);
-                }
+            for (int c = s0; c < s0 + spt && c < span; c += 4) {
+                u16x4 v = *reinterpret_cast<const u16x4*>(&lds.anc[c]);
+                m = max(m, (int)v.x); v.x = (uint16_t)(m - 1);
+                m = max(m, (int)v.y); v.y = (uint16_t)(m - 1);
+                m = max(m, (int)v.z); v.z = (uint16_t)(m - 1);
+                m = max(m, (int)v.w); v.w = (uint16_t)(m - 1);
+                *reinterpret_cast<u16x4*>(&lds.anc[c]) = v;
             }
             __syncthreads();
-            for (int i = tid; i < nj; i += BC) {
-                const int kk = lds.anc[i];
-                sx[j0 + i] = s_x[kk];
-                sy[j0 + i] = s_y[kk];
-                if (anc_out) anc_out[j0 + i] = first + kk;
+            // scatter: group q holds the round's slots 4 q - lead .. + 3, at
+            // global slots g0 - lead + 4 q .. + 3
+            for (int q = tid; 4 * q < span; q += BC) {
+                const int i0 = 4 * q - lead;
+                const int gs = g0 - lead + 4 * q;
+                const u16x4 v = *reinterpret_cast<const u16x4*>(&lds.anc[4 * q]);
+                if (i0 >= 0 && i0 + 4 <= nj) {  // the whole group lies in the round
+                    const XY p0 = lds.xy[v.x], p1 = lds.xy[v.y], p2 = lds.xy[v.z], p3 = lds.xy[v.w];
+                    *reinterpret_cast<gbl_t<Store4>*>(gx + gs) = Store4{p0.x, p1.x, p2.x, p3.x};
+                    *reinterpret_cast<gbl_t<Store4>*>(gy + gs) = Store4{p0.y, p1.y, p2.y, p3.y};
+                    if (anc_out) {
+                        typedef int32_t I4 __attribute__((ext_vector_type(4)));
+                        *reinterpret_cast<gbl_t<I4>*>(anc_out + gs) =
+                            I4{first + v.x, first + v.y, first + v.z, first + v.w};
+                    }
+                } else {  // the round's first or last group: slot by slot
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int i = i0 + u;
+                        if (i >= 0 && i < nj) {
+                            const int k = v[u];
+                            const XY pk = lds.xy[k];
+                            gx[gs + u] = pk.x;
+                            gy[gs + u] = pk.y;
+                            if (anc_out) anc_out[gs + u] = first + k;
+                        }
+                    }
+                }
             }
-            carry = (int)lds.anc[nj - 1] + 1;
+            carry = (int)lds.anc[nj - 1 + lead] + 1;
             __syncthreads();
         }
     }
@@ -1477,21 +1644,26 @@ __global__ __launch_bounds__(BC, BC >= 256 ? 8 : 1) void pass_c_kernel(StepArgs 
     const int nt = a.ntiles, G = gridDim.x;
     int t = blockIdx.x;
     PassCIn<DT, BC> cur;
+    typename TileSlotsT<DT>::Raw r0;
+    r0.load(a, t);
     cur.load(a, t);
-    TileSlotsT<DT> ts(a, t);
+    cur.settle();  // one wait for the first tile's words and inputs
+    TileSlotsT<DT> ts(r0);
     for (;;) {
         const int tn = t + G;
+        // the next tile's table words and inputs are loaded now and used
+        // after this tile's scatter
+        typename TileSlotsT<DT>::Raw rn;
         PassCIn<DT, BC> nxt;
-        TileSlotsT<DT> tsn;
         if (tn < nt) {  // uniform
+            rn.load(a, tn);
             nxt.load(a, tn);
-            tsn = TileSlotsT<DT>(a, tn);
         }
         pass_c_run<DT, BC>(a, t, lds, cur, ts);
         if (tn >= nt) break;
         t = tn;
         cur = nxt;
-        ts = tsn;
+        ts = TileSlotsT<DT>(rn);
     }
 }
 
@@ -1725,7 +1897,7 @@ __global__ __launch_bounds__(NT) void combine_batch_kernel(BatchArgs b)
 // whatever filters they belong to, loading each tile's arguments and inputs
 // while it scatters the one before.
 template <int DT>
-__global__ __launch_bounds__(pass_c_threads(DT, 1 << 30), 8) void pass_c_batch_kernel(BatchArgs b)
+__global__ __launch_bounds__(pass_c_threads(DT, 1 << 30), 6) void pass_c_batch_kernel(BatchArgs b)
 {
     constexpr int BC = pass_c_threads(DT, 1 << 30);
     __shared__ PassCLds<DT> lds;
@@ -1737,6 +1909,19 @@ __global__ __launch_bounds__(pass_c_threads(DT, 1 << 30), 8) void pass_c_batch_k
         const int e = b.tile_entry[gt];
         a = batch_args(b, e);
         lt = gt - b.entries[e].tile_base;
+        // the filter's values pass C uses, held in scalar registers (they
+        // are the workgroup's; loaded from memory, they would otherwise take
+        // vector registers while the next tile's inputs are prefetched)
+        a.q = uniform(a.q);
+        a.px = uniform(a.px);
+        a.py = uniform(a.py);
+        a.sx = uniform(a.sx);
+        a.sy = uniform(a.sy);
+        a.tab = uniform(a.tab);
+        a.blk = uniform(a.blk);
+        a.dg_anc = uniform(a.dg_anc);
+        a.n = (int64_t)uniform((uint64_t)a.n);
+        a.ntiles = __builtin_amdgcn_readfirstlane(a.ntiles);
     };
     int gt = blockIdx.x;
     StepArgs a;
@@ -1745,20 +1930,23 @@ __global__ __launch_bounds__(pass_c_threads(DT, 1 << 30), 8) void pass_c_batch_k
     PassCIn<DT, BC> cur;
     TileSlotsT<DT> ts;
     if (lt < a.ntiles) {
+        typename TileSlotsT<DT>::Raw r0;
+        r0.load(a, lt);
         cur.load(a, lt);
-        ts = TileSlotsT<DT>(a, lt);
+        cur.settle();
+        ts = TileSlotsT<DT>(r0);
     }
     for (;;) {
         const int gn = gt + G;
         StepArgs an;
         int ln = 0;
+        typename TileSlotsT<DT>::Raw rn;
         PassCIn<DT, BC> nxt;
-        TileSlotsT<DT> tsn;
         if (gn < b.tiles) {  // uniform
             resolve(gn, an, ln);
             if (ln < an.ntiles) {
+                rn.load(an, ln);
                 nxt.load(an, ln);
-                tsn = TileSlotsT<DT>(an, ln);
             }
         }
         if (lt < a.ntiles) pass_c_run<DT, BC>(a, lt, lds, cur, ts);
@@ -1767,7 +1955,7 @@ __global__ __launch_bounds__(pass_c_threads(DT, 1 << 30), 8) void pass_c_batch_k
         a = an;
         lt = ln;
         cur = nxt;
-        ts = tsn;
+        if (lt < a.ntiles) ts = TileSlotsT<DT>(rn);
     }
 }
 

@@ -31,3 +31,15 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=300)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_ablation_variants_are_valid_step_parameters():
+    # every row of the naive-vs-optimised table must name a variant the
+    # binding accepts (the table is only exercised on a GPU otherwise)
+    import paper_2308_00763_amd as pf
+    assert bench.ABLATION and bench.ABLATION[0] == ("optimised", {})
+    names = [name for name, _ in bench.ABLATION]
+    assert len(set(names)) == len(names)
+    for _, var in bench.ABLATION:
+        p = pf.make_params(1 << 20, 1024, 1024, "f16", **var)
+        assert p.n_particles == 1 << 20
