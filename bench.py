@@ -668,7 +668,7 @@ def main():
             from paper_2308_00763_amd.tune import autotune
             r = autotune(w.n_particles, w.width, w.height, frames_dev, dtype=head, radius=w.radius,
                          x0=vid.centres[0][0], y0=vid.centres[0][1], drift=w.drift, sigma=w.sigma)
-            r["default_threads"] = {"pass_a": 256, "pass_c": "512 up to 1024 tiles, else 256; FP64 256"}
+            r["default_threads"] = {"pass_a": 256, "pass_c": 256}
             return r
         section("autotune", tune_headline)
     if not args.no_track:

@@ -88,9 +88,7 @@ typedef enum pf_lik_norm { PF_LIK_MEAN = 0, PF_LIK_SUM = 1 } pf_lik_norm;
  *     bits 8-11 (PF_THREADS_A_SHIFT)  pass A, 1024 particles per workgroup:
  *                                     128, 256 (default) or 512 threads;
  *     bits 12-15 (PF_THREADS_C_SHIFT) pass C or the naive resampler: 64-1024
- *                                     (default: pass C 512 up to 1024 tiles,
- *                                     else 256, and 256 in FP64; the naive
- *                                     resampler 256). */
+ *                                     (default 256 for both). */
 #define PF_FLAG_NAIVE_LIKELIHOOD 2u
 #define PF_FLAG_NAIVE_RESAMPLE 4u
 #define PF_THREADS_A_SHIFT 8

@@ -324,9 +324,14 @@ struct ModeT<PF_F16> {
             y[i] = yy.x; y[i + 1] = yy.y;
         }
     }
+    // A half's value in float, plus one half, is exact (at most 18
+    // significant bits), so floor(v + 1/2) is the half-up rounding that
+    // offset_cell forms in general.
     static __device__ __forceinline__ int cell(Val v, int origin, int lo, int hi)
     {
-        return offset_cell((float)v, origin, lo, hi);
+        const float f = __builtin_amdgcn_fmed3f((float)v, (float)(lo - origin) - 1.0f, (float)(hi - origin) + 1.0f);
+        const int c = origin + (int)floorf(f + 0.5f);
+        return min(max(c, lo), hi);
     }
 };
 

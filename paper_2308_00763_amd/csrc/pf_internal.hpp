@@ -10,15 +10,13 @@
 namespace pf {
 
 constexpr int kBlock = 256;        // threads per workgroup of the small kernels
-// Default threads per pass-C workgroup: in the single-precision modes 512
-// while a filter has at most 1024 tiles (one tile per workgroup;
-// latency-bound), else 256 (each resident workgroup streams several tiles);
-// FP64 always 256 (its 512-thread kernel would not fit the registers that
-// four resident workgroups per compute unit leave it).  Batches, whose grids
-// are large, use the value for many tiles.
-__host__ __device__ constexpr int pass_c_threads(int dtype, int ntiles)
+// Default threads per pass-C workgroup, whatever the filter's size (a
+// workgroup scatters four slots per thread; with 1024-particle tiles more
+// threads would idle).  The dtype and tile count stay in the signature for
+// the launchers.
+__host__ __device__ constexpr int pass_c_threads(int /*dtype*/, int /*ntiles*/)
 {
-    return dtype != PF_F64 && ntiles <= 1024 ? 512 : 256;
+    return 256;
 }
 constexpr int kWaves = kBlock / 64;
 constexpr int kTile = 1024;        // particles per tile (one pass-A and one pass-C workgroup)

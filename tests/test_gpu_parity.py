@@ -144,6 +144,46 @@ def test_reduced_modes_one_tile_takes_every_slot(dtype):
     assert out[0][0]["anc"].max() < 1024
 
 
+def _second_tile_init(n, vid, k_first):
+    # tile 1 sits on the object (small integer offsets), and so do the first
+    # k_first particles of tile 0; every other particle is on background:
+    # tile 0 owns a few slots, so tile 1's first global slot is seldom a
+    # multiple of four, and tile 1 owns nearly all the others (several rounds)
+    cx, cy = vid.centres[1]
+    x = np.full(n, 20.0)
+    y = np.full(n, 20.0)
+    k = np.arange(1024)
+    x[1024:2048] = cx + (k % 5) - 2
+    y[1024:2048] = cy + (k // 5) % 3 - 1
+    x[:k_first] = cx
+    y[:k_first] = cy
+    return x, y
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f16"])
+def test_multi_round_tile_whose_first_slot_is_not_aligned(dtype):
+    # pass C writes four slots per thread at global slots divisible by four;
+    # a round that starts elsewhere has partial first and last groups
+    w = pfsynth.WORKLOADS["disk128_n1000"]
+    vid = pfsynth.workload_video(w)
+    n = 8192 + 300
+    leads = set()
+    for k_first in (1, 2, 3, 5):
+        out = _run_teacher_forced(dtype, n, vid, 5, 1, init=_second_tile_init(n, vid, k_first),
+                                  sigma=(0.0, 0.0), drift=(0.0, 0.0))
+        for got, gs, est, ref in out:
+            if dtype == "f64":
+                compare_f64_step(got, gs, est, ref, n)
+            else:
+                check_resample_consistency(got, gs, n)
+                assert tv(got["w"], ref["w"]) <= 1e-2
+            anc = got["anc"]
+            first = int(np.sum(anc < 1024))  # tile 0's slots
+            assert int(np.sum((anc >= 1024) & (anc < 2048))) > 4096
+            leads.add(first % 4)
+    assert leads - {0}, leads
+
+
 def _padded_frames(frames, extra, offset):
     """The frames on the device at row pitch W + extra, starting `offset`
     bytes into a buffer: (T, H, W) views with that stride."""
