@@ -53,18 +53,6 @@ __device__ __forceinline__ gbl_t<T>* gbl(T* p)
 {
     return (gbl_t<T>*)p;
 }
-// A value the whole wave holds, made explicit (scalar registers).
-__device__ __forceinline__ uint64_t uniform(uint64_t v)
-{
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
-template <typename T>
-__device__ __forceinline__ T* uniform(T* p)
-{
-    return reinterpret_cast<T*>(uniform(reinterpret_cast<uint64_t>(p)));
-}
 // Tile records through such pointers, member by member (a structure's
 // implicit copy does not bind to global-memory references).
 __device__ __forceinline__ TileRec64 load_rec(const gbl_t<const TileRec64>* p)
@@ -1869,13 +1857,34 @@ __global__ __launch_bounds__(kBlock) void fill_kernel(Store* x, Store* y, int64_
 // code of the single-filter kernels on its filter's arguments, so a filter's
 // results do not depend on the batch it runs in.
 
+// The batch's plan (filter arguments, entries, tile map) does not change while
+// a kernel runs, so the kernels read it through the constant address space:
+// its uniform reads become scalar loads, which wait on their own counter (a
+// tile's arguments can arrive while vector loads of its inputs are in flight)
+// and come through the scalar cache.
+template <typename T>
+using cst_t = __attribute__((address_space(4))) T;
+template <typename T>
+__device__ __forceinline__ const cst_t<T>* cst(const T* p)
+{
+    return (const cst_t<T>*)p;
+}
+
+__device__ __forceinline__ int tile_entry_of(const BatchArgs& b, int gt) { return cst(b.tile_entry)[gt]; }
+__device__ __forceinline__ int tile_base_of(const BatchArgs& b, int e) { return cst(b.entries)[e].tile_base; }
+
 __device__ __forceinline__ StepArgs batch_args(const BatchArgs& b, int e)
 {
-    const BatchEntry en = b.entries[e];
-    StepArgs a = b.args[en.fid];
-    a.frame = en.frame;
-    a.pitch = en.pitch;
-    a.t = en.t;
+    static_assert(sizeof(StepArgs) % 4 == 0, "StepArgs copies as 32-bit words");
+    const cst_t<BatchEntry>* en = cst(b.entries) + e;
+    StepArgs a;
+    const cst_t<uint32_t>* src = reinterpret_cast<const cst_t<uint32_t>*>(cst(b.args) + en->fid);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&a);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(StepArgs) / 4); ++i) dst[i] = src[i];
+    a.frame = en->frame;
+    a.pitch = en->pitch;
+    a.t = en->t;
     return a;
 }
 
@@ -1883,9 +1892,9 @@ template <int DT, int RC>
 __global__ __launch_bounds__(kBlockA) void pass_a_batch_kernel(BatchArgs b)
 {
     __shared__ PassALds lds;
-    const int e = b.tile_entry[blockIdx.x];
+    const int e = tile_entry_of(b, blockIdx.x);
     const StepArgs a = batch_args(b, e);
-    const int lt = (int)blockIdx.x - b.entries[e].tile_base;
+    const int lt = (int)blockIdx.x - tile_base_of(b, e);
     if (lt >= a.ntiles) return;  // a plan captured before the filter was re-initialised smaller
     pass_a_tile<DT, RC, kPPT>(a, lt, lds);
 }
@@ -1911,22 +1920,9 @@ __global__ __launch_bounds__(pass_c_threads(DT, 1 << 30), 6) void pass_c_batch_k
     // (past the filter's tiles: a plan captured before a smaller
     // re-initialisation; such a tile is skipped)
     auto resolve = [&](int gt, StepArgs& a, int& lt) {
-        const int e = b.tile_entry[gt];
+        const int e = tile_entry_of(b, gt);
         a = batch_args(b, e);
-        lt = gt - b.entries[e].tile_base;
-        // the filter's values pass C uses, held in scalar registers (they
-        // are the workgroup's; loaded from memory, they would otherwise take
-        // vector registers while the next tile's inputs are prefetched)
-        a.q = uniform(a.q);
-        a.px = uniform(a.px);
-        a.py = uniform(a.py);
-        a.sx = uniform(a.sx);
-        a.sy = uniform(a.sy);
-        a.tab = uniform(a.tab);
-        a.blk = uniform(a.blk);
-        a.dg_anc = uniform(a.dg_anc);
-        a.n = (int64_t)uniform((uint64_t)a.n);
-        a.ntiles = __builtin_amdgcn_readfirstlane(a.ntiles);
+        lt = gt - tile_base_of(b, e);
     };
     int gt = blockIdx.x;
     StepArgs a;
