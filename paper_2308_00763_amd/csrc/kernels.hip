@@ -608,7 +608,8 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
         ey = ey + wt[i] * (Acc)y[i];
     }
     Acc sw = wave_incl_sum(run, lane);
-    sw = wave_incl_max(sw, lane);
+    if constexpr (DT == PF_F64) sw = wave_incl_max(sw, lane);
+    else sw = wave_incl_max_nonneg(sw);  // the weights are non-negative
     ex = wave_sum(ex);
     ey = wave_sum(ey);
     Acc (*red)[kMaxWavesA];

@@ -126,6 +126,15 @@ __device__ __forceinline__ T wave_incl_sum(T v, int /*lane*/) { return wave_incl
 template <typename T>
 __device__ __forceinline__ T wave_incl_max(T v, int /*lane*/) { return wave_incl_scan<OpMax>(v); }
 
+// Inclusive prefix maximum of non-negative floats.  Such floats order as
+// their bit patterns do as signed integers, so the scan runs on the integers,
+// whose DPP maximum steps the compiler folds into single instructions.  Equal,
+// bit for bit, to the float scan on non-negative values.
+__device__ __forceinline__ float wave_incl_max_nonneg(float v)
+{
+    return __int_as_float(wave_incl_scan<OpMax>(__float_as_int(v)));
+}
+
 // Workgroup-wide reductions for a block of NW waves.  `red` is LDS scratch of
 // at least NW elements; every thread receives the result.
 template <int NW, typename T>
