@@ -300,6 +300,16 @@ def test_reduced_modes_many_tiles(dtype):
         d = tv(got["w"], ref["w"])
         print(f"[parity] {dtype} N=2^24+5000 r=8 TV {d:.3e}", flush=True)
         assert d <= 1e-2
+        # the large configuration's own checks: no inf or NaN anywhere, the
+        # normalised weights sum to one, and the largest weight (e^0 = 1
+        # before normalising) is held by a particle of the largest disk sum
+        w = got["w"]
+        assert np.all(np.isfinite(w)) and np.all(np.isfinite(got["x"])) and np.all(np.isfinite(got["y"]))
+        assert np.all(np.isfinite(est))
+        assert abs(w.sum() - 1.0) <= 1e-6
+        s = gs["disk_sum"]
+        assert s[int(np.argmax(w))] == s.max()
+        assert np.max(w) == np.max(w[s == s.max()])
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
