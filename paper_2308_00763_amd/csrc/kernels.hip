@@ -1079,6 +1079,12 @@ __device__ __forceinline__ void combine_filter(const StepArgs& a)
             loc = A::add(loc, v[k]);
         }
         const T sw = A::sum_scan(loc);
+        if (one_round) {
+            // the estimate sums are complete after the only round: their
+            // wave totals ride on this round's exchange
+            const Fv wx = wave_sum(ex), wy = wave_sum(ey);
+            if (lane == 0) { red_x[wv] = wx; red_y[wv] = wy; }
+        }
         if (lane == 63) red_s[wv] = sw;
         __syncthreads();
         if (wv == 0) {
@@ -1103,13 +1109,15 @@ __device__ __forceinline__ void combine_filter(const StepArgs& a)
             }
         }
         carry = wave_off[NW];
-        __syncthreads();
+        if (base + CHUNK < nt) __syncthreads();  // the next round rewrites the exchange
     }
     const T Z = carry;
-    ex = wave_sum(ex);
-    ey = wave_sum(ey);
-    if (lane == 0) { red_x[wv] = ex; red_y[wv] = ey; }
-    __syncthreads();
+    if (!one_round) {
+        ex = wave_sum(ex);
+        ey = wave_sum(ey);
+        if (lane == 0) { red_x[wv] = ex; red_y[wv] = ey; }
+        __syncthreads();
+    }
     Fv sx = red_x[0], sy = red_y[0];
 #pragma unroll
     for (int w = 1; w < NW; ++w) { sx = sx + red_x[w]; sy = sy + red_y[w]; }
@@ -1155,7 +1163,7 @@ __device__ __forceinline__ void combine_filter(const StepArgs& a)
             if (t < nt) tab[t].E = run;
         }
         carry_e = woff_e[NW];
-        __syncthreads();
+        if (base + CHUNK < nt) __syncthreads();
     }
 
     if (tid == 0) {
