@@ -720,11 +720,12 @@ struct TileSlots<PF_F64> {
             const auto* tw = gbl(static_cast<const uint32_t*>(a.tab));
             const auto* bw = gbl(reinterpret_cast<const uint32_t*>(a.blk));
             const int lane = threadIdx.x & 63;
-            const gbl_t<const uint32_t>* p = lane < 5 ? tw + ((int64_t)kW * t + lane)
-                              : lane < 7 ? tw + ((int64_t)kW * (t + 1) + (lane - 5))
-                              : lane == 7 ? tw + ((int64_t)kW * (t - 1) + 4)
-                              : lane < 10 ? bw + (offsetof(DevBlock, R) / 4 + (lane - 8))
-                                          : bw + (offsetof(DevBlock, u0) / 4 + (lane - 10));
+            const gbl_t<const uint32_t>* p =
+                lane < 5    ? tw + ((int64_t)kW * t + lane)
+                : lane < 7  ? tw + ((int64_t)kW * (t + 1) + (lane - 5))
+                : lane == 7 ? tw + ((int64_t)kW * (t - 1) + 4)
+                : lane < 10 ? bw + (offsetof(DevBlock, R) / 4 + (lane - 8))
+                            : bw + (offsetof(DevBlock, u0) / 4 + (lane - 10));
             w = 0;
             if (lane < 12 && (lane != 7 || t > 0)) w = *p;
         }
@@ -735,13 +736,6 @@ struct TileSlots<PF_F64> {
                   "table word layout");
     static_assert(offsetof(DevBlock, R) % 8 == 0 && offsetof(DevBlock, u0) % 8 == 0, "block word layout");
     TileSlots() = default;
-    // straight from the table (uniform loads)
-    __device__ TileSlots(const StepArgs& a, int t)
-    {
-        const auto* tab = gbl(static_cast<const TileTab64*>(a.tab));
-        const auto* blk = gbl(a.blk);
-        init(blk->R, blk->u0, tab[t].off, tab[t].f, tab[t + 1].off, tab[t].E, t > 0 ? tab[t - 1].E : 0);
-    }
     __device__ explicit TileSlots(const Raw& r)
     {
         init(r.dword(8), r.dword(10), r.dword(0), r.dword(2), r.dword(5), r.word(4), r.word(7));
@@ -754,7 +748,6 @@ struct TileSlots<PF_F64> {
         E = e;
         Eprev = eprev;
     }
-    __device__ int operator()(const void* q, int i, int n) const { return of(static_cast<const double*>(q)[i], n); }
     __device__ int of(double qv, int n) const
     {
         double y = __builtin_fma(scale, qv, base);
@@ -783,10 +776,11 @@ struct TileSlots<PF_F32> {
             const auto* tw = gbl(static_cast<const uint32_t*>(a.tab));
             const auto* bw = gbl(reinterpret_cast<const uint32_t*>(a.blk));
             const int lane = threadIdx.x & 63;
-            const gbl_t<const uint32_t>* p = lane < 4 ? tw + (4 * (int64_t)t + lane)
-                              : lane == 4 ? tw + (4 * (int64_t)(t - 1) + 3)
-                              : lane < 7 ? bw + (offsetof(DevBlock, R_hi) / 4 + (lane - 5))
-                                         : bw + (offsetof(DevBlock, u0_hi) / 4 + (lane - 7));
+            const gbl_t<const uint32_t>* p =
+                lane < 4    ? tw + (4 * (int64_t)t + lane)
+                : lane == 4 ? tw + (4 * (int64_t)(t - 1) + 3)
+                : lane < 7  ? bw + (offsetof(DevBlock, R_hi) / 4 + (lane - 5))
+                            : bw + (offsetof(DevBlock, u0_hi) / 4 + (lane - 7));
             w = 0;
             if (lane < 9 && (lane != 4 || t > 0)) w = *p;
         }
@@ -798,14 +792,6 @@ struct TileSlots<PF_F32> {
     static_assert(offsetof(DevBlock, R_lo) == offsetof(DevBlock, R_hi) + 4 &&
                   offsetof(DevBlock, u0_lo) == offsetof(DevBlock, u0_hi) + 4, "block word layout");
     TileSlots() = default;
-    // straight from the table (uniform loads)
-    __device__ TileSlots(const StepArgs& a, int t)
-    {
-        const auto* tab = gbl(static_cast<const TileTab32*>(a.tab));
-        const auto* blk = gbl(a.blk);
-        init(ff{blk->R_hi, blk->R_lo}, ff{blk->u0_hi, blk->u0_lo}, ff{tab[t].off_hi, tab[t].off_lo},
-             tab[t].f, tab[t].E, t > 0 ? tab[t - 1].E : 0);
-    }
     __device__ explicit TileSlots(const Raw& r)
     {
         init(ff{r.fword(5), r.fword(6)}, ff{r.fword(7), r.fword(8)}, ff{r.fword(0), r.fword(1)}, r.fword(2),
@@ -823,7 +809,6 @@ struct TileSlots<PF_F32> {
         Eprev = eprev;
         cap = E - B;
     }
-    __device__ int operator()(const void* q, int i, int n) const { return of(static_cast<const float*>(q)[i], n); }
     __device__ int of(float qv, int /*n*/) const
     {
         const float y = __builtin_fmaf(scale, qv, frac);
