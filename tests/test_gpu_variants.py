@@ -1,16 +1,17 @@
 """GPU tests of the implementation variants (the straightforward likelihood
 and resampler, and other workgroup sizes): the same step as the default, so
-FP64 keeps element-wise parity with the oracle, the reduced modes keep the
-resampling properties, and variants that do not change the arithmetic give
-bit-identical results."""
+FP64 keeps element-wise parity with the oracle, the reduced modes resample as
+the FP64 step of their own disk sums does (within the mode's resolution, which
+the straightforward resampler's float distribution widens), and variants that
+do not change the arithmetic give bit-identical results."""
 import numpy as np
 import pytest
 import torch
 
 import paper_2308_00763_amd as pf
 import pfsynth
-from gpu_common import (check_resample_consistency, compare_f64_step, make_filter,
-                        oracle_params, oracle_step_parts, tv)
+from gpu_common import (check_reduced_step, compare_f64_step, make_filter, oracle_params,
+                        oracle_step_parts, tv)
 
 pytestmark = pytest.mark.gpu
 
@@ -65,11 +66,12 @@ def test_f64_variant_matches_oracle(variant, n):
 
 @pytest.mark.parametrize("variant", VARIANTS, ids=lambda v: "-".join(f"{k}={x}" for k, x in v.items()))
 @pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
-def test_reduced_variant_keeps_the_resampling_properties(variant, dtype):
+def test_reduced_variant_resamples_as_fp64_does(variant, dtype):
     _, vid = _vid()
     n = 5000
     for got, gs, est, ref in _teacher_forced(dtype, n, vid, 3, **variant):
-        check_resample_consistency(got, gs, n)
+        check_reduced_step(got, gs, est, ref["u0"], ref["denom"], n, dtype,
+                           naive=bool(variant.get("naive_resample")))
         assert tv(got["w"], ref["w"]) <= 0.1
 
 
