@@ -95,6 +95,8 @@ def lib():
                                     ctypes.c_uint32, ctypes.c_uint32, ip, dp]
         L.or_gumbel_max.argtypes = [ctypes.c_int64, dp, ctypes.c_uint64, ctypes.c_uint32,
                                     ctypes.c_uint32, ip, dp]
+        L.or_rejection.argtypes = [ctypes.c_int64, dp, ctypes.c_int32, ctypes.c_uint64,
+                                   ctypes.c_uint32, ctypes.c_uint32, ip, dp, ip]
         _lib = L
     return _lib
 
@@ -262,3 +264,17 @@ def gumbel_max(L, seed: int, stream_id: int, t: int):
     lib().or_gumbel_max(n, _ptr(L, ctypes.c_double), int(seed), int(stream_id), int(t),
                         _ptr(anc, ctypes.c_int32), _ptr(margin, ctypes.c_double))
     return anc, margin
+
+
+def rejection(L, cap: int, seed: int, stream_id: int, t: int):
+    """Rejection resampling of log-likelihoods L with at most `cap` trials per
+    slot (pf_oracle.c, or_rejection).  Returns (ancestors, margins, trials)."""
+    L = np.ascontiguousarray(L, dtype=np.float64)
+    n = L.size
+    anc = np.zeros(n, dtype=np.int32)
+    margin = np.zeros(n)
+    trials = np.zeros(n, dtype=np.int32)
+    lib().or_rejection(n, _ptr(L, ctypes.c_double), int(cap), int(seed), int(stream_id), int(t),
+                       _ptr(anc, ctypes.c_int32), _ptr(margin, ctypes.c_double),
+                       _ptr(trials, ctypes.c_int32))
+    return anc, margin, trials

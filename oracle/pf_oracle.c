@@ -330,6 +330,53 @@ void or_metropolis(int64_t n, const double *L, int32_t B, uint64_t seed, uint32_
 }
 
 /* ------------------------------------------------------------------ */
+/* Rejection resampling (Murray, Lee & Jacob 2016, the other scan-free
+ * resampler of the related work the paper cites, Sec. 3): slot j first
+ * proposes its own particle c = j; a proposal c is accepted with probability
+ * w_c / w_max = exp(L_c - M), M = max_k L_k; after a rejection the next
+ * proposal is a particle drawn uniformly.  It needs the maximum but no sum or
+ * cumulative distribution.  Each particle's expected offspring count is
+ * exactly N w_i / sum(w): P(a_j = i) = [i = j] r_j + (1 - r_j) w_i / sum(w)
+ * with r_j = w_j / w_max, and summing over j gives N w_i / sum(w).  The
+ * expected number of trials of slot j is 1 + (1 - r_j) N w_max / sum(w).
+ * At most `cap` trials: a slot that rejects all of them keeps the particle
+ * of its last trial (a bias the cap bounds).
+ * Random numbers of slot j at step t (this build's layout): trials m = 2q
+ * and 2q + 1 share ctr = (j, t, stream_id, 2 + q); trial 2q uses words 0
+ * and 1, trial 2q + 1 words 2 and 3; the first word gives u = (word + 1/2)
+ * 2^-32, the test u <= exp(L_c - M), and the second the next proposal
+ * floor(word * n / 2^32).
+ * margin (optional): for slot j the smallest |u - exp(L_c - M)| over its
+ * trials; trials (optional): the number of trials slot j took. */
+void or_rejection(int64_t n, const double *L, int32_t cap, uint64_t seed, uint32_t stream_id,
+                  uint32_t t, int32_t *anc, double *margin, int32_t *trials)
+{
+    double M = -INFINITY;
+    for (int64_t k = 0; k < n; ++k)
+        if (L[k] > M) M = L[k];
+    for (int64_t j = 0; j < n; ++j) {
+        int64_t c = j;
+        double mg = 1.0;
+        uint32_t w[4] = {0, 0, 0, 0};
+        int32_t m = 0;
+        for (; m < cap; ++m) {
+            if (m % 2 == 0) or_philox_words(seed, (uint32_t)j, t, stream_id, 2u + (uint32_t)(m / 2), w);
+            uint32_t wu = (m % 2 == 0) ? w[0] : w[2];
+            uint32_t wi = (m % 2 == 0) ? w[1] : w[3];
+            double u = ((double)wu + 0.5) * 0x1.0p-32;
+            double r = exp(L[c] - M);
+            double d = fabs(u - r);
+            if (d < mg) mg = d;
+            if (u <= r) break;
+            if (m + 1 < cap) c = (int64_t)(((uint64_t)wi * (uint64_t)n) >> 32);
+        }
+        anc[j] = (int32_t)c;
+        if (margin) margin[j] = mg;
+        if (trials) trials[j] = m < cap ? m + 1 : cap;
+    }
+}
+
+/* ------------------------------------------------------------------ */
 /* Multinomial resampling by the Gumbel-max scheme (the alternative the
  * paper weighs in Sec. 4, numerical-stability paragraph): slot i takes
  * a_i = argmax_j (L_j + G_ij) with G_ij independent standard Gumbel
