@@ -46,21 +46,33 @@ def pass_a_slots(dtype, radius):
     """Algorithmic pass-A slots per update at disk radius r: the radius-5
     count with its 18 + 1 disk-sum slots replaced by 2 (2r - 1) + 1."""
     return PASS_A_SLOTS[dtype] - 19 + 2 * (2 * radius - 1) + 1
+# Algorithmic bytes per update (spill-free): the particle's state read and
+# its resampled state written, two coordinates of 8 / 4 / 2 / 2 bytes each way.
 STATE_BYTES = {"f64": 32, "f32": 16, "f16": 8, "bf16": 8}
-# pass C per update: read the propagated position and the tile-local prefix
-# sum, write the resampled position
-PASS_C_BYTES = {"f64": 16 + 8 + 16, "f32": 8 + 4 + 8, "f16": 4 + 4 + 4, "bf16": 4 + 4 + 4}
-# pass A per update: read the state, write the propagated position and the
-# tile-local prefix sum
-PASS_A_BYTES = {"f64": 16 + 16 + 8, "f32": 8 + 8 + 4, "f16": 4 + 4 + 4, "bf16": 4 + 4 + 4}
+# Algorithmic VALU slots of resampling per update: the particle's end slot
+# (one multiply-add, floor, conversion, compare), its first-slot mark, its
+# share of the slot scan and the copy of its position.
+RESAMPLE_SLOTS = 8
+# Bytes per update that the two-pass step moves beyond the algorithmic ones:
+# pass A writes the propagated state and the tile-local prefix sums, pass C
+# reads them back.
+SPILL_BYTES = {"f64": 2 * (16 + 8), "f32": 2 * (8 + 4), "f16": 2 * (4 + 4), "bf16": 2 * (4 + 4)}
+
+
+def step_slots(dtype, radius):
+    """Algorithmic VALU slots of one whole step per update."""
+    return pass_a_slots(dtype, radius) + RESAMPLE_SLOTS
 
 
 def step_bound_s(dtype, radius, n):
-    """Roofline time of one step of n particles: pass A at the larger of its
-    VALU and HBM times, then pass C at its HBM time (the combine's work is
-    per tile, negligible); the passes run one after the other."""
-    a = max(pass_a_slots(dtype, radius) / PEAK_LANE_OPS, PASS_A_BYTES[dtype] / PEAK_HBM)
-    return n * (a + PASS_C_BYTES[dtype] / PEAK_HBM)
+    """Roofline time of one step of n particles on the algorithmic work only:
+    the larger of the VALU time of every step part (pass-A slots plus
+    resampling) and the HBM time of the state read and written.  The spill of
+    the propagated state and prefix sums between passes is not algorithmic
+    work and is not counted."""
+    return n * max(step_slots(dtype, radius) / PEAK_LANE_OPS, STATE_BYTES[dtype] / PEAK_HBM)
+
+
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "pass_a_f16_disk1024_n1m_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2308_00763_amd", "csrc", f)
                   for f in ("kernels.hip", "philox.hpp", "wave.hpp", "pf_internal.hpp")]
@@ -75,9 +87,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, dtype):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel sources (else None)."""
+def _traffic_values():
+    """Machine-readable values of the committed counter summary, if it was
+    taken on the current kernel sources (else None)."""
     if not os.path.exists(TRAFFIC_SUMMARY):
         return None
     vals = {}
@@ -88,11 +100,30 @@ def measured_traffic(kernel, dtype):
                 vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256") != kernel_source_hash():
         return None
-    if vals.get("kernel") != kernel or vals.get("dtype") != dtype:
+    return vals
+
+
+def measured_traffic(kernel, dtype):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's counts), if
+    it was taken on the current kernel sources for this mode (else None)."""
+    vals = _traffic_values()
+    if vals is None or vals.get("dtype") != dtype or f"{kernel}_fetch_kib" not in vals:
         return None
-    fetch = float(vals["fetch_kib_per_dispatch"]) * 1024 * float(vals["fetch_scale"])
-    write = float(vals["write_kib_per_dispatch"]) * 1024 * float(vals["write_scale"])
+    fetch = float(vals[f"{kernel}_fetch_kib"]) * 1024 * float(vals["fetch_scale"])
+    write = float(vals[f"{kernel}_write_kib"]) * 1024 * float(vals["write_scale"])
     return fetch + write
+
+
+def measured_step_traffic(dtype):
+    """HBM bytes of one whole step (every kernel of the step) from the same
+    summary, or None."""
+    vals = _traffic_values()
+    if vals is None or vals.get("dtype") != dtype:
+        return None
+    ks = [k.strip() for k in vals.get("kernels", "").split(",") if k.strip()]
+    parts = [measured_traffic(k, dtype) for k in ks]
+    return sum(parts) if parts and None not in parts else None
 
 
 def log(msg):
@@ -503,27 +534,69 @@ def run_large(pf, torch, pfsynth, args, modes):
                 steps=ls, warmup=lw, modes=lres)
 
 
-def cpu_baseline(w, vid, budget_s):
-    """The FP64 oracle (sequential C, one thread) on the first steps of the
-    same video at the same N, as many steps as fit in about budget_s."""
+def _oracle_rate(pfsynth, w, vid, budget_s, max_steps=None, repeat=False):
+    """Particle-updates/s of the oracle's OpenMP timing build on one filter
+    of workload w over the frames of vid, stepping until about budget_s
+    (whole passes over the video when `repeat`)."""
     import oracle
-    oracle.build(force=False)
     op = oracle.make_params(w.n_particles, w.width, w.height, radius=w.radius, drift=w.drift,
                             sigma=w.sigma, seed=w.filter_seed)
-    x = np.full(w.n_particles, vid.centres[0][0])
-    y = np.full(w.n_particles, vid.centres[0][1])
-    t0 = time.perf_counter()
+    T = vid.frames.shape[0]
+    last = T - 1 if max_steps is None else min(T - 1, max_steps)
     steps = 0
-    while steps < vid.frames.shape[0] - 1:
-        out = oracle.step(op, steps + 1, vid.frames[steps + 1], x, y)
-        x, y = out["x"], out["y"]
-        steps += 1
-        if time.perf_counter() - t0 > budget_s:
+    t0 = time.perf_counter()
+    while True:
+        st = oracle.OmpStepper(op, np.full(w.n_particles, vid.centres[0][0]),
+                               np.full(w.n_particles, vid.centres[0][1]))
+        for t in range(1, last + 1):
+            st.step(t, vid.frames[t])
+            steps += 1
+            if not repeat and time.perf_counter() - t0 > budget_s:
+                break
+        if not repeat or time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
-    return dict(value=w.n_particles * steps / dt, unit="particle-updates/s", cores=1,
-                kind="oracle",
-                sample=f"first {steps} steps of {w.name} at N={w.n_particles}, FP64, 1 thread")
+    return w.n_particles * steps / dt, steps, st.threads
+
+
+def cpu_baseline(w, vid, budget_s, pfsynth):
+    """The FP64 oracle timed on the host's cores: its OpenMP timing build
+    (the sequential oracle's per-particle functions, per-thread partial sums
+    and a two-pass parallel scan), as many threads as OpenMP is given, on a
+    bounded sample of each single-GPU workload: the headline video
+    (`value`), the 128 px parity video, the 2^24-particle video and a 5 %
+    sample of the 4096-stream fleet.  About budget_s seconds per workload."""
+    import oracle
+    oracle.build(force=False)
+    per = {}
+    rate, steps, thr = _oracle_rate(pfsynth, w, vid, budget_s)
+    per[w.name] = dict(value=rate, sample=f"first {steps} steps at N={w.n_particles}")
+    w1 = pfsynth.WORKLOADS["disk128_n1000"]
+    r1, s1, _ = _oracle_rate(pfsynth, w1, pfsynth.workload_video(w1), budget_s / 4, repeat=True)
+    per[w1.name] = dict(value=r1, sample=f"{s1} steps (whole 9-step runs, repeated) at N=1000")
+    w3 = pfsynth.WORKLOADS["disk512_r8_n16m"]
+    r3, s3, _ = _oracle_rate(pfsynth, w3, pfsynth.workload_video(w3, frames=6), budget_s, max_steps=5)
+    per[w3.name] = dict(value=r3, sample=f"first {s3} steps at N={w3.n_particles}, radius 8")
+    # the fleet: every 20th of the 4096 streams (205 filters), 10 steps each
+    streams = pfsynth.stream_mix(4096, side=256, frames=50)[::20]
+    upd = 0
+    t0 = time.perf_counter()
+    for s in streams:
+        v = pfsynth.stream_video(s, 256, 11)
+        p = oracle.make_params(s.n_particles, 256, 256, radius=5, drift=s.velocity, seed=0,
+                               stream_id=s.stream_id)
+        st = oracle.OmpStepper(p, np.full(s.n_particles, float(s.start[0])),
+                               np.full(s.n_particles, float(s.start[1])))
+        for t in range(1, 11):
+            st.step(t, v.frames[t])
+        upd += 10 * s.n_particles
+    r4 = upd / (time.perf_counter() - t0)
+    per["fleet4096_256px"] = dict(value=r4, sample=f"every 20th of the 4096 streams ({len(streams)} filters, "
+                                                   f"{upd} updates), first 10 steps each, one filter at a time")
+    return dict(value=rate, unit="particle-updates/s", cores=thr, kind="oracle",
+                sample=f"first {steps} steps of {w.name} at N={w.n_particles}, FP64, OpenMP timing build "
+                       f"of the oracle on {thr} threads (host CPUs visible: {os.cpu_count()})",
+                per_workload=per)
 
 
 def main():
@@ -533,7 +606,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="disk1024_n1m")
     ap.add_argument("--modes", default="f16,f32,bf16,f64")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-budget", type=float, default=6.0,
+                    help="seconds of oracle timing per workload of the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-track", action="store_true")
     ap.add_argument("--large", default="disk512_r8_n16m",
@@ -614,11 +688,17 @@ def main():
                     kernel_us=r["pass_a_us"],
                     work_per_update=pass_a_slots(head, w.radius), work_unit="VALU lane slots")
     else:
+        # pass C's algorithmic bytes: the resampled state it writes
         c_s = r["pass_c_us"] * 1e-6
-        achieved = PASS_C_BYTES[head] * w.n_particles / c_s
+        achieved = STATE_BYTES[head] // 2 * w.n_particles / c_s
         roof = dict(bound="hbm", kernel="pass_c", achieved=achieved / 1e9, peak=PEAK_HBM / 1e9,
-                    unit="GB/s", frac=achieved / PEAK_HBM, traffic=None, kernel_us=r["pass_c_us"],
-                    work_per_update=PASS_C_BYTES[head], work_unit="bytes")
+                    unit="GB/s", frac=achieved / PEAK_HBM,
+                    traffic=measured_traffic("pass_c", head) if w.name == "disk1024_n1m" else None,
+                    kernel_us=r["pass_c_us"], work_per_update=STATE_BYTES[head] // 2, work_unit="bytes")
+    # HBM bytes the whole step moves (counters) against its algorithmic bytes
+    st = measured_step_traffic(head) if w.name == "disk1024_n1m" else None
+    r["step_traffic_bytes"] = st
+    r["traffic_ratio"] = st / (STATE_BYTES[head] * w.n_particles) if st else None
 
     out = {
         "metric": "particle-updates/sec FP16 vs FP64 at <=0.5px track error; p99 frame latency",
@@ -682,7 +762,7 @@ def main():
         section("serving_closed_loop", lambda: run_serving_closed(pf, torch, pfsynth, 10.0))
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
-        section("cpu_baseline", lambda: cpu_baseline(w, vid, args.cpu_budget))
+        section("cpu_baseline", lambda: cpu_baseline(w, vid, args.cpu_budget, pfsynth))
     print(json.dumps(out), flush=True)
 
 

@@ -16,22 +16,27 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pf_oracle.c")
+_SRC_OMP = os.path.join(_HERE, "pf_oracle_omp.c")
 _BUILD = os.path.join(_HERE, "_build")
 _LIB_PATH = os.path.join(_BUILD, "liboracle.so")
+_LIB_OMP_PATH = os.path.join(_BUILD, "liboracle_omp.so")
 
 MEAN = 0
 SUM = 1
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (no FMA contraction, glibc libm)."""
+    """Compile the oracle with gcc (no FMA contraction, glibc libm): the
+    sequential build used for parity, and the OpenMP build used only to time
+    the oracle on every host core."""
     os.makedirs(_BUILD, exist_ok=True)
-    if force or not os.path.exists(_LIB_PATH):
-        tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(
-            ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-             "-fPIC", "-shared", _SRC, "-lm", "-o", tmp])
-        os.replace(tmp, _LIB_PATH)
+    for src, path, extra in ((_SRC, _LIB_PATH, []), (_SRC_OMP, _LIB_OMP_PATH, ["-fopenmp"])):
+        if force or not os.path.exists(path):
+            tmp = path + ".tmp"
+            subprocess.check_call(
+                ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math"] + extra +
+                ["-fPIC", "-shared", src, "-lm", "-o", tmp])
+            os.replace(tmp, path)
     return _LIB_PATH
 
 
@@ -99,6 +104,27 @@ def lib():
                                    ctypes.c_uint32, ctypes.c_uint32, ip, dp, ip]
         _lib = L
     return _lib
+
+
+_lib_omp = None
+
+
+def lib_omp():
+    """The OpenMP timing build (pf_oracle_omp.c)."""
+    global _lib_omp
+    if _lib_omp is None:
+        if not os.path.exists(_LIB_OMP_PATH):
+            build(force=False)
+        L = ctypes.CDLL(_LIB_OMP_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.or_step_omp.argtypes = [ctypes.POINTER(Params), ctypes.c_uint32,
+                                  ctypes.POINTER(ctypes.c_uint8), ctypes.c_int64,
+                                  dp, dp, dp, dp, dp, dp, dp]
+        L.or_step_omp.restype = ctypes.c_int
+        L.or_omp_set_threads.argtypes = [ctypes.c_int]
+        L.or_omp_max_threads.restype = ctypes.c_int
+        _lib_omp = L
+    return _lib_omp
 
 
 def _ptr(a, ctype):
@@ -227,6 +253,36 @@ def step(p: Params, t, frame, x, y):
                   _ptr(L, ctypes.c_double), _ptr(w, ctypes.c_double),
                   _ptr(anc, ctypes.c_int32), _ptr(est, ctypes.c_double))
     return dict(x=x, y=y, x_prop=xp, y_prop=yp, L=L, w=w, anc=anc, est=est)
+
+
+class OmpStepper:
+    """Steps of one filter with the OpenMP timing build, reusing its work
+    arrays; x, y hold the particles after the latest step.  `threads` > 0
+    sets OpenMP's thread count for the process."""
+
+    def __init__(self, p: Params, x, y, threads: int = 0):
+        self.p = p
+        self.x = np.array(x, dtype=np.float64)
+        self.y = np.array(y, dtype=np.float64)
+        assert self.x.size == p.n and self.y.size == p.n
+        self.xp = np.zeros(p.n)
+        self.yp = np.zeros(p.n)
+        self.L = np.zeros(p.n)
+        self.P = np.zeros(p.n)
+        self.est = np.zeros(2)
+        if threads > 0:
+            lib_omp().or_omp_set_threads(int(threads))
+        self.threads = 0
+
+    def step(self, t, frame):
+        frame = np.ascontiguousarray(frame, dtype=np.uint8)
+        assert frame.shape == (self.p.height, self.p.width)
+        d = ctypes.c_double
+        self.threads = lib_omp().or_step_omp(
+            ctypes.byref(self.p), t, _ptr(frame, ctypes.c_uint8), frame.shape[1],
+            _ptr(self.x, d), _ptr(self.y, d), _ptr(self.xp, d), _ptr(self.yp, d),
+            _ptr(self.L, d), _ptr(self.P, d), _ptr(self.est, d))
+        return self.est.copy()
 
 
 def run(p: Params, video, x0, y0):

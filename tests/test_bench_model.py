@@ -16,14 +16,20 @@ def test_pass_a_slots_scale_with_the_disk_rows():
     assert bench.pass_a_slots("f64", 8) - bench.pass_a_slots("f64", 5) == 12
 
 
-def test_step_bound_is_pass_a_roof_plus_pass_c_bytes():
+def test_step_bound_counts_algorithmic_work_only():
+    # the larger of the step's VALU time and the HBM time of the state read
+    # and written (8 B per FP16 update); the two-pass spill is not counted
+    assert bench.STATE_BYTES == {"f64": 32, "f32": 16, "f16": 8, "bf16": 8}
     for dt in ("f64", "f32", "f16", "bf16"):
-        a = max(bench.pass_a_slots(dt, 5) / bench.PEAK_LANE_OPS, bench.PASS_A_BYTES[dt] / bench.PEAK_HBM)
-        one = a + bench.PASS_C_BYTES[dt] / bench.PEAK_HBM
+        v = (bench.pass_a_slots(dt, 5) + bench.RESAMPLE_SLOTS) / bench.PEAK_LANE_OPS
+        m = bench.STATE_BYTES[dt] / bench.PEAK_HBM
+        one = max(v, m)
         assert abs(bench.step_bound_s(dt, 5, 1) - one) < 1e-24
         assert abs(bench.step_bound_s(dt, 5, 1 << 20) - (1 << 20) * one) < 1e-15
-    # every pass-A roof here is the VALU's; FP64 moves the most bytes
-    assert bench.PASS_C_BYTES["f64"] > bench.PASS_C_BYTES["f32"] > bench.PASS_C_BYTES["f16"]
+        # every mode's step is VALU-bound on its algorithmic work
+        assert v > m
+    # 130 slots per FP16 update at r = 5: 3.47 us for 2^20 particles
+    assert abs(bench.step_bound_s("f16", 5, 1 << 20) - 130 * (1 << 20) / bench.PEAK_LANE_OPS) < 1e-15
 
 
 def test_more_than_one_gpu_is_refused():
