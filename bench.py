@@ -446,7 +446,8 @@ def run_resamplers(pf, torch, frames_dev, centres, w, steps, warmup, dtypes=("f1
     nsteps = warmup + steps
     cases = [(w, "systematic", {}), (w, "metropolis B=8", dict(metropolis_steps=8)),
              (w, "metropolis B=32", dict(metropolis_steps=32)),
-             (w, "metropolis B=128", dict(metropolis_steps=128))]
+             (w, "metropolis B=128", dict(metropolis_steps=128)),
+             (w, "rejection, at most 4096 trials", dict(rejection_trials=4096))]
     w64 = dataclasses.replace(w, n_particles=65536, name=w.name + "_n65536")
     cases += [(w64, "systematic", {}), (w64, "gumbel-max", dict(gumbel_max=True))]
     res = {}
@@ -461,6 +462,63 @@ def run_resamplers(pf, torch, frames_dev, centres, w, steps, warmup, dtypes=("f1
                              resample_us=1e3 * prof[2] / prof[3], track_rms_vs_truth_px=rms))
         res[dt] = rows
     return res
+
+
+RESAMPLER_CASES = [("systematic", {}), ("metropolis B=8", dict(metropolis_steps=8)),
+                   ("metropolis B=32", dict(metropolis_steps=32)),
+                   ("metropolis B=128", dict(metropolis_steps=128)),
+                   ("rejection, at most 4096 trials", dict(rejection_trials=4096))]
+
+
+def run_resampler_bias(pf, torch, pfsynth, runs=8, steps=10, dtype="f16"):
+    """Bias and speed of the resamplers at 2^24 particles (512x512, radius 8,
+    noise sigma 8).  Speed: ms per step and resampling kernel time on the
+    video.  Bias: the particles of a real step (after three systematic steps)
+    are frozen (no drift, no noise) and resampled `runs` times with fresh
+    random streams; the offspring counts averaged over the runs are compared
+    with N w (w the step's normalised weights, the same in every run): TV =
+    1/2 sum |mean count / N - w|.  An unbiased multinomial resampler's TV from
+    its noise alone is about 1/2 sum sqrt(2 w (1 - w) / (pi N runs)) (the
+    "multinomial_floor"); systematic resampling's counts vary less."""
+    wl = pfsynth.WORKLOADS["disk512_r8_n16m"]
+    n = wl.n_particles
+    vid = pfsynth.workload_video(wl, frames=steps + 12)
+    fr = torch.from_numpy(vid.frames).to("cuda:0")
+    x0, y0 = vid.centres[0]
+    out = {"workload": f"{wl.name}: N={n}, radius {wl.radius}, noise sigma {wl.noise_sigma}, {dtype}",
+           "runs": runs, "rows": []}
+    # a state to freeze: three systematic steps on the video
+    f = pf.Filter(pf.make_params(n, wl.width, wl.height, dtype, radius=wl.radius, x0=x0, y0=y0,
+                                 drift=wl.drift, sigma=wl.sigma, seed=wl.filter_seed))
+    for t in (1, 2, 3):
+        f.step(fr[t])
+    st = f.export()
+    f.close()
+    floor = None
+    for name, var in RESAMPLER_CASES:
+        secs, _ = run_mode(pf, torch, fr, vid.centres, wl, dtype, steps, 1, False, **var)
+        _, prof = run_mode(pf, torch, fr, vid.centres, wl, dtype, steps, 1, True, **var)
+        g = pf.Filter(pf.make_params(n, wl.width, wl.height, dtype, radius=wl.radius, x0=x0, y0=y0,
+                                     drift=(0.0, 0.0), sigma=(0.0, 0.0), seed=wl.filter_seed,
+                                     diagnostics=True, **var))
+        mean = np.zeros(n)
+        w = None
+        for r in range(runs):
+            g.load(st["x"], st["y"], 3 + r)
+            g.step(fr[4])
+            e = g.export()
+            mean += np.bincount(e["anc"], minlength=n)
+            w = e["w"] if w is None else w
+        g.close()
+        mean /= runs
+        tv = 0.5 * float(np.sum(np.abs(mean / n - w)))
+        if floor is None:
+            floor = 0.5 * float(np.sum(np.sqrt(2 * w * (1 - w) / (np.pi * n * runs))))
+        out["rows"].append(dict(resampler=name, ms_per_step=1e3 * secs / steps,
+                                resample_us=1e3 * prof[2] / prof[3],
+                                offspring_tv=tv))
+    out["multinomial_floor"] = floor
+    return out
 
 
 # The paper's FP16 speedups (whole application, 32k and 64k particles, on
@@ -679,8 +737,8 @@ def main():
     r = res[head]
     # dominant kernel: the longer of the two passes
     dom = "pass_a" if r["pass_a_us"] >= r["pass_c_us"] else "pass_c"
-    a_s = r["pass_a_us"] * 1e-6
     if dom == "pass_a":
+        a_s = r["pass_a_us"] * 1e-6
         achieved = pass_a_slots(head, w.radius) * w.n_particles / a_s
         roof = dict(bound="alu", kernel="pass_a", achieved=achieved / 1e12, peak=PEAK_LANE_OPS / 1e12,
                     unit="Tlane-op/s", frac=achieved / PEAK_LANE_OPS,
@@ -743,6 +801,7 @@ def main():
                                                      min(args.steps, 40), args.warmup))
         section("paper_sizes", lambda: run_paper_sizes(pf, torch, frames_dev, vid.centres, w,
                                                        min(args.steps, 40), args.warmup))
+        section("resampler_bias", lambda: run_resampler_bias(pf, torch, pfsynth))
     if not args.no_ablation:
         def tune_headline():
             from paper_2308_00763_amd.tune import autotune

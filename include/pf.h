@@ -121,6 +121,22 @@ typedef enum pf_lik_norm { PF_LIK_MEAN = 0, PF_LIK_SUM = 1 } pf_lik_norm;
  * particle of workspace.  Not accepted by the batch calls. */
 #define PF_FLAG_GUMBEL_MAX (1u << 17)
 
+/* Rejection resampling (Murray, Lee & Jacob, 2016; the other scan-free
+ * resampler of the paper's related work, Sec. 3) instead of systematic
+ * resampling: slot j first proposes particle j; a proposal c is accepted
+ * with probability w_c / w_max = exp(L_c - max L), and after a rejection the
+ * next proposal is a uniform particle.  Each particle's expected offspring
+ * count is exactly N w_c (unbiased) while no slot runs out of trials; at
+ * most 64 v trials (v in bits 18-25, PF_METROPOLIS_STEPS_SHIFT; 0 = 4096),
+ * after which a slot keeps its last proposal.  Needs the maximum but no
+ * normaliser or cumulative distribution.  Random numbers: trials 2q and
+ * 2q + 1 of slot j at step t use counter (j, t, stream_id, 2 + q), words 0-1
+ * and 2-3; the first of each pair gives u = (word + 1/2) 2^-32 (the top 24
+ * bits in the reduced modes), the second the next proposal
+ * floor(word * N / 2^32).  Costs 4 bytes per particle of workspace.  Not
+ * accepted by the batch calls. */
+#define PF_FLAG_REJECTION (1u << 28)
+
 typedef struct pf_params {
     uint32_t struct_size;  /* must be sizeof(pf_params) */
     int32_t dtype;         /* pf_dtype */

@@ -33,6 +33,7 @@ PF_THREADS_C_SHIFT = 12
 PF_FLAG_METROPOLIS = 1 << 16
 PF_METROPOLIS_STEPS_SHIFT = 18
 PF_FLAG_GUMBEL_MAX = 1 << 17
+PF_FLAG_REJECTION = 1 << 28
 
 PF_ABI_VERSION = 3
 
@@ -134,10 +135,16 @@ def make_params(n, width, height, dtype="f64", radius=5, x0=0.0, y0=0.0, drift=(
                 sigma=(5.0, 2.0), seed=0, stream_id=0, fg=228, bg=100, kappa=50.0,
                 lik_norm=PF_LIK_MEAN, diagnostics=False, naive_likelihood=False,
                 naive_resample=False, threads_a=None, threads_c=None,
-                metropolis_steps=0, gumbel_max=False) -> pf_params:
+                metropolis_steps=0, gumbel_max=False, rejection_trials=0) -> pf_params:
+    """Parameters of one filter.  rejection_trials > 0 selects rejection
+    resampling with at most that many trials per slot (a multiple of 64 up
+    to 16320)."""
     dt = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
     if not 0 <= int(metropolis_steps) <= 255:
         raise ValueError(f"metropolis_steps must be in [0, 255], got {metropolis_steps}")
+    rj = int(rejection_trials)
+    if rj and (rj % 64 or not 64 <= rj <= 64 * 255):
+        raise ValueError(f"rejection_trials must be a multiple of 64 in [64, 16320], got {rejection_trials}")
     flags = ((PF_FLAG_DIAGNOSTICS if diagnostics else 0)
              | (PF_FLAG_NAIVE_LIKELIHOOD if naive_likelihood else 0)
              | (PF_FLAG_NAIVE_RESAMPLE if naive_resample else 0)
@@ -145,7 +152,8 @@ def make_params(n, width, height, dtype="f64", radius=5, x0=0.0, y0=0.0, drift=(
              | (threads_field(threads_c) << PF_THREADS_C_SHIFT)
              | ((PF_FLAG_METROPOLIS | (int(metropolis_steps) << PF_METROPOLIS_STEPS_SHIFT))
                 if metropolis_steps else 0)
-             | (PF_FLAG_GUMBEL_MAX if gumbel_max else 0))
+             | (PF_FLAG_GUMBEL_MAX if gumbel_max else 0)
+             | ((PF_FLAG_REJECTION | ((rj // 64) << PF_METROPOLIS_STEPS_SHIFT)) if rj else 0))
     return pf_params(ctypes.sizeof(pf_params), dt, int(n), int(width), int(height), int(radius),
                      int(fg), int(bg), int(lik_norm), float(kappa), float(x0), float(y0),
                      float(drift[0]), float(drift[1]), float(sigma[0]), float(sigma[1]),

@@ -130,18 +130,18 @@ int check_params(const pf_params* p)
     if (p->sigma_x < 0 || p->sigma_y < 0) return fail(PF_ERR_INVALID_ARG, "sigma must be >= 0");
     const uint32_t known = PF_FLAG_DIAGNOSTICS | PF_FLAG_NAIVE_LIKELIHOOD | PF_FLAG_NAIVE_RESAMPLE |
                            (0xFu << PF_THREADS_A_SHIFT) | (0xFu << PF_THREADS_C_SHIFT) | PF_FLAG_METROPOLIS |
-                           (0xFFu << PF_METROPOLIS_STEPS_SHIFT) | PF_FLAG_GUMBEL_MAX;
+                           (0xFFu << PF_METROPOLIS_STEPS_SHIFT) | PF_FLAG_GUMBEL_MAX | PF_FLAG_REJECTION;
     if (p->flags & ~known) return fail(PF_ERR_INVALID_ARG, "unknown flags 0x%x", p->flags);
     const uint32_t ta = (p->flags >> PF_THREADS_A_SHIFT) & 0xF, tc = (p->flags >> PF_THREADS_C_SHIFT) & 0xF;
     if (ta != 0 && (ta < 2 || ta > 4)) return fail(PF_ERR_INVALID_ARG, "pass A threads field %u outside {2, 3, 4}", ta);
     if (tc > 5) return fail(PF_ERR_INVALID_ARG, "pass C threads field %u outside [0, 5]", tc);
     const int resamplers = !!(p->flags & PF_FLAG_METROPOLIS) + !!(p->flags & PF_FLAG_NAIVE_RESAMPLE) +
-                           !!(p->flags & PF_FLAG_GUMBEL_MAX);
+                           !!(p->flags & PF_FLAG_GUMBEL_MAX) + !!(p->flags & PF_FLAG_REJECTION);
     if (resamplers > 1) return fail(PF_ERR_INVALID_ARG, "at most one resampler variant may be chosen");
     if ((p->flags & PF_FLAG_GUMBEL_MAX) && p->n_particles > 65536)
         return fail(PF_ERR_INVALID_ARG, "Gumbel-max resampling takes at most 65536 particles");
-    if (!(p->flags & PF_FLAG_METROPOLIS) && ((p->flags >> PF_METROPOLIS_STEPS_SHIFT) & 0xFFu))
-        return fail(PF_ERR_INVALID_ARG, "Metropolis steps given without PF_FLAG_METROPOLIS");
+    if (!(p->flags & (PF_FLAG_METROPOLIS | PF_FLAG_REJECTION)) && ((p->flags >> PF_METROPOLIS_STEPS_SHIFT) & 0xFFu))
+        return fail(PF_ERR_INVALID_ARG, "Metropolis steps or rejection trials given without their resampler");
     return PF_OK;
 }
 
@@ -260,7 +260,13 @@ void setup_filter(pf_filter* h, const pf_params& pr, uint8_t* ws, hipStream_t st
         const int steps = (int)((p->flags >> PF_METROPOLIS_STEPS_SHIFT) & 0xFFu);
         a.mh_steps = steps == 0 ? 32 : steps;
     }
-    a.s_all = (p->flags & (PF_FLAG_METROPOLIS | PF_FLAG_GUMBEL_MAX)) ? (int32_t*)at(h, L.s_all) : nullptr;
+    a.rj_cap = 0;
+    if (p->flags & PF_FLAG_REJECTION) {
+        const int v = (int)((p->flags >> PF_METROPOLIS_STEPS_SHIFT) & 0xFFu);
+        a.rj_cap = v == 0 ? 4096 : 64 * v;
+    }
+    a.s_all = (p->flags & (PF_FLAG_METROPOLIS | PF_FLAG_GUMBEL_MAX | PF_FLAG_REJECTION)) ? (int32_t*)at(h, L.s_all)
+                                                                                        : nullptr;
 
     DevBlock b{};
     *vx = p->x0;

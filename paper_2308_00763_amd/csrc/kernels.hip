@@ -1817,6 +1817,51 @@ __global__ __launch_bounds__(kBlock) void gumbel_kernel(StepArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// Rejection resampling (Murray, Lee & Jacob, 2016), one thread per slot: slot
+// j first proposes particle j; a proposal c is accepted with probability
+// w_c / w_max = exp(L_c - M), M the step's maximum log-likelihood (the
+// combine's); after a rejection the next proposal is a uniform particle.  At
+// most a.rj_cap trials; a slot that rejects them all keeps its last
+// proposal.  Random words of slot j at step t: trials 2q and 2q + 1 use
+// counter (j, t, stream_id, 2 + q), words 0-1 and 2-3: the first of each pair
+// is the acceptance uniform, the second the next proposal
+// floor(word * N / 2^32).  FP64: L = S / denom and exp in double; the
+// reduced modes compare ((word >> 8) + 1/2) 2^-24 with
+// exp2((S_c - S_max) beta) in float.
+
+template <int DT>
+__global__ __launch_bounds__(kBlock) void rejection_kernel(StepArgs a)
+{
+    using Store = typename ModeT<DT>::Store;
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    const int n = (int)a.n;
+    if (j >= n) return;
+    const int32_t* S = a.s_all;
+    const DevBlock* blk = a.blk;
+    const uint32_t t = blk->t;  // this step's index (the combine has advanced the count)
+    int c = j;
+    u32x4 w{0u, 0u, 0u, 0u};
+    for (int m = 0; m < a.rj_cap; ++m) {
+        if ((m & 1) == 0)
+            w = philox4x32_10((uint32_t)j, t, a.stream_id, 2u + (uint32_t)(m >> 1), a.key0, a.key1);
+        const uint32_t wu = (m & 1) ? w.v2 : w.v0;
+        const uint32_t wi = (m & 1) ? w.v3 : w.v1;
+        bool accept;
+        if constexpr (DT == PF_F64) {
+            accept = ((double)wu + 0.5) * 0x1.0p-32 <= exp((double)S[c] / a.denom - blk->M);
+        } else {
+            accept = ((float)(wu >> 8) + 0.5f) * 0x1.0p-24f <=
+                     __builtin_amdgcn_exp2f((float)(S[c] - blk->Smax) * a.beta);
+        }
+        if (accept) break;
+        if (m + 1 < a.rj_cap) c = (int)(((uint64_t)wi * (uint64_t)(uint32_t)n) >> 32);
+    }
+    static_cast<Store*>(a.sx)[j] = static_cast<const Store*>(a.px)[c];
+    static_cast<Store*>(a.sy)[j] = static_cast<const Store*>(a.py)[c];
+    if (a.dg_anc) a.dg_anc[j] = c;
+}
+
+// ---------------------------------------------------------------------------
 // Normalised weights of the latest step for diagnostics: w_k = wt_k f_t / Z.
 template <int DT>
 __global__ __launch_bounds__(kBlock) void diag_weights_kernel(StepArgs a)
@@ -2035,6 +2080,8 @@ static hipError_t launch_pass_c_t(const StepArgs& a, hipStream_t s, const KTimin
     const dim3 g((unsigned)a.ntiles);
     if (a.mh_steps > 0)
         return launch1(metropolis_kernel<DT>, dim3((unsigned)((a.n + kBlock - 1) / kBlock)), dim3(kBlock), s, tm, a);
+    if (a.rj_cap > 0)
+        return launch1(rejection_kernel<DT>, dim3((unsigned)((a.n + kBlock - 1) / kBlock)), dim3(kBlock), s, tm, a);
     if (a.gumbel)
         return launch1(gumbel_kernel<DT>, dim3((unsigned)((a.n + kBlock - 1) / kBlock)), dim3(kBlock), s, tm, a);
     if (a.naive_res) {

@@ -147,7 +147,7 @@ inline Layout make_layout(const pf_params& p)
     } else {
         L.cdf = 0;
     }
-    if (p.flags & (PF_FLAG_METROPOLIS | PF_FLAG_GUMBEL_MAX)) {
+    if (p.flags & (PF_FLAG_METROPOLIS | PF_FLAG_GUMBEL_MAX | PF_FLAG_REJECTION)) {
         L.s_all = o; o = align256(o + 4 * (size_t)L.n_pad);
     } else {
         L.s_all = 0;
@@ -188,6 +188,7 @@ struct StepArgs {
     int32_t threads_c;  // pass C / naive resampler threads per workgroup: 64 .. 1024 (0: by tile count)
     void* cdf;          // naive resampler: normalised cumulative weights
     int32_t mh_steps;   // Metropolis resampling: steps per slot (0: systematic)
+    int32_t rj_cap;     // rejection resampling: most trials per slot (0: systematic)
     int32_t gumbel;     // Gumbel-max multinomial resampling
     int32_t* s_all;     // Metropolis / Gumbel-max: integer disk terms of all particles
 };

@@ -112,3 +112,15 @@ def test_batch_null_handles_are_rejected_without_a_device():
     arr = (pf.pf_params * 1)(good)
     assert L.pf_batch_init(arr, 1, ctypes.c_void_p(256), 16, None,
                            ctypes.byref(out)) == pf.PF_ERR_WORKSPACE
+
+
+def test_rejection_trials_field():
+    # rejection resampling keeps at most 64 v trials per slot (v in the
+    # shared field), and excludes every other resampler
+    p = pf.make_params(1000, 128, 128, rejection_trials=640)
+    assert p.flags & pf.PF_FLAG_REJECTION
+    assert (p.flags >> pf.PF_METROPOLIS_STEPS_SHIFT) & 0xFF == 10
+    with pytest.raises(ValueError):
+        pf.make_params(1000, 128, 128, rejection_trials=100)
+    with pytest.raises(pf.PfError):
+        pf.pf_workspace_bytes(pf.make_params(1000, 128, 128, rejection_trials=64, metropolis_steps=8))

@@ -2,9 +2,14 @@
 oracle's chain: teacher-forced steps on the 128 px video.  FP64: the
 propagation, disk sums, weights and estimate as in the systematic step, and
 every slot's ancestor equal to the oracle's except where one of the chain's
-comparisons lies within 1e-12 of its threshold.  Reduced modes: the
-oracle's chain run on the GPU's own integer disk terms agrees on at least
-99.9 % of the slots (float against double comparisons)."""
+comparisons lies within 1e-12 of its threshold.  Reduced modes: the oracle's
+chain run on the GPU's own integer disk terms; a slot may differ only where
+one of its chain's comparisons lies within the reduced arithmetic's
+resolution of its threshold: the uniform is the top 24 bits of the word
+(|u24 - u32| <= 2^-24) and exp2((S_i - S_k) beta) is formed in float (the
+exponent carries at most |S_i - S_k| beta 2^-23 <= 24 * 2^-23 of error
+wherever the threshold is above 2^-24, so the ratio's relative error is below
+2.1e-6, plus one ulp of v_exp_f32): REDUCED_MARGIN = 2^-24 + 2.5e-6."""
 import numpy as np
 import pytest
 import torch
@@ -14,6 +19,8 @@ import pfsynth
 from gpu_common import make_filter, near_half, oracle_params, oracle_step_parts
 
 pytestmark = pytest.mark.gpu
+
+REDUCED_MARGIN = 2.0 ** -24 + 2.5e-6
 
 
 def _run(dtype, n, B, steps=3):
@@ -61,9 +68,9 @@ def test_reduced_metropolis_follows_the_oracle_chain_on_its_own_disk_terms(dtype
     for t, got, gs, est, ref, op, nd in _run(dtype, n, B):
         L = gs["disk_sum"].astype(np.float64) / (op.kappa * nd)
         anc, margin = oracle.metropolis(L, B, op.seed, op.stream_id, t)
-        agree = np.mean(got["anc"] == anc)
-        print(f"[metropolis] {dtype} step {t}: {agree:.6f} of slots agree", flush=True)
-        assert agree >= 0.999
+        mism = got["anc"] != anc
+        print(f"[metropolis] {dtype} step {t}: {mism.sum()} of {n} slots differ", flush=True)
+        assert np.all(margin[mism] <= REDUCED_MARGIN), np.flatnonzero(mism & (margin > REDUCED_MARGIN))[:10]
         assert got["anc"].min() >= 0 and got["anc"].max() < n
         assert np.array_equal(got["x"], gs["x_prop"][got["anc"]])
 
