@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define PF_ABI_VERSION 3
+#define PF_ABI_VERSION 4
 
 typedef enum pf_status {
     PF_OK = 0,
@@ -137,6 +137,23 @@ typedef enum pf_lik_norm { PF_LIK_MEAN = 0, PF_LIK_SUM = 1 } pf_lik_norm;
  * accepted by the batch calls. */
 #define PF_FLAG_REJECTION (1u << 28)
 
+/* A filter whose workspace holds only its state: the device block (step
+ * count, origins, estimate), the particle positions and, with
+ * PF_FLAG_DIAGNOSTICS, the diagnostics -- 2 * elt bytes per particle plus
+ * 256 instead of about 5 * elt.  Its steps run through
+ * pf_step_static_scratch, whose per-step scratch (tile records and table,
+ * propagated positions, tile prefix sums) is the library's static device
+ * array, shared by every such filter on the device.  Accepted only with the
+ * default step (no PF_FLAG_NAIVE_*, PF_FLAG_METROPOLIS, PF_FLAG_GUMBEL_MAX or
+ * PF_FLAG_REJECTION) and only when that scratch fits PF_STATIC_SCRATCH_BYTES
+ * (N <= 2^20 in PF_F64, about 2.09 million in PF_F32, 3.1 million in PF_F16
+ * and PF_BF16); not accepted by the batch calls.  pf_step and the
+ * propagated positions of pf_export_step refuse such a filter. */
+#define PF_FLAG_STATE_ONLY (1u << 26)
+
+/* Size of the static step scratch (bytes per device). */
+#define PF_STATIC_SCRATCH_BYTES (24u * 1024u * 1024u + 64u * 1024u)
+
 typedef struct pf_params {
     uint32_t struct_size;  /* must be sizeof(pf_params) */
     int32_t dtype;         /* pf_dtype */
@@ -192,6 +209,25 @@ int pf_init(const pf_params* p, void* d_workspace, size_t workspace_bytes, void*
  * PF_ERR_INVALID_ARG (NULL frame, pitch < W), PF_ERR_HIP (the handle is then
  * poisoned), PF_ERR_STATE. */
 int pf_step(pf_filter* h, const uint8_t* d_frame, int64_t row_pitch);
+
+/* The step of pf_step for a filter created with PF_FLAG_STATE_ONLY, for
+ * callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): it allocates nothing and needs no
+ * scratch from the caller.  The scratch of the step is a static device array
+ * of PF_STATIC_SCRATCH_BYTES that the library holds on each device it runs
+ * on until the process ends (its address is looked up once per device, in
+ * pf_init of the first such filter on that device).  The step's kernels and
+ * arithmetic are those of pf_step: its results are bit-identical to pf_step
+ * on a filter with the same parameters, frames and step count.
+ * Every call on a device shares that device's array: calls that may overlap
+ * on one device (different streams without ordering between them) race and
+ * give wrong results; order them on one stream or synchronise.  Nothing of
+ * the array needs clearing between calls (each step writes every scratch
+ * word it reads).  Errors: PF_ERR_INVALID_ARG (not a PF_FLAG_STATE_ONLY
+ * filter, NULL frame, pitch < W, a stream on another device than the one the
+ * filter was created on), PF_ERR_HIP (the handle is then poisoned),
+ * PF_ERR_STATE. */
+int pf_step_static_scratch(pf_filter* h, const uint8_t* d_frame, int64_t row_pitch);
 
 /* The estimate of the latest step (x, y in pixels), or (x0, y0) before the
  * first step.  Waits for the filter's stream.  Errors: PF_ERR_STATE,

@@ -34,11 +34,14 @@ PF_FLAG_METROPOLIS = 1 << 16
 PF_METROPOLIS_STEPS_SHIFT = 18
 PF_FLAG_GUMBEL_MAX = 1 << 17
 PF_FLAG_REJECTION = 1 << 28
+PF_FLAG_STATE_ONLY = 1 << 26
+PF_STATIC_SCRATCH_BYTES = 24 * 1024 * 1024 + 64 * 1024
 
-PF_ABI_VERSION = 3
+PF_ABI_VERSION = 4
 
 # Every function the C header declares (checked against include/pf.h by the tests).
-EXPORTS = ("pf_workspace_bytes", "pf_init", "pf_step", "pf_estimate", "pf_estimate_async",
+EXPORTS = ("pf_workspace_bytes", "pf_init", "pf_step", "pf_step_static_scratch", "pf_estimate",
+           "pf_estimate_async",
            "pf_export", "pf_export_step", "pf_import", "pf_destroy", "pf_last_error",
            "pf_abi_version", "pf_profile_start", "pf_profile_read",
            "pf_batch_workspace_bytes", "pf_batch_init", "pf_batch_step", "pf_batch_estimates",
@@ -90,6 +93,7 @@ def lib():
         L.pf_workspace_bytes.argtypes = [P(pf_params), P(ctypes.c_size_t)]
         L.pf_init.argtypes = [P(pf_params), vp, ctypes.c_size_t, vp, P(vp)]
         L.pf_step.argtypes = [vp, vp, ctypes.c_int64]
+        L.pf_step_static_scratch.argtypes = [vp, vp, ctypes.c_int64]
         L.pf_estimate.argtypes = [vp, P(ctypes.c_double)]
         L.pf_estimate_async.argtypes = [vp, vp]
         L.pf_export.argtypes = [vp, vp, vp, vp, vp, P(ctypes.c_uint32)]
@@ -135,7 +139,8 @@ def make_params(n, width, height, dtype="f64", radius=5, x0=0.0, y0=0.0, drift=(
                 sigma=(5.0, 2.0), seed=0, stream_id=0, fg=228, bg=100, kappa=50.0,
                 lik_norm=PF_LIK_MEAN, diagnostics=False, naive_likelihood=False,
                 naive_resample=False, threads_a=None, threads_c=None,
-                metropolis_steps=0, gumbel_max=False, rejection_trials=0) -> pf_params:
+                metropolis_steps=0, gumbel_max=False, rejection_trials=0,
+                state_only=False) -> pf_params:
     """Parameters of one filter.  rejection_trials > 0 selects rejection
     resampling with at most that many trials per slot (a multiple of 64 up
     to 16320)."""
@@ -153,7 +158,8 @@ def make_params(n, width, height, dtype="f64", radius=5, x0=0.0, y0=0.0, drift=(
              | ((PF_FLAG_METROPOLIS | (int(metropolis_steps) << PF_METROPOLIS_STEPS_SHIFT))
                 if metropolis_steps else 0)
              | (PF_FLAG_GUMBEL_MAX if gumbel_max else 0)
-             | ((PF_FLAG_REJECTION | ((rj // 64) << PF_METROPOLIS_STEPS_SHIFT)) if rj else 0))
+             | ((PF_FLAG_REJECTION | ((rj // 64) << PF_METROPOLIS_STEPS_SHIFT)) if rj else 0)
+             | (PF_FLAG_STATE_ONLY if state_only else 0))
     return pf_params(ctypes.sizeof(pf_params), dt, int(n), int(width), int(height), int(radius),
                      int(fg), int(bg), int(lik_norm), float(kappa), float(x0), float(y0),
                      float(drift[0]), float(drift[1]), float(sigma[0]), float(sigma[1]),
@@ -178,6 +184,10 @@ def pf_init(p: pf_params, d_workspace: int, workspace_bytes: int, hip_stream: in
 
 def pf_step(h, d_frame: int, row_pitch: int):
     _check(lib().pf_step(h, ctypes.c_void_p(d_frame), int(row_pitch)))
+
+
+def pf_step_static_scratch(h, d_frame: int, row_pitch: int):
+    _check(lib().pf_step_static_scratch(h, ctypes.c_void_p(d_frame), int(row_pitch)))
 
 
 def pf_estimate(h):
@@ -318,7 +328,10 @@ class Filter:
         """frame: (H, W) uint8 CUDA tensor (row pitch from its stride)."""
         assert frame.dtype.itemsize == 1 and frame.dim() == 2 and frame.stride(1) == 1
         assert frame.is_cuda
-        pf_step(self.handle, frame.data_ptr(), frame.stride(0))
+        if self.params.flags & PF_FLAG_STATE_ONLY:
+            pf_step_static_scratch(self.handle, frame.data_ptr(), frame.stride(0))
+        else:
+            pf_step(self.handle, frame.data_ptr(), frame.stride(0))
 
     def estimate(self):
         return pf_estimate(self.handle)

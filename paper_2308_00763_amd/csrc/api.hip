@@ -26,6 +26,10 @@ struct pf_filter {
     uint32_t t;
     bool poisoned;
     pf_batch* owner;  // the batch this filter belongs to, or null
+    // PF_FLAG_STATE_ONLY: the device the filter was created on and the
+    // address of the static step scratch there
+    int device;
+    uint8_t* scratch;
     // per-pass timing (pf_profile_start / pf_profile_read)
     std::vector<hipEvent_t> prof_ev;  // kProfEv events per recorded step
     uint32_t prof_max, prof_used;
@@ -130,7 +134,8 @@ int check_params(const pf_params* p)
     if (p->sigma_x < 0 || p->sigma_y < 0) return fail(PF_ERR_INVALID_ARG, "sigma must be >= 0");
     const uint32_t known = PF_FLAG_DIAGNOSTICS | PF_FLAG_NAIVE_LIKELIHOOD | PF_FLAG_NAIVE_RESAMPLE |
                            (0xFu << PF_THREADS_A_SHIFT) | (0xFu << PF_THREADS_C_SHIFT) | PF_FLAG_METROPOLIS |
-                           (0xFFu << PF_METROPOLIS_STEPS_SHIFT) | PF_FLAG_GUMBEL_MAX | PF_FLAG_REJECTION;
+                           (0xFFu << PF_METROPOLIS_STEPS_SHIFT) | PF_FLAG_GUMBEL_MAX | PF_FLAG_REJECTION |
+                           PF_FLAG_STATE_ONLY;
     if (p->flags & ~known) return fail(PF_ERR_INVALID_ARG, "unknown flags 0x%x", p->flags);
     const uint32_t ta = (p->flags >> PF_THREADS_A_SHIFT) & 0xF, tc = (p->flags >> PF_THREADS_C_SHIFT) & 0xF;
     if (ta != 0 && (ta < 2 || ta > 4)) return fail(PF_ERR_INVALID_ARG, "pass A threads field %u outside {2, 3, 4}", ta);
@@ -142,6 +147,16 @@ int check_params(const pf_params* p)
         return fail(PF_ERR_INVALID_ARG, "Gumbel-max resampling takes at most 65536 particles");
     if (!(p->flags & (PF_FLAG_METROPOLIS | PF_FLAG_REJECTION)) && ((p->flags >> PF_METROPOLIS_STEPS_SHIFT) & 0xFFu))
         return fail(PF_ERR_INVALID_ARG, "Metropolis steps or rejection trials given without their resampler");
+    if (p->flags & PF_FLAG_STATE_ONLY) {
+        if (resamplers || (p->flags & PF_FLAG_NAIVE_LIKELIHOOD))
+            return fail(PF_ERR_INVALID_ARG, "PF_FLAG_STATE_ONLY takes only the default step");
+        const int nt = (int)((p->n_particles + kTile - 1) / kTile);
+        const size_t need = make_scratch_layout(*p, nt, (int64_t)nt * kTile).total;
+        if (need > PF_STATIC_SCRATCH_BYTES)
+            return fail(PF_ERR_INVALID_ARG, "PF_FLAG_STATE_ONLY: the step scratch of %lld particles needs %zu bytes, "
+                        "more than the static scratch's %u", (long long)p->n_particles, need,
+                        (unsigned)PF_STATIC_SCRATCH_BYTES);
+    }
     return PF_OK;
 }
 
@@ -231,15 +246,22 @@ void setup_filter(pf_filter* h, const pf_params& pr, uint8_t* ws, hipStream_t st
     a.denom = p->lik_norm == PF_LIK_MEAN ? p->kappa * (double)a.nd : p->kappa;
     a.beta = (float)(1.4426950408889634 / a.denom);
     a.blk = (DevBlock*)at(h, L.blk);
-    a.rec = at(h, L.rec);
-    a.tab = at(h, L.tab);
-    a.grec = at(h, L.grec);
-    a.gtab = at(h, L.gtab);
     a.sx = at(h, L.sx);
     a.sy = at(h, L.sy);
-    a.px = at(h, L.px);
-    a.py = at(h, L.py);
-    a.q = at(h, L.q);
+    h->device = -1;
+    h->scratch = nullptr;
+    if (p->flags & PF_FLAG_STATE_ONLY) {
+        // the step points these into the static scratch
+        a.rec = a.tab = a.grec = a.gtab = a.px = a.py = a.q = nullptr;
+    } else {
+        a.rec = at(h, L.rec);
+        a.tab = at(h, L.tab);
+        a.grec = at(h, L.grec);
+        a.gtab = at(h, L.gtab);
+        a.px = at(h, L.px);
+        a.py = at(h, L.py);
+        a.q = at(h, L.q);
+    }
     if (p->flags & PF_FLAG_DIAGNOSTICS) {
         a.dg_s = (int32_t*)at(h, L.dg_s);
         a.dg_w = (double*)at(h, L.dg_w);
@@ -316,7 +338,21 @@ int pf_init(const pf_params* p, void* d_workspace, size_t workspace_bytes, void*
     DevBlock b;
     double vx, vy;
     setup_filter(h, *p, (uint8_t*)d_workspace, (hipStream_t)hip_stream, &b, &vx, &vy);
-    hipError_t e = write_block(h, b);
+    hipError_t e = hipSuccess;
+    if (p->flags & PF_FLAG_STATE_ONLY) {
+        // set-up of the static step scratch on the stream's device, with that
+        // device current
+        int cur = 0;
+        e = hipGetDevice(&cur);
+        if (e == hipSuccess) e = hipStreamGetDevice(h->stream, &h->device);
+        if (e == hipSuccess && h->device != cur) e = hipSetDevice(h->device);
+        if (e == hipSuccess) e = static_scratch_setup(h->device, &h->scratch);
+        if (h->device >= 0 && h->device != cur) {
+            const hipError_t e2 = hipSetDevice(cur);
+            if (e == hipSuccess) e = e2;
+        }
+    }
+    if (e == hipSuccess) e = write_block(h, b);
     if (e == hipSuccess) e = launch_fill(p->dtype, h->args, vx, vy, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) {
@@ -331,6 +367,8 @@ int pf_init(const pf_params* p, void* d_workspace, size_t workspace_bytes, void*
 int pf_step(pf_filter* h, const uint8_t* d_frame, int64_t row_pitch)
 {
     if (int rc = live(h)) return rc;
+    if (h->p.flags & PF_FLAG_STATE_ONLY)
+        return fail(PF_ERR_INVALID_ARG, "a PF_FLAG_STATE_ONLY filter steps through pf_step_static_scratch");
     if (!d_frame) return fail(PF_ERR_INVALID_ARG, "frame is NULL");
     if (row_pitch < h->p.width) return fail(PF_ERR_INVALID_ARG, "row_pitch %lld < width %d", (long long)row_pitch, h->p.width);
     if (h->t == UINT32_MAX) return fail(PF_ERR_INVALID_ARG, "step counter exhausted");
@@ -354,6 +392,39 @@ int pf_step(pf_filter* h, const uint8_t* d_frame, int64_t row_pitch)
     }
     if (e == hipSuccess && a.dg_w) e = launch_diag_weights(h->p.dtype, a, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "pf_step launch");
+    h->t = a.t;
+    return ok();
+}
+
+int pf_step_static_scratch(pf_filter* h, const uint8_t* d_frame, int64_t row_pitch)
+{
+    if (int rc = live(h)) return rc;
+    if (!(h->p.flags & PF_FLAG_STATE_ONLY) || !h->scratch)
+        return fail(PF_ERR_INVALID_ARG, "pf_step_static_scratch needs a filter created with PF_FLAG_STATE_ONLY");
+    if (!d_frame) return fail(PF_ERR_INVALID_ARG, "frame is NULL");
+    if (row_pitch < h->p.width) return fail(PF_ERR_INVALID_ARG, "row_pitch %lld < width %d", (long long)row_pitch, h->p.width);
+    if (h->t == UINT32_MAX) return fail(PF_ERR_INVALID_ARG, "step counter exhausted");
+    int dev = -1;
+    hipError_t e = hipStreamGetDevice(h->stream, &dev);
+    if (e != hipSuccess) return hip_fail(h, e, "pf_step_static_scratch");
+    if (dev != h->device)
+        return fail(PF_ERR_INVALID_ARG, "the filter's stream runs on device %d, its scratch was set up on %d", dev,
+                    h->device);
+    const ScratchLayout S = make_scratch_layout(h->p, h->L.ntiles, h->L.n_pad);
+    StepArgs a = h->args;
+    a.frame = d_frame;
+    a.pitch = row_pitch;
+    a.t = h->t + 1;
+    a.rec = h->scratch + S.rec;
+    a.tab = h->scratch + S.tab;
+    a.grec = h->scratch + S.grec;
+    a.gtab = h->scratch + S.gtab;
+    a.px = h->scratch + S.px;
+    a.py = h->scratch + S.py;
+    a.q = h->scratch + S.q;
+    e = launch_step(h->p.dtype, a, h->stream);
+    if (e == hipSuccess && a.dg_w) e = launch_diag_weights(h->p.dtype, a, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "pf_step_static_scratch launch");
     h->t = a.t;
     return ok();
 }
@@ -434,6 +505,8 @@ int pf_export_step(pf_filter* h, double* x_prop, double* y_prop, int32_t* disk_s
     const DevBlock b = read_block(h, &e);
     if (e != hipSuccess) return hip_fail(h, e, "pf_export_step");
     if (b.t == 0) return fail(PF_ERR_INVALID_ARG, "no step taken yet");
+    if ((x_prop || y_prop) && (h->p.flags & PF_FLAG_STATE_ONLY))
+        return fail(PF_ERR_INVALID_ARG, "a PF_FLAG_STATE_ONLY filter keeps no propagated positions");
     if (int rc = export_positions(h, h->L.px, h->L.py, x_prop, y_prop, b)) return rc;
     if (disk_sum) {
         e = hipMemcpyAsync(disk_sum, at(h, h->L.dg_s), (size_t)h->p.n_particles * 4, hipMemcpyDeviceToHost,

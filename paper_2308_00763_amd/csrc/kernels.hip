@@ -28,6 +28,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "philox.hpp"
@@ -2256,6 +2257,40 @@ hipError_t launch_fill(int dtype, const StepArgs& a, double vx, double vy, hipSt
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+}  // namespace pf
+
+// ---------------------------------------------------------------------------
+// Static step scratch of the filters created with PF_FLAG_STATE_ONLY: the
+// tile records and table, group records and table, propagated positions and
+// tile prefix sums of one step, for callers that cannot allocate.  Each
+// device holds its own copy at its own address; the array's name is only a
+// host-side stand-in, so host code uses the address that
+// hipGetSymbolAddress returns on each device, never the name.
+static __device__ __align__(256) uint8_t scratch[PF_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t* g_scratch_addr[kMaxScratchDevices];
+}  // namespace
+
+namespace pf {
+
+hipError_t static_scratch_setup(int device, uint8_t** out)
+{
+    if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p || ((uintptr_t)p & 255) != 0) return hipErrorInvalidSymbol;
+        g_scratch_addr[device] = static_cast<uint8_t*>(p);
+    }
+    *out = g_scratch_addr[device];
+    return hipSuccess;
 }
 
 }  // namespace pf

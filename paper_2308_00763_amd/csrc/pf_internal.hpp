@@ -112,6 +112,37 @@ struct Layout {
 
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// Step scratch of a filter: the sections one step writes before it reads
+// them (tile records and table, group records and table, propagated
+// positions, tile prefix sums); offsets relative to the scratch's base.
+struct ScratchLayout {
+    size_t rec, tab, grec, gtab, px, py, q, total;
+};
+
+inline ScratchLayout make_scratch_layout(const pf_params& p, int ntiles, int64_t n_pad)
+{
+    ScratchLayout S{};
+    const size_t elt = (size_t)elt_of(p.dtype);
+    const size_t rec = p.dtype == PF_F64 ? sizeof(TileRec64) : sizeof(TileRec32);
+    const size_t tab = p.dtype == PF_F64 ? sizeof(TileTab64) : sizeof(TileTab32);
+    const size_t qel = p.dtype == PF_F64 ? 8 : 4;
+    const size_t ngroups = ((size_t)ntiles + 1023) / 1024;
+    size_t o = 0;
+    S.rec = o; o = align256(o + rec * (size_t)ntiles);
+    S.tab = o; o = align256(o + tab * (size_t)(ntiles + 1));
+    S.grec = o; o = align256(o + 32 * ngroups);
+    S.gtab = o; o = align256(o + 32 * ngroups);
+    S.px = o; o = align256(o + elt * (size_t)n_pad);
+    S.py = o; o = align256(o + elt * (size_t)n_pad);
+    S.q = o; o = align256(o + qel * (size_t)n_pad);
+    S.total = o;
+    return S;
+}
+
+// Workspace layout: the block and the state (positions), then the step
+// scratch (absent with PF_FLAG_STATE_ONLY: those offsets are 0 and the step
+// points them into the static scratch), then the optional diagnostics and
+// variant buffers.
 inline Layout make_layout(const pf_params& p)
 {
     Layout L{};
@@ -120,21 +151,24 @@ inline Layout make_layout(const pf_params& p)
     L.ntiles = (int)((L.n + L.tile - 1) / L.tile);
     L.n_pad = (int64_t)L.ntiles * L.tile;
     const size_t elt = (size_t)elt_of(p.dtype);
-    const size_t rec = p.dtype == PF_F64 ? sizeof(TileRec64) : sizeof(TileRec32);
-    const size_t tab = p.dtype == PF_F64 ? sizeof(TileTab64) : sizeof(TileTab32);
     const size_t qel = p.dtype == PF_F64 ? 8 : 4;
     size_t o = 0;
     L.blk = o; o += 256;
-    L.rec = o; o = align256(o + rec * (size_t)L.ntiles);
-    L.tab = o; o = align256(o + tab * (size_t)(L.ntiles + 1));
-    const size_t ngroups = ((size_t)L.ntiles + 1023) / 1024;
-    L.grec = o; o = align256(o + 32 * ngroups);
-    L.gtab = o; o = align256(o + 32 * ngroups);
     L.sx = o; o = align256(o + elt * (size_t)L.n_pad);
     L.sy = o; o = align256(o + elt * (size_t)L.n_pad);
-    L.px = o; o = align256(o + elt * (size_t)L.n_pad);
-    L.py = o; o = align256(o + elt * (size_t)L.n_pad);
-    L.q = o; o = align256(o + qel * (size_t)L.n_pad);
+    if (p.flags & PF_FLAG_STATE_ONLY) {
+        L.rec = L.tab = L.grec = L.gtab = L.px = L.py = L.q = 0;
+    } else {
+        const ScratchLayout S = make_scratch_layout(p, L.ntiles, L.n_pad);
+        L.rec = o + S.rec;
+        L.tab = o + S.tab;
+        L.grec = o + S.grec;
+        L.gtab = o + S.gtab;
+        L.px = o + S.px;
+        L.py = o + S.py;
+        L.q = o + S.q;
+        o += S.total;
+    }
     if (p.flags & PF_FLAG_DIAGNOSTICS) {
         L.dg_s = o; o = align256(o + 4 * (size_t)L.n_pad);
         L.dg_w = o; o = align256(o + 8 * (size_t)L.n_pad);
@@ -220,6 +254,12 @@ struct BatchArgs {
 struct KTiming {
     hipEvent_t start = nullptr, stop = nullptr;
 };
+
+// The static step scratch of filters created with PF_FLAG_STATE_ONLY
+// (kernels.hip): PF_STATIC_SCRATCH_BYTES on every device.  With `device`
+// current, static_scratch_setup looks up the array's address on that device
+// (once per device; later calls return the address found then).
+hipError_t static_scratch_setup(int device, uint8_t** out);
 
 // Host-side launchers (kernels.hip).  launch_step = launch_pass_a,
 // launch_combine, launch_pass_c on the same stream.

@@ -114,6 +114,44 @@ def test_batch_null_handles_are_rejected_without_a_device():
                            ctypes.byref(out)) == pf.PF_ERR_WORKSPACE
 
 
+def test_state_only_workspace_holds_only_the_state():
+    # block + two position planes of N_pad elements (tiles of 1024)
+    for dt, elt in (("f64", 8), ("f32", 4), ("f16", 2), ("bf16", 2)):
+        for n in (1, 1000, 1025, 1 << 20):
+            pad = -(-n // 1024) * 1024
+            p = pf.make_params(n, 1024, 1024, dt, state_only=True)
+            assert pf.pf_workspace_bytes(p) == 256 + 2 * (-(-elt * pad // 256) * 256)
+            assert pf.pf_workspace_bytes(p) < pf.pf_workspace_bytes(pf.make_params(n, 1024, 1024, dt)) / 2
+    src = open(HEADER).read()
+    assert "#define PF_STATIC_SCRATCH_BYTES (24u * 1024u * 1024u + 64u * 1024u)" in src
+    assert pf.PF_STATIC_SCRATCH_BYTES == 24 * 1024 * 1024 + 64 * 1024
+
+
+@pytest.mark.parametrize("dt,n_ok,n_bad", [("f64", 1 << 20, (1 << 20) + 1),
+                                           ("f32", (1 << 21) - 5 * 1024, 1 << 21),
+                                           ("f16", 3_100_000, 3_200_000)])
+def test_state_only_size_limit(dt, n_ok, n_bad):
+    pf.pf_workspace_bytes(pf.make_params(n_ok, 1024, 1024, dt, state_only=True))
+    with pytest.raises(pf.PfError) as ei:
+        pf.pf_workspace_bytes(pf.make_params(n_bad, 1024, 1024, dt, state_only=True))
+    assert ei.value.code == pf.PF_ERR_INVALID_ARG and "static scratch" in pf.pf_last_error()
+
+
+@pytest.mark.parametrize("variant", [dict(naive_likelihood=True), dict(naive_resample=True),
+                                     dict(metropolis_steps=8), dict(gumbel_max=True),
+                                     dict(rejection_trials=64)])
+def test_state_only_takes_only_the_default_step(variant):
+    with pytest.raises(pf.PfError) as ei:
+        pf.pf_workspace_bytes(pf.make_params(1000, 128, 128, "f16", state_only=True, **variant))
+    assert ei.value.code == pf.PF_ERR_INVALID_ARG
+
+
+def test_state_only_filters_are_not_batched():
+    ps = [pf.make_params(1000, 128, 128, "f16", state_only=True)]
+    with pytest.raises(pf.PfError):
+        pf.pf_batch_workspace_bytes(ps)
+
+
 def test_rejection_trials_field():
     # rejection resampling keeps at most 64 v trials per slot (v in the
     # shared field), and excludes every other resampler
