@@ -73,7 +73,7 @@ def step_bound_s(dtype, radius, n):
     return n * max(step_slots(dtype, radius) / PEAK_LANE_OPS, STATE_BYTES[dtype] / PEAK_HBM)
 
 
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "pass_a_f16_disk1024_n1m_traffic.md")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "step_traffic_f16_disk1024_n1m.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2308_00763_amd", "csrc", f)
                   for f in ("kernels.hip", "philox.hpp", "wave.hpp", "pf_internal.hpp")]
 
@@ -473,51 +473,56 @@ RESAMPLER_CASES = [("systematic", {}), ("metropolis B=8", dict(metropolis_steps=
 def run_resampler_bias(pf, torch, pfsynth, runs=8, steps=10, dtype="f16"):
     """Bias and speed of the resamplers at 2^24 particles (512x512, radius 8,
     noise sigma 8).  Speed: ms per step and resampling kernel time on the
-    video.  Bias: the particles of a real step (after three systematic steps)
-    are frozen (no drift, no noise) and resampled `runs` times with fresh
-    random streams; the offspring counts averaged over the runs are compared
-    with N w (w the step's normalised weights, the same in every run): TV =
-    1/2 sum |mean count / N - w|.  An unbiased multinomial resampler's TV from
-    its noise alone is about 1/2 sum sqrt(2 w (1 - w) / (pi N runs)) (the
-    "multinomial_floor"); systematic resampling's counts vary less."""
+    video.  Bias: a cloud of particles around the object (normal offsets of
+    3 px per axis, seeded) is frozen (no drift, no noise) and resampled
+    `runs` times with fresh random streams, so the normalised weights w are
+    the same in every run; offspring counts averaged over the runs are
+    compared with N w, per pixel cell (particles in one cell share their
+    weight): TV = 1/2 sum over cells |mean offspring share - weight share|.
+    An unbiased multinomial resampler's TV from its noise alone is about
+    1/2 sum sqrt(2 W (1 - W) / (pi N runs)) over the cells' weights W (the
+    "multinomial_floor"); systematic resampling's counts vary less, a biased
+    resampler's TV stays above the floor however many runs."""
     wl = pfsynth.WORKLOADS["disk512_r8_n16m"]
     n = wl.n_particles
     vid = pfsynth.workload_video(wl, frames=steps + 12)
     fr = torch.from_numpy(vid.frames).to("cuda:0")
     x0, y0 = vid.centres[0]
-    out = {"workload": f"{wl.name}: N={n}, radius {wl.radius}, noise sigma {wl.noise_sigma}, {dtype}",
+    cx, cy = vid.centres[4]
+    rng = np.random.Generator(np.random.PCG64(11))
+    xs = cx + 3.0 * rng.standard_normal(n)
+    ys = cy + 3.0 * rng.standard_normal(n)
+    cell = (np.floor(ys + 0.5).astype(np.int64) * 4096 + np.floor(xs + 0.5).astype(np.int64))
+    _, cell_id = np.unique(cell, return_inverse=True)
+    out = {"workload": f"{wl.name}: N={n}, radius {wl.radius}, noise sigma {wl.noise_sigma}, {dtype}; "
+                       f"frozen cloud of N(0, 3^2) offsets around the object for the bias",
            "runs": runs, "rows": []}
-    # a state to freeze: three systematic steps on the video
-    f = pf.Filter(pf.make_params(n, wl.width, wl.height, dtype, radius=wl.radius, x0=x0, y0=y0,
-                                 drift=wl.drift, sigma=wl.sigma, seed=wl.filter_seed))
-    for t in (1, 2, 3):
-        f.step(fr[t])
-    st = f.export()
-    f.close()
     floor = None
     for name, var in RESAMPLER_CASES:
+        log(f"[bench] resampler bias: {name}")
         secs, _ = run_mode(pf, torch, fr, vid.centres, wl, dtype, steps, 1, False, **var)
         _, prof = run_mode(pf, torch, fr, vid.centres, wl, dtype, steps, 1, True, **var)
         g = pf.Filter(pf.make_params(n, wl.width, wl.height, dtype, radius=wl.radius, x0=x0, y0=y0,
                                      drift=(0.0, 0.0), sigma=(0.0, 0.0), seed=wl.filter_seed,
                                      diagnostics=True, **var))
-        mean = np.zeros(n)
+        counts = np.zeros(n)
         w = None
         for r in range(runs):
-            g.load(st["x"], st["y"], 3 + r)
+            g.load(xs, ys, 3 + r)
             g.step(fr[4])
             e = g.export()
-            mean += np.bincount(e["anc"], minlength=n)
+            counts += np.bincount(e["anc"], minlength=n)
             w = e["w"] if w is None else w
         g.close()
-        mean /= runs
-        tv = 0.5 * float(np.sum(np.abs(mean / n - w)))
+        W = np.bincount(cell_id, weights=w)
+        share = np.bincount(cell_id, weights=counts) / (n * runs)
+        tv = 0.5 * float(np.sum(np.abs(share - W)))
         if floor is None:
-            floor = 0.5 * float(np.sum(np.sqrt(2 * w * (1 - w) / (np.pi * n * runs))))
+            floor = 0.5 * float(np.sum(np.sqrt(2 * W * (1 - W) / (np.pi * n * runs))))
         out["rows"].append(dict(resampler=name, ms_per_step=1e3 * secs / steps,
-                                resample_us=1e3 * prof[2] / prof[3],
-                                offspring_tv=tv))
+                                resample_us=1e3 * prof[2] / prof[3], cell_tv=tv))
     out["multinomial_floor"] = floor
+    out["cells"] = int(cell_id.max() + 1)
     return out
 
 
