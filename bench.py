@@ -410,6 +410,9 @@ ABLATION = [
     ("naive resampling, 1024 threads", dict(naive_resample=True, threads_c=1024)),
     ("naive likelihood + resampling, 128 threads",
      dict(naive_likelihood=True, naive_resample=True, threads_c=128)),
+    ("unpacked half propagation (FP16 only)", dict(naive_half=True)),
+    ("naive half step: unpacked half + division per particle in the resampler (FP16 only)",
+     dict(naive_half=True, naive_resample=True)),
     ("pass A 128 threads (8 particles each)", dict(threads_a=128)),
     ("pass A 256 threads (4 particles each)", dict(threads_a=256)),
     ("pass A 512 threads (2 particles each)", dict(threads_a=512)),
@@ -428,6 +431,8 @@ def run_ablation(pf, torch, frames_dev, centres, w, steps, warmup, dtypes=("f16"
     for dt in dtypes:
         rows = {}
         for name, var in ABLATION:
+            if var.get("naive_half") and dt != "f16":
+                continue
             secs, _ = run_mode(pf, torch, frames_dev, centres, w, dt, steps, warmup, False, **var)
             _, prof = run_mode(pf, torch, frames_dev, centres, w, dt, steps, warmup, True, **var)
             a_ms, m_ms, c_ms, n = prof

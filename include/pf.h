@@ -91,6 +91,15 @@ typedef enum pf_lik_norm { PF_LIK_MEAN = 0, PF_LIK_SUM = 1 } pf_lik_norm;
  *                                     (default 256 for both). */
 #define PF_FLAG_NAIVE_LIKELIHOOD 2u
 #define PF_FLAG_NAIVE_RESAMPLE 4u
+/*   PF_FLAG_NAIVE_HALF       -- PF_F16 only, with the default pass-A size:
+ *       the propagation runs one particle at a time in scalar half
+ *       arithmetic (each normal cast to half on its own, a scalar half
+ *       multiply-add and add per axis) instead of two particles per packed
+ *       register; the same roundings, so the same results bit for bit.
+ *       With PF_FLAG_NAIVE_RESAMPLE it is the straightforward half step the
+ *       paper starts from (Sec. 4, pipeline-optimisation paragraph): no
+ *       packing, and a division per particle and casts in the resampler. */
+#define PF_FLAG_NAIVE_HALF (1u << 29)
 #define PF_THREADS_A_SHIFT 8
 #define PF_THREADS_C_SHIFT 12
 

@@ -28,6 +28,7 @@ PF_LIK_MEAN, PF_LIK_SUM = 0, 1
 PF_FLAG_DIAGNOSTICS = 1
 PF_FLAG_NAIVE_LIKELIHOOD = 2
 PF_FLAG_NAIVE_RESAMPLE = 4
+PF_FLAG_NAIVE_HALF = 1 << 29
 PF_THREADS_A_SHIFT = 8
 PF_THREADS_C_SHIFT = 12
 PF_FLAG_METROPOLIS = 1 << 16
@@ -140,7 +141,7 @@ def make_params(n, width, height, dtype="f64", radius=5, x0=0.0, y0=0.0, drift=(
                 lik_norm=PF_LIK_MEAN, diagnostics=False, naive_likelihood=False,
                 naive_resample=False, threads_a=None, threads_c=None,
                 metropolis_steps=0, gumbel_max=False, rejection_trials=0,
-                state_only=False) -> pf_params:
+                state_only=False, naive_half=False) -> pf_params:
     """Parameters of one filter.  rejection_trials > 0 selects rejection
     resampling with at most that many trials per slot (a multiple of 64 up
     to 16320)."""
@@ -159,7 +160,8 @@ def make_params(n, width, height, dtype="f64", radius=5, x0=0.0, y0=0.0, drift=(
                 if metropolis_steps else 0)
              | (PF_FLAG_GUMBEL_MAX if gumbel_max else 0)
              | ((PF_FLAG_REJECTION | ((rj // 64) << PF_METROPOLIS_STEPS_SHIFT)) if rj else 0)
-             | (PF_FLAG_STATE_ONLY if state_only else 0))
+             | (PF_FLAG_STATE_ONLY if state_only else 0)
+             | (PF_FLAG_NAIVE_HALF if naive_half else 0))
     return pf_params(ctypes.sizeof(pf_params), dt, int(n), int(width), int(height), int(radius),
                      int(fg), int(bg), int(lik_norm), float(kappa), float(x0), float(y0),
                      float(drift[0]), float(drift[1]), float(sigma[0]), float(sigma[1]),

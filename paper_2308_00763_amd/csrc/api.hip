@@ -135,7 +135,7 @@ int check_params(const pf_params* p)
     const uint32_t known = PF_FLAG_DIAGNOSTICS | PF_FLAG_NAIVE_LIKELIHOOD | PF_FLAG_NAIVE_RESAMPLE |
                            (0xFu << PF_THREADS_A_SHIFT) | (0xFu << PF_THREADS_C_SHIFT) | PF_FLAG_METROPOLIS |
                            (0xFFu << PF_METROPOLIS_STEPS_SHIFT) | PF_FLAG_GUMBEL_MAX | PF_FLAG_REJECTION |
-                           PF_FLAG_STATE_ONLY;
+                           PF_FLAG_STATE_ONLY | PF_FLAG_NAIVE_HALF;
     if (p->flags & ~known) return fail(PF_ERR_INVALID_ARG, "unknown flags 0x%x", p->flags);
     const uint32_t ta = (p->flags >> PF_THREADS_A_SHIFT) & 0xF, tc = (p->flags >> PF_THREADS_C_SHIFT) & 0xF;
     if (ta != 0 && (ta < 2 || ta > 4)) return fail(PF_ERR_INVALID_ARG, "pass A threads field %u outside {2, 3, 4}", ta);
@@ -147,8 +147,13 @@ int check_params(const pf_params* p)
         return fail(PF_ERR_INVALID_ARG, "Gumbel-max resampling takes at most 65536 particles");
     if (!(p->flags & (PF_FLAG_METROPOLIS | PF_FLAG_REJECTION)) && ((p->flags >> PF_METROPOLIS_STEPS_SHIFT) & 0xFFu))
         return fail(PF_ERR_INVALID_ARG, "Metropolis steps or rejection trials given without their resampler");
+    if ((p->flags & PF_FLAG_NAIVE_HALF) && p->dtype != PF_F16)
+        return fail(PF_ERR_INVALID_ARG, "PF_FLAG_NAIVE_HALF applies to PF_F16 only");
+    if ((p->flags & PF_FLAG_NAIVE_HALF) && ((p->flags >> PF_THREADS_A_SHIFT) & 0xF) != 0 &&
+        ((p->flags >> PF_THREADS_A_SHIFT) & 0xF) != 3)
+        return fail(PF_ERR_INVALID_ARG, "PF_FLAG_NAIVE_HALF runs pass A with 256 threads only");
     if (p->flags & PF_FLAG_STATE_ONLY) {
-        if (resamplers || (p->flags & PF_FLAG_NAIVE_LIKELIHOOD))
+        if (resamplers || (p->flags & (PF_FLAG_NAIVE_LIKELIHOOD | PF_FLAG_NAIVE_HALF)))
             return fail(PF_ERR_INVALID_ARG, "PF_FLAG_STATE_ONLY takes only the default step");
         const int nt = (int)((p->n_particles + kTile - 1) / kTile);
         const size_t need = make_scratch_layout(*p, nt, (int64_t)nt * kTile).total;
@@ -273,6 +278,7 @@ void setup_filter(pf_filter* h, const pf_params& pr, uint8_t* ws, hipStream_t st
     }
     a.naive_lik = (p->flags & PF_FLAG_NAIVE_LIKELIHOOD) ? 1 : 0;
     a.naive_res = (p->flags & PF_FLAG_NAIVE_RESAMPLE) ? 1 : 0;
+    a.naive_half = (p->flags & PF_FLAG_NAIVE_HALF) ? 1 : 0;
     a.threads_a = threads_of((p->flags >> PF_THREADS_A_SHIFT) & 0xF, kBlockA);
     a.threads_c = threads_of((p->flags >> PF_THREADS_C_SHIFT) & 0xF, 0);
     a.cdf = a.naive_res ? at(h, L.cdf) : nullptr;

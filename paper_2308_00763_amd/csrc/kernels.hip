@@ -160,14 +160,17 @@ __device__ __forceinline__ int disk_sum_global(const uint8_t* frame, int64_t pit
 // |offset| <= 1/2, where 16-bit formats are densest.  The pixel of a particle
 // is c + floor(offset) + [frac(offset) >= 1/2], computed exactly in float.
 
-// Half-up rounding of a reduced-precision offset to its pixel: exact in float
-// for every input (floor and the fraction v - floor(v) are exact).
+// Half-up rounding of a reduced-precision offset to its pixel, clamped to
+// [lo, hi]: exact in float for every input (floor and the fraction
+// v - floor(v) are exact).  The offset is first clamped to the integers
+// [lo - origin, hi - origin], which gives the clamped pixel directly: below
+// lo - origin the cell is lo either way, and at the upper bound the fraction
+// is 0.
 __device__ __forceinline__ int offset_cell(float v, int origin, int lo, int hi)
 {
-    v = __builtin_amdgcn_fmed3f(v, (float)(lo - origin) - 1.0f, (float)(hi - origin) + 1.0f);
+    v = __builtin_amdgcn_fmed3f(v, (float)(lo - origin), (float)(hi - origin));
     const float fl = floorf(v);
-    const int c = origin + (int)fl + ((v - fl) >= 0.5f ? 1 : 0);
-    return min(max(c, lo), hi);
+    return origin + (int)fl + ((v - fl) >= 0.5f ? 1 : 0);
 }
 
 template <int DT>
@@ -313,14 +316,43 @@ struct ModeT<PF_F16> {
             y[i] = yy.x; y[i + 1] = yy.y;
         }
     }
+    // The same propagation one particle at a time in scalar half arithmetic
+    // (each normal cast to half on its own, then a scalar fused multiply-add
+    // and add per axis): the straightforward unpacked form, kept to measure
+    // what packing two particles per register gains.  Written as explicit
+    // instructions so that the compiler cannot pack them again; every
+    // operation rounds as its packed lane does, so the results are the same
+    // bit for bit.
+    template <int PPT>
+    static __device__ __forceinline__ void propagate_scalar(Val* x, Val* y, const Prop& pr, const StepArgs& a,
+                                                            int k0, uint32_t t)
+    {
+        const _Float16 dx = pr.dx.x, dy = pr.dy.x, sx = pr.sx.x, sy = pr.sy.x;
+#pragma unroll
+        for (int i = 0; i < PPT; ++i) {
+            const u32x4 w = philox4x32_10((uint32_t)(k0 + i), t, a.stream_id, 0u, a.key0, a.key1);
+            float zx, zy;
+            normal_pair_f32(w, zx, zy);
+            _Float16 hx, hy, mx, my, ox, oy;
+            __asm__("v_cvt_f16_f32 %0, %1" : "=v"(hx) : "v"(zx));
+            __asm__("v_cvt_f16_f32 %0, %1" : "=v"(hy) : "v"(zy));
+            __asm__("v_fma_f16 %0, %1, %2, %3" : "=v"(mx) : "v"(sx), "v"(hx), "v"(dx));
+            __asm__("v_fma_f16 %0, %1, %2, %3" : "=v"(my) : "v"(sy), "v"(hy), "v"(dy));
+            __asm__("v_add_f16 %0, %1, %2" : "=v"(ox) : "v"(x[i]), "v"(mx));
+            __asm__("v_add_f16 %0, %1, %2" : "=v"(oy) : "v"(y[i]), "v"(my));
+            x[i] = ox;
+            y[i] = oy;
+        }
+    }
     // A half's value in float, plus one half, is exact (at most 18
     // significant bits), so floor(v + 1/2) is the half-up rounding that
-    // offset_cell forms in general.
+    // offset_cell forms in general; clamping v + 1/2 to the integers
+    // [lo - origin, hi - origin] before the floor clamps the cell to
+    // [lo, hi] (floor commutes with a clamp to integers).
     static __device__ __forceinline__ int cell(Val v, int origin, int lo, int hi)
     {
-        const float f = __builtin_amdgcn_fmed3f((float)v, (float)(lo - origin) - 1.0f, (float)(hi - origin) + 1.0f);
-        const int c = origin + (int)floorf(f + 0.5f);
-        return min(max(c, lo), hi);
+        const float f = __builtin_amdgcn_fmed3f((float)v + 0.5f, (float)(lo - origin), (float)(hi - origin));
+        return origin + (int)floorf(f);
     }
 };
 
@@ -411,9 +443,10 @@ struct PassALds {
 
 // Pass A of tile `tile` of the filter described by `a`, PPT particles per
 // thread (kTile / PPT threads).
-template <int DT, int RC, int PPT>
+template <int DT, int RC, int PPT, bool SCALAR_HALF = false>
 __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALds& lds)
 {
+    static_assert(!SCALAR_HALF || DT == PF_F16, "the unpacked propagation is a half-precision variant");
     using M = ModeT<DT>;
     constexpr int kBlockA = kTile / PPT;
     constexpr int kWavesA = kBlockA / 64;
@@ -443,7 +476,8 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
     typename M::Val x[PPT], y[PPT];
     M::template load<PPT>(a.sx, k0, x);
     M::template load<PPT>(a.sy, k0, y);
-    M::template propagate<PPT>(x, y, pr, a, k0, tn);
+    if constexpr (SCALAR_HALF) M::template propagate_scalar<PPT>(x, y, pr, a, k0, tn);
+    else M::template propagate<PPT>(x, y, pr, a, k0, tn);
     M::template store<PPT>(a.px, k0, x);
     M::template store<PPT>(a.py, k0, y);
 
@@ -669,11 +703,11 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
     }
 }
 
-template <int DT, int RC, int PPT>
+template <int DT, int RC, int PPT, bool SCALAR_HALF = false>
 __global__ __launch_bounds__(kTile / PPT) void pass_a_kernel(StepArgs a)
 {
     __shared__ PassALds lds;
-    pass_a_tile<DT, RC, PPT>(a, blockIdx.x, lds);
+    pass_a_tile<DT, RC, PPT, SCALAR_HALF>(a, blockIdx.x, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -2040,6 +2074,13 @@ static hipError_t launch_pass_a_t(const StepArgs& a, hipStream_t s, const KTimin
         return launch1(pass_a_kernel<DT, 0, 2>, g, dim3(512), s, tm, a);
     }
     const dim3 blk(kBlockA);
+    if constexpr (DT == PF_F16) {
+        if (a.naive_half) {  // the unpacked half propagation
+            if (a.r == 5) return launch1(pass_a_kernel<DT, 5, kPPT, true>, g, blk, s, tm, a);
+            if (a.r == 8) return launch1(pass_a_kernel<DT, 8, kPPT, true>, g, blk, s, tm, a);
+            return launch1(pass_a_kernel<DT, 0, kPPT, true>, g, blk, s, tm, a);
+        }
+    }
     if (a.r == 5) return launch1(pass_a_kernel<DT, 5, kPPT>, g, blk, s, tm, a);
     if (a.r == 8) return launch1(pass_a_kernel<DT, 8, kPPT>, g, blk, s, tm, a);
     return launch1(pass_a_kernel<DT, 0, kPPT>, g, blk, s, tm, a);

@@ -218,6 +218,7 @@ struct StepArgs {
     // implementation variants (measurement of the straightforward step)
     int32_t naive_lik;  // disk sums read every pixel from the frame
     int32_t naive_res;  // normalised CDF + per-slot binary search instead of pass C
+    int32_t naive_half; // FP16: propagation one particle at a time in scalar half arithmetic
     int32_t threads_a;  // pass A threads per tile: 128, 256 (default) or 512
     int32_t threads_c;  // pass C / naive resampler threads per workgroup: 64 .. 1024 (0: by tile count)
     void* cdf;          // naive resampler: normalised cumulative weights

@@ -102,6 +102,25 @@ def test_variants_with_the_same_arithmetic_are_bit_identical(variant, dtype):
         assert np.array_equal(g0[key], g1[key]), key
 
 
+@pytest.mark.parametrize("n", [5000, 70001, (1 << 20) + 3])
+def test_unpacked_half_propagation_is_bit_identical(n):
+    # the paper's straightforward half step propagates one particle at a
+    # time; each scalar operation rounds as its lane of the packed one does
+    e0, g0 = _free_run("f16", n)
+    e1, g1 = _free_run("f16", n, naive_half=True)
+    assert np.array_equal(e0, e1)
+    for key in ("x", "y", "w", "anc"):
+        assert np.array_equal(g0[key], g1[key]), key
+
+
+def test_naive_half_step_resamples_as_fp64_does():
+    # unpacked half with the straightforward resampler (a division per
+    # particle and casts): the step the paper's optimisation starts from
+    w, vid = _vid()
+    for got, gs, est, ref in _teacher_forced("f16", 5000, vid, 3, naive_half=True, naive_resample=True):
+        check_reduced_step(got, gs, est, ref["u0"], ref["denom"], 5000, "f16", naive=True)
+
+
 @pytest.mark.parametrize("threads_c", [64, 1024])
 @pytest.mark.parametrize("dtype", ["f64", "f16"])
 def test_streaming_pass_c_sizes_are_bit_identical_over_many_tiles(threads_c, dtype):
@@ -124,6 +143,9 @@ def test_variant_flags_are_checked():
         pf.make_params(1000, 128, 128, threads_c=96)
     with pytest.raises(pf.PfError):
         pf.Batch([pf.make_params(1000, 128, 128, "f16", naive_resample=True)])
+    for bad in (dict(dtype="f32", naive_half=True), dict(dtype="f16", naive_half=True, threads_a=128)):
+        with pytest.raises(pf.PfError):
+            pf.pf_workspace_bytes(pf.make_params(1000, 128, 128, **bad))
     base = pf.pf_workspace_bytes(pf.make_params(1 << 20, 128, 128, "f16"))
     naive = pf.pf_workspace_bytes(pf.make_params(1 << 20, 128, 128, "f16", naive_resample=True))
     assert naive - base >= 4 << 20
