@@ -686,6 +686,9 @@ def main():
                     help="skip the naive-vs-optimised and workgroup-size runs")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="measured seconds of the serving workload after a 10 s warm-up (0 to skip)")
+    ap.add_argument("--variant", default="", metavar="KEY=VAL,...",
+                    help="implementation variant for the timed modes, as make_params keywords "
+                         "(e.g. naive_half=1,naive_resample=1)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (five times), "
                          "to scale hardware byte counters")
@@ -717,15 +720,19 @@ def main():
     vid = pfsynth.workload_video(w)
     frames_dev = torch.from_numpy(vid.frames).to("cuda:0")
     modes = args.modes.split(",")
+    variant = {}
+    for kv in filter(None, args.variant.split(",")):
+        key, val = kv.split("=")
+        variant[key] = int(val)
 
     res = {}
     for dt in modes:
         log(f"[bench] timing {dt}: warmup {args.warmup}, steps {args.steps}")
         secs, _ = run_mode(pf, torch, frames_dev, vid.centres, w, dt, args.steps, args.warmup,
-                           profile=False)
+                           profile=False, **variant)
         # the same steps again, with HIP events around every kernel
         psecs, prof = run_mode(pf, torch, frames_dev, vid.centres, w, dt, args.steps, args.warmup,
-                               profile=True)
+                               profile=True, **variant)
         a_ms, m_ms, c_ms, n = prof
         res[dt] = dict(seconds=secs, ms_per_step=1e3 * secs / args.steps,
                        updates_per_s=w.n_particles * args.steps / secs,
@@ -788,6 +795,8 @@ def main():
         "roofline": roof,
         "kernel_source_sha256": kernel_source_hash(),
     }
+    if variant:
+        out["variant"] = variant
     if "f64" in res:
         out["speedup_f16_vs_f64"] = res["f64"]["seconds"] / res.get("f16", res["f64"])["seconds"]
     if "f32" in res and "f16" in res:
