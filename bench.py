@@ -168,6 +168,34 @@ def run_mode(pf, torch, frames_dev, centres, w, dtype, steps, warmup, profile, *
     return (t1 - t0), prof
 
 
+def warm_gpu(pf, torch, frames_dev, centres, w, dtype, seconds, **variant):
+    """Step one filter untimed for about `seconds` so that the GPU's clocks
+    have ramped up before the first timed mode (the first mode timed in a
+    fresh process otherwise runs its pass A about 12 % slower than later
+    modes).  Returns the steps run."""
+    import ctypes
+    T = frames_dev.shape[0]
+    x0, y0 = centres[0]
+    p = pf.make_params(w.n_particles, w.width, w.height, dtype, radius=w.radius, x0=x0, y0=y0,
+                       drift=w.drift, sigma=w.sigma, seed=w.filter_seed, **variant)
+    f = pf.Filter(p)
+    lib = pf.lib()
+    pitch = int(frames_dev.stride(1))
+    base = int(frames_dev.data_ptr())
+    fstride = int(frames_dev.stride(0))
+    ptrs = [ctypes.c_void_p(base + t * fstride) for t in range(T)]
+    n = 0
+    t_end = time.perf_counter() + seconds
+    while time.perf_counter() < t_end:
+        for _ in range(32):
+            n += 1
+            if lib.pf_step(f.handle, ptrs[(n - 1) % (T - 1) + 1], pitch):
+                raise pf.PfError(-1, pf.pf_last_error())
+        torch.cuda.synchronize()
+    f.close()
+    return n
+
+
 def track(pf, frames_dev, centres, w, dtype, nsteps, **variant):
     """Free-running estimates over frames 1..nsteps (untimed)."""
     x0, y0 = centres[0]
@@ -566,8 +594,13 @@ def run_accuracy(pf, torch, pfsynth, modes):
         r = dict(rms_vs_truth_px=float(np.sqrt(np.mean(np.sum((e - vid.centres) ** 2, axis=1)))),
                  max_vs_truth_px=float(np.max(np.hypot(*(e - vid.centres).T))))
         if "f64" in tr:
+            rms = float(np.sqrt(np.mean(np.sum((e - tr["f64"]) ** 2, axis=1))))
+            r["rms_vs_f64_px"] = rms
             r["max_vs_f64_px"] = float(np.max(np.hypot(*(e - tr["f64"]).T)))
             r["rounded_equal_f64"] = float(np.mean(np.all(np.rint(e) == np.rint(tr["f64"]), axis=1)))
+            # the accuracy bound of the reduced modes: RMS distance to the FP64
+            # track at most 0.5 px (False: the mode misses it on this video)
+            r["within_0p5px_of_f64"] = rms <= 0.5
         res[dt] = r
     return dict(workload=f"{w.name}: {w.width}x{w.height}, {w.frames} frames, bounce off y = 0 at frame 47, "
                          f"N={w.n_particles}", modes=res)
@@ -684,7 +717,9 @@ def main():
                     help="streams of the batched fleet workload (0 to skip)")
     ap.add_argument("--no-ablation", action="store_true",
                     help="skip the naive-vs-optimised and workgroup-size runs")
-    ap.add_argument("--serve-seconds", type=float, default=20.0,
+    ap.add_argument("--gpu-warmup-s", type=float, default=1.0,
+                    help="seconds of untimed steps before the first timed mode (clock ramp-up)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="measured seconds of the serving workload after a 10 s warm-up (0 to skip)")
     ap.add_argument("--variant", default="", metavar="KEY=VAL,...",
                     help="implementation variant for the timed modes, as make_params keywords "
@@ -695,7 +730,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the filter step is single-GPU "
-              "(sharding across GPUs is described in DESIGN.md, not built)", file=sys.stderr)
+              "(sharding a filter across GPUs is not built)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -725,6 +760,9 @@ def main():
         key, val = kv.split("=")
         variant[key] = int(val)
 
+    if args.gpu_warmup_s > 0:
+        nw = warm_gpu(pf, torch, frames_dev, vid.centres, w, modes[0], args.gpu_warmup_s, **variant)
+        log(f"[bench] GPU warm-up: {nw} untimed {modes[0]} steps in {args.gpu_warmup_s:g} s")
     res = {}
     for dt in modes:
         log(f"[bench] timing {dt}: warmup {args.warmup}, steps {args.steps}")
@@ -782,6 +820,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "gpu_warmup_s": args.gpu_warmup_s,
         "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
