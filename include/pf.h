@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define PF_ABI_VERSION 4
+#define PF_ABI_VERSION 5
 
 typedef enum pf_status {
     PF_OK = 0,
@@ -159,6 +159,19 @@ typedef enum pf_lik_norm { PF_LIK_MEAN = 0, PF_LIK_SUM = 1 } pf_lik_norm;
  * and PF_BF16); not accepted by the batch calls.  pf_step and the
  * propagated positions of pf_export_step refuse such a filter. */
 #define PF_FLAG_STATE_ONLY (1u << 26)
+
+/* Workgroup sizes from the tuning table (the threads-per-block study of the
+ * paper's Sec. 5, kept per GPU): pf_init, pf_batch_init and pf_batch_reinit
+ * replace both threads fields with the entry that the table installed in the
+ * library (pf_tune_set, pf_tune_load) holds for the stream's GPU
+ * architecture, the dtype and the particle-count bucket ceil(log2 N), as
+ * pf_tune_lookup resolves it; the defaults when the table has nothing for
+ * that architecture and dtype.  Both threads fields must be 0, and
+ * PF_FLAG_NAIVE_HALF (which runs pass A at its default size) is refused with
+ * it.  pf_launch_config reports the sizes a filter resolved to.  The sizes
+ * change results only through pass A's, which fixes the order of the
+ * tile-local prefix sums. */
+#define PF_FLAG_TUNED (1u << 30)
 
 /* Size of the static step scratch (bytes per device). */
 #define PF_STATIC_SCRATCH_BYTES (24u * 1024u * 1024u + 64u * 1024u)
@@ -295,14 +308,57 @@ int pf_profile_start(pf_filter* h, uint32_t max_steps);
 int pf_profile_read(pf_filter* h, double out_ms[3], uint32_t* steps);
 
 /* ------------------------------------------------------------------------
+ * Tuning table: (GPU architecture, dtype, particle-count bucket) -> (pass-A
+ * threads, pass-C threads), read by PF_FLAG_TUNED.  One table per process,
+ * shared by every device and thread (the calls take a lock); entries persist
+ * as a text file that pf_tune_load reads (the package ships one measured on
+ * its target GPU).
+ */
+
+/* Install entry (arch, dtype, bucket), replacing one with the same key.
+ * arch: architecture name without feature suffixes ("gfx950"), 1 to 31
+ * characters of [A-Za-z0-9_]; bucket b in [0, 28] covers the particle
+ * counts N with ceil(log2 N) = b; threads_a in {0, 128, 256, 512} and
+ * threads_c in {0, 64, 128, 256, 512, 1024}, 0 meaning the default size.
+ * Errors: PF_ERR_INVALID_ARG (nothing changes). */
+int pf_tune_set(const char* arch, int32_t dtype, int32_t bucket, int32_t threads_a, int32_t threads_c);
+
+/* Read a table file (text, one entry a line: `arch dtype bucket threads_a
+ * threads_c`, dtype one of f64 f32 f16 bf16; blank lines and anything after
+ * '#' ignored) and install its entries as pf_tune_set does.  The whole file
+ * is checked first: a bad line installs nothing.  *out_entries (may be NULL)
+ * receives the number of entries read.  Errors: PF_ERR_INVALID_ARG (file
+ * unreadable, or the text names the first bad line). */
+int pf_tune_load(const char* path, int32_t* out_entries);
+
+/* Remove every entry. */
+int pf_tune_clear(void);
+
+/* The sizes PF_FLAG_TUNED resolves to for architecture `arch`, `dtype` and n
+ * particles: the entry of bucket ceil(log2 n), else the entry of the nearest
+ * bucket with the same arch and dtype (the smaller bucket on a tie), else 0
+ * and 0 (the defaults).  Host only.  Errors: PF_ERR_INVALID_ARG. */
+int pf_tune_lookup(const char* arch, int32_t dtype, int64_t n, int32_t* threads_a, int32_t* threads_c);
+
+/* The workgroup sizes filter h launches with: pass A threads (128, 256 or
+ * 512) and pass C threads (the naive resampler's with
+ * PF_FLAG_NAIVE_RESAMPLE; for a batch member, the batch's pass C size,
+ * which it uses for every member).  Errors: PF_ERR_INVALID_ARG. */
+int pf_launch_config(pf_filter* h, int32_t* threads_a, int32_t* threads_c);
+
+/* ------------------------------------------------------------------------
  * Batches: many independent filters (one per video stream, say), each running
  * the step of pf_step (paper Sec. 2 and Sec. 4) on its own frame, advanced
  * together with one launch per pass.  The filters of a batch share the dtype;
  * everything else in their parameters may differ (N, frame size, radius,
- * seeds, motion model).  A filter's results in a batch are bit-identical to
- * the same filter run alone through pf_step with the same parameters, frames
- * and step count: each of its workgroups runs the single-filter code on that
- * filter's data, whatever else the batch holds.
+ * seeds, motion model, pass-A size).  A filter's results in a batch are
+ * bit-identical to the same filter run alone through pf_step with the same
+ * parameters, frames and step count: each of its workgroups runs the
+ * single-filter code on that filter's data, whatever else the batch holds.
+ * Members may take PF_FLAG_DIAGNOSTICS, PF_FLAG_TUNED and the threads fields
+ * (no other variant): pass A runs each member at its own size, one launch
+ * per size present; pass C runs every member at the batch's size (the pass-C
+ * size changes no result).
  */
 typedef struct pf_batch pf_batch;
 
@@ -316,7 +372,7 @@ int pf_batch_workspace_bytes(const pf_params* ps, int32_t n, size_t* out_bytes);
  * owned workspace (device memory, 256-byte aligned, at least
  * pf_batch_workspace_bytes() bytes; the batch must not outlive it).  The
  * batch allocates pinned host memory for staging each step's plan (32 bytes
- * per filter plus 4 bytes per tile, four copies: three for eager steps, one
+ * per filter plus 8 bytes per tile, four copies: three for eager steps, one
  * for a captured step) and frees it in pf_batch_destroy.  All device work is ordered on `hip_stream`; waits for
  * the initialisation to finish.  Errors: PF_ERR_INVALID_ARG,
  * PF_ERR_WORKSPACE, PF_ERR_HIP. */

@@ -15,6 +15,10 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpf.so")
+# Workgroup sizes measured per (GPU architecture, dtype, particle-count
+# bucket) by tune.py; installed in the library when it is loaded, read by
+# filters created with PF_FLAG_TUNED.
+TUNE_TABLE = os.path.join(_HERE, "tune_table.txt")
 
 PF_OK = 0
 PF_ERR_INVALID_ARG = 1
@@ -36,9 +40,10 @@ PF_METROPOLIS_STEPS_SHIFT = 18
 PF_FLAG_GUMBEL_MAX = 1 << 17
 PF_FLAG_REJECTION = 1 << 28
 PF_FLAG_STATE_ONLY = 1 << 26
+PF_FLAG_TUNED = 1 << 30
 PF_STATIC_SCRATCH_BYTES = 24 * 1024 * 1024 + 64 * 1024
 
-PF_ABI_VERSION = 4
+PF_ABI_VERSION = 5
 
 # Every function the C header declares (checked against include/pf.h by the tests).
 EXPORTS = ("pf_workspace_bytes", "pf_init", "pf_step", "pf_step_static_scratch", "pf_estimate",
@@ -46,7 +51,8 @@ EXPORTS = ("pf_workspace_bytes", "pf_init", "pf_step", "pf_step_static_scratch",
            "pf_export", "pf_export_step", "pf_import", "pf_destroy", "pf_last_error",
            "pf_abi_version", "pf_profile_start", "pf_profile_read",
            "pf_batch_workspace_bytes", "pf_batch_init", "pf_batch_step", "pf_batch_estimates",
-           "pf_batch_estimates_async", "pf_batch_reinit", "pf_batch_filter", "pf_batch_destroy")
+           "pf_batch_estimates_async", "pf_batch_reinit", "pf_batch_filter", "pf_batch_destroy",
+           "pf_tune_set", "pf_tune_load", "pf_tune_clear", "pf_tune_lookup", "pf_launch_config")
 
 
 class PfError(RuntimeError):
@@ -114,9 +120,19 @@ def lib():
         L.pf_batch_reinit.argtypes = [vp, ctypes.c_int32, P(pf_params)]
         L.pf_batch_filter.argtypes = [vp, ctypes.c_int32, P(vp)]
         L.pf_batch_destroy.argtypes = [vp]
+        i32 = ctypes.c_int32
+        L.pf_tune_set.argtypes = [ctypes.c_char_p, i32, i32, i32, i32]
+        L.pf_tune_load.argtypes = [ctypes.c_char_p, P(i32)]
+        L.pf_tune_clear.argtypes = []
+        L.pf_tune_lookup.argtypes = [ctypes.c_char_p, i32, ctypes.c_int64, P(i32), P(i32)]
+        L.pf_launch_config.argtypes = [vp, P(i32), P(i32)]
         for name in EXPORTS:
             if name != "pf_last_error":
                 getattr(L, name).restype = ctypes.c_int
+        if os.path.exists(TUNE_TABLE):
+            n = i32()
+            if L.pf_tune_load(TUNE_TABLE.encode(), ctypes.byref(n)) != PF_OK:
+                raise PfError(PF_ERR_INVALID_ARG, L.pf_last_error().decode())
         _lib = L
     return _lib
 
@@ -141,10 +157,11 @@ def make_params(n, width, height, dtype="f64", radius=5, x0=0.0, y0=0.0, drift=(
                 lik_norm=PF_LIK_MEAN, diagnostics=False, naive_likelihood=False,
                 naive_resample=False, threads_a=None, threads_c=None,
                 metropolis_steps=0, gumbel_max=False, rejection_trials=0,
-                state_only=False, naive_half=False) -> pf_params:
+                state_only=False, naive_half=False, tuned=False) -> pf_params:
     """Parameters of one filter.  rejection_trials > 0 selects rejection
     resampling with at most that many trials per slot (a multiple of 64 up
-    to 16320)."""
+    to 16320).  tuned=True takes the workgroup sizes from the library's
+    tuning table (threads_a and threads_c must then be None)."""
     dt = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
     if not 0 <= int(metropolis_steps) <= 255:
         raise ValueError(f"metropolis_steps must be in [0, 255], got {metropolis_steps}")
@@ -161,7 +178,8 @@ def make_params(n, width, height, dtype="f64", radius=5, x0=0.0, y0=0.0, drift=(
              | (PF_FLAG_GUMBEL_MAX if gumbel_max else 0)
              | ((PF_FLAG_REJECTION | ((rj // 64) << PF_METROPOLIS_STEPS_SHIFT)) if rj else 0)
              | (PF_FLAG_STATE_ONLY if state_only else 0)
-             | (PF_FLAG_NAIVE_HALF if naive_half else 0))
+             | (PF_FLAG_NAIVE_HALF if naive_half else 0)
+             | (PF_FLAG_TUNED if tuned else 0))
     return pf_params(ctypes.sizeof(pf_params), dt, int(n), int(width), int(height), int(radius),
                      int(fg), int(bg), int(lik_norm), float(kappa), float(x0), float(y0),
                      float(drift[0]), float(drift[1]), float(sigma[0]), float(sigma[1]),
@@ -312,6 +330,34 @@ def pf_batch_destroy(b):
 # ---------------------------------------------------------------------------
 # Convenience wrapper: workspace and stream from PyTorch.
 
+def pf_tune_set(arch: str, dtype, bucket: int, threads_a: int, threads_c: int):
+    dt = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+    _check(lib().pf_tune_set(arch.encode(), dt, int(bucket), int(threads_a), int(threads_c)))
+
+
+def pf_tune_load(path: str) -> int:
+    n = ctypes.c_int32()
+    _check(lib().pf_tune_load(path.encode(), ctypes.byref(n)))
+    return n.value
+
+
+def pf_tune_clear():
+    _check(lib().pf_tune_clear())
+
+
+def pf_tune_lookup(arch: str, dtype, n: int):
+    dt = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+    ta, tc = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().pf_tune_lookup(arch.encode(), dt, int(n), ctypes.byref(ta), ctypes.byref(tc)))
+    return ta.value, tc.value
+
+
+def pf_launch_config(h):
+    ta, tc = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().pf_launch_config(h, ctypes.byref(ta), ctypes.byref(tc)))
+    return ta.value, tc.value
+
+
 class Filter:
     """One particle filter with a torch-allocated workspace on `device`."""
 
@@ -337,6 +383,10 @@ class Filter:
 
     def estimate(self):
         return pf_estimate(self.handle)
+
+    def launch_config(self):
+        """(pass A threads, pass C threads) the filter launches with."""
+        return pf_launch_config(self.handle)
 
     def export(self):
         return pf_export(self.handle, self.n, self.diagnostics)

@@ -3,10 +3,12 @@
 #include <hip/hip_runtime.h>
 
 #include <math.h>
+#include <stdlib.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -37,10 +39,13 @@ struct pf_filter {
 
 // A batch of filters in one workspace:
 //   [StepArgs x n][BatchEntry x n][tile map: int32 x total tiles]
-//   [estimates: 2n doubles][filter 0 layout][filter 1 layout]...
+//   [the same two for a captured step][estimates: 2n doubles]
+//   [pass-A tile lists: int32 x total tiles, twice]
+//   [filter 0 layout][filter 1 layout]...
 // Each step uploads, from a ring of pinned host buffers, the entries of the
 // stepped filters (grouped by combine class) and, when the set of stepped
-// filters changed, the map from grid tile to entry.
+// filters changed, the map from grid tile to entry and, when the stepped
+// filters have several pass-A sizes, the grid tiles of each size.
 constexpr int kRing = 3;
 
 struct pf_batch {
@@ -55,9 +60,12 @@ struct pf_batch {
     int32_t* d_tile_entry;
     BatchEntry* d_g_entries;          // plan of a captured step (replays write only these)
     int32_t* d_g_tile_entry;
+    int32_t* d_a_tiles;               // pass-A tile lists (members of several pass-A sizes)
+    int32_t* d_g_a_tiles;
     double* d_est;
     std::vector<pf_filter*> f;
     std::vector<int> cls;            // combine class of every filter
+    std::vector<int> ta;             // pass-A threads of every filter
     std::vector<size_t> slot_bytes;  // workspace share of every filter
     std::vector<int> slot_tiles;     // tiles of every filter at creation (the most it may have)
     std::vector<StepArgs> args_host; // host copy of the filters' StepArgs
@@ -135,11 +143,15 @@ int check_params(const pf_params* p)
     const uint32_t known = PF_FLAG_DIAGNOSTICS | PF_FLAG_NAIVE_LIKELIHOOD | PF_FLAG_NAIVE_RESAMPLE |
                            (0xFu << PF_THREADS_A_SHIFT) | (0xFu << PF_THREADS_C_SHIFT) | PF_FLAG_METROPOLIS |
                            (0xFFu << PF_METROPOLIS_STEPS_SHIFT) | PF_FLAG_GUMBEL_MAX | PF_FLAG_REJECTION |
-                           PF_FLAG_STATE_ONLY | PF_FLAG_NAIVE_HALF;
+                           PF_FLAG_STATE_ONLY | PF_FLAG_NAIVE_HALF | PF_FLAG_TUNED;
     if (p->flags & ~known) return fail(PF_ERR_INVALID_ARG, "unknown flags 0x%x", p->flags);
     const uint32_t ta = (p->flags >> PF_THREADS_A_SHIFT) & 0xF, tc = (p->flags >> PF_THREADS_C_SHIFT) & 0xF;
     if (ta != 0 && (ta < 2 || ta > 4)) return fail(PF_ERR_INVALID_ARG, "pass A threads field %u outside {2, 3, 4}", ta);
     if (tc > 5) return fail(PF_ERR_INVALID_ARG, "pass C threads field %u outside [0, 5]", tc);
+    if ((p->flags & PF_FLAG_TUNED) && (ta || tc))
+        return fail(PF_ERR_INVALID_ARG, "PF_FLAG_TUNED takes both threads fields from the tuning table: give them as 0");
+    if ((p->flags & PF_FLAG_TUNED) && (p->flags & PF_FLAG_NAIVE_HALF))
+        return fail(PF_ERR_INVALID_ARG, "PF_FLAG_NAIVE_HALF runs pass A at its default size: not with PF_FLAG_TUNED");
     const int resamplers = !!(p->flags & PF_FLAG_METROPOLIS) + !!(p->flags & PF_FLAG_NAIVE_RESAMPLE) +
                            !!(p->flags & PF_FLAG_GUMBEL_MAX) + !!(p->flags & PF_FLAG_REJECTION);
     if (resamplers > 1) return fail(PF_ERR_INVALID_ARG, "at most one resampler variant may be chosen");
@@ -166,6 +178,124 @@ int check_params(const pf_params* p)
 }
 
 int threads_of(uint32_t field, int dflt) { return field == 0 ? dflt : 1 << (field + 5); }
+
+// ---------------------------------------------------------------------------
+// Tuning table: (architecture, dtype, bucket) -> (pass-A threads, pass-C
+// threads), one per process, guarded by g_tune_mu.
+
+struct TuneEntry {
+    std::string arch;
+    int32_t dtype, bucket, ta, tc;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+
+constexpr int kMaxBucket = 28;
+
+int bucket_of(int64_t n)
+{
+    int b = 0;
+    while (b < 62 && (int64_t(1) << b) < n) ++b;
+    return b;
+}
+
+bool arch_ok(const char* a)
+{
+    if (!a) return false;
+    const size_t len = strlen(a);
+    if (len < 1 || len > 31) return false;
+    for (size_t i = 0; i < len; ++i) {
+        const char c = a[i];
+        if (!((c >= 'a' && c <= 'z') || (c >= 'A' && c <= 'Z') || (c >= '0' && c <= '9') || c == '_')) return false;
+    }
+    return true;
+}
+
+// The threads field of a size (0 for the default), or -1.
+int field_of(int threads, bool pass_a)
+{
+    if (threads == 0) return 0;
+    for (int f = pass_a ? 2 : 1; f <= (pass_a ? 4 : 5); ++f)
+        if (threads == (1 << (f + 5))) return f;
+    return -1;
+}
+
+int check_tune_entry(const char* arch, int32_t dtype, int32_t bucket, int32_t ta, int32_t tc)
+{
+    if (!arch_ok(arch)) return fail(PF_ERR_INVALID_ARG, "architecture name must be 1-31 characters of [A-Za-z0-9_]");
+    if (dtype < PF_F64 || dtype > PF_BF16) return fail(PF_ERR_INVALID_ARG, "bad dtype %d", dtype);
+    if (bucket < 0 || bucket > kMaxBucket) return fail(PF_ERR_INVALID_ARG, "bucket %d outside [0, %d]", bucket, kMaxBucket);
+    if (field_of(ta, true) < 0) return fail(PF_ERR_INVALID_ARG, "pass A threads %d not in {0, 128, 256, 512}", ta);
+    if (field_of(tc, false) < 0)
+        return fail(PF_ERR_INVALID_ARG, "pass C threads %d not in {0, 64, 128, 256, 512, 1024}", tc);
+    return PF_OK;
+}
+
+void tune_put(const TuneEntry& en)  // caller holds g_tune_mu
+{
+    for (TuneEntry& o : g_tune)
+        if (o.arch == en.arch && o.dtype == en.dtype && o.bucket == en.bucket) {
+            o = en;
+            return;
+        }
+    g_tune.push_back(en);
+}
+
+void tune_find(const char* arch, int32_t dtype, int64_t n, int32_t* ta, int32_t* tc)
+{
+    const int b = bucket_of(n);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const TuneEntry* best = nullptr;
+    for (const TuneEntry& o : g_tune) {
+        if (o.arch != arch || o.dtype != dtype) continue;
+        const int d = std::abs(o.bucket - b), bd = best ? std::abs(best->bucket - b) : 1 << 30;
+        if (d < bd || (d == bd && best && o.bucket < best->bucket)) best = &o;
+    }
+    *ta = best ? best->ta : 0;
+    *tc = best ? best->tc : 0;
+}
+
+// Architecture name of a device without feature suffixes, cached per device.
+int device_arch(int dev, std::string* out)
+{
+    static std::mutex mu;
+    static std::vector<std::string> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    if (dev < 0) return fail(PF_ERR_INVALID_ARG, "bad device %d", dev);
+    if ((size_t)dev < cache.size() && !cache[(size_t)dev].empty()) {
+        *out = cache[(size_t)dev];
+        return PF_OK;
+    }
+    hipDeviceProp_t prop;
+    const hipError_t e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return fail(PF_ERR_HIP, "hipGetDeviceProperties: %s", hipGetErrorString(e));
+    std::string a(prop.gcnArchName);
+    const size_t colon = a.find(':');
+    if (colon != std::string::npos) a.resize(colon);
+    if ((size_t)dev >= cache.size()) cache.resize((size_t)dev + 1);
+    cache[(size_t)dev] = a;
+    *out = a;
+    return PF_OK;
+}
+
+// `p` with PF_FLAG_TUNED replaced by the threads fields of the table entry
+// for the stream's device (unchanged without the flag).
+int resolve_tuned(const pf_params* p, hipStream_t s, pf_params* out)
+{
+    *out = *p;
+    if (!(p->flags & PF_FLAG_TUNED)) return PF_OK;
+    int dev = -1;
+    const hipError_t e = hipStreamGetDevice(s, &dev);
+    if (e != hipSuccess) return fail(PF_ERR_HIP, "hipStreamGetDevice: %s", hipGetErrorString(e));
+    std::string arch;
+    if (int rc = device_arch(dev, &arch)) return rc;
+    int32_t ta = 0, tc = 0;
+    tune_find(arch.c_str(), p->dtype, p->n_particles, &ta, &tc);
+    const uint32_t fields = (0xFu << PF_THREADS_A_SHIFT) | (0xFu << PF_THREADS_C_SHIFT);
+    out->flags = (p->flags & ~(PF_FLAG_TUNED | fields)) | ((uint32_t)field_of(ta, true) << PF_THREADS_A_SHIFT) |
+                 ((uint32_t)field_of(tc, false) << PF_THREADS_C_SHIFT);
+    return PF_OK;
+}
 
 int live(pf_filter* h)
 {
@@ -320,6 +450,91 @@ int pf_abi_version(void) { return PF_ABI_VERSION; }
 
 const char* pf_last_error(void) { return g_err.c_str(); }
 
+int pf_tune_set(const char* arch, int32_t dtype, int32_t bucket, int32_t threads_a, int32_t threads_c)
+{
+    if (int rc = check_tune_entry(arch, dtype, bucket, threads_a, threads_c)) return rc;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_put(TuneEntry{arch, dtype, bucket, threads_a, threads_c});
+    return ok();
+}
+
+int pf_tune_load(const char* path, int32_t* out_entries)
+{
+    if (!path) return fail(PF_ERR_INVALID_ARG, "path is NULL");
+    FILE* f = fopen(path, "r");
+    if (!f) return fail(PF_ERR_INVALID_ARG, "cannot open tuning table %s", path);
+    std::vector<TuneEntry> got;
+    char line[512];
+    int ln = 0, rc = PF_OK;
+    while (rc == PF_OK && fgets(line, sizeof line, f)) {
+        ++ln;
+        if (!strchr(line, '\n') && !feof(f)) {
+            rc = fail(PF_ERR_INVALID_ARG, "%s:%d: line longer than %zu characters", path, ln, sizeof line - 2);
+            break;
+        }
+        if (char* hash = strchr(line, '#')) *hash = '\0';
+        char arch[64], dt[16], extra[8];
+        int bucket = 0, ta = 0, tc = 0;
+        const int got_n = sscanf(line, "%63s %15s %d %d %d %7s", arch, dt, &bucket, &ta, &tc, extra);
+        if (got_n <= 0) continue;  // blank
+        if (got_n != 5) {
+            rc = fail(PF_ERR_INVALID_ARG, "%s:%d: expected `arch dtype bucket threads_a threads_c`", path, ln);
+            break;
+        }
+        const int dtype = !strcmp(dt, "f64") ? PF_F64 : !strcmp(dt, "f32") ? PF_F32 : !strcmp(dt, "f16") ? PF_F16
+                        : !strcmp(dt, "bf16") ? PF_BF16 : -1;
+        if (dtype < 0) {
+            rc = fail(PF_ERR_INVALID_ARG, "%s:%d: dtype %s is not one of f64 f32 f16 bf16", path, ln, dt);
+            break;
+        }
+        if (check_tune_entry(arch, dtype, bucket, ta, tc)) {
+            rc = fail(PF_ERR_INVALID_ARG, "%s:%d: %s", path, ln, g_err.c_str());
+            break;
+        }
+        got.push_back(TuneEntry{arch, dtype, bucket, ta, tc});
+    }
+    if (rc == PF_OK && ferror(f)) rc = fail(PF_ERR_INVALID_ARG, "error reading %s", path);
+    fclose(f);
+    if (rc != PF_OK) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (const TuneEntry& en : got) tune_put(en);
+    }
+    if (out_entries) *out_entries = (int32_t)got.size();
+    return ok();
+}
+
+int pf_tune_clear(void)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+    return ok();
+}
+
+int pf_tune_lookup(const char* arch, int32_t dtype, int64_t n, int32_t* threads_a, int32_t* threads_c)
+{
+    if (!arch_ok(arch)) return fail(PF_ERR_INVALID_ARG, "architecture name must be 1-31 characters of [A-Za-z0-9_]");
+    if (dtype < PF_F64 || dtype > PF_BF16) return fail(PF_ERR_INVALID_ARG, "bad dtype %d", dtype);
+    if (n < 1) return fail(PF_ERR_INVALID_ARG, "n %lld < 1", (long long)n);
+    if (!threads_a || !threads_c) return fail(PF_ERR_INVALID_ARG, "output is NULL");
+    tune_find(arch, dtype, n, threads_a, threads_c);
+    return ok();
+}
+
+int pf_launch_config(pf_filter* h, int32_t* threads_a, int32_t* threads_c)
+{
+    if (!h) return fail(PF_ERR_INVALID_ARG, "handle is NULL");
+    if (!threads_a || !threads_c) return fail(PF_ERR_INVALID_ARG, "output is NULL");
+    *threads_a = h->args.threads_a;
+    if (h->owner)
+        *threads_c = pass_c_threads(h->p.dtype, 1 << 30);
+    else if (h->args.threads_c)
+        *threads_c = h->args.threads_c;
+    else
+        *threads_c = h->args.naive_res ? 256 : pass_c_threads(h->p.dtype, h->L.ntiles);
+    return ok();
+}
+
 int pf_workspace_bytes(const pf_params* p, size_t* out_bytes)
 {
     if (int rc = check_params(p)) return rc;
@@ -328,11 +543,14 @@ int pf_workspace_bytes(const pf_params* p, size_t* out_bytes)
     return ok();
 }
 
-int pf_init(const pf_params* p, void* d_workspace, size_t workspace_bytes, void* hip_stream, pf_filter** out)
+int pf_init(const pf_params* p_in, void* d_workspace, size_t workspace_bytes, void* hip_stream, pf_filter** out)
 {
-    if (int rc = check_params(p)) return rc;
+    if (int rc = check_params(p_in)) return rc;
     if (!out) return fail(PF_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
+    pf_params tuned;
+    if (int rc = resolve_tuned(p_in, (hipStream_t)hip_stream, &tuned)) return rc;
+    const pf_params* p = &tuned;
     if (!d_workspace) return fail(PF_ERR_INVALID_ARG, "workspace is NULL");
     if (((uintptr_t)d_workspace & 255) != 0) return fail(PF_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
     const Layout L = make_layout(*p);
@@ -628,9 +846,13 @@ int pf_destroy(pf_filter* h)
 // Batches.
 
 struct BatchLayout {
-    size_t args, entries, tile_entry, g_entries, g_tile_entry, est, filters, total;
+    size_t args, entries, tile_entry, g_entries, g_tile_entry, est, a_tiles, g_a_tiles, filters, total;
     int64_t tiles;
 };
+
+// Flags a batch member may carry: diagnostics and the workgroup sizes.
+constexpr uint32_t kBatchFlags =
+    PF_FLAG_DIAGNOSTICS | PF_FLAG_TUNED | (0xFu << PF_THREADS_A_SHIFT) | (0xFu << PF_THREADS_C_SHIFT);
 
 static int check_batch(const pf_params* ps, int32_t n, BatchLayout* bl, std::vector<size_t>* foff)
 {
@@ -642,7 +864,7 @@ static int check_batch(const pf_params* ps, int32_t n, BatchLayout* bl, std::vec
     for (int32_t k = 0; k < n; ++k) {
         if (check_params(&ps[k])) return fail(PF_ERR_INVALID_ARG, "filter %d: %s", k, g_err.c_str());
         if (ps[k].dtype != ps[0].dtype) return fail(PF_ERR_INVALID_ARG, "filter %d: dtype differs from filter 0", k);
-        if (ps[k].flags & ~PF_FLAG_DIAGNOSTICS)
+        if (ps[k].flags & ~kBatchFlags)
             return fail(PF_ERR_INVALID_ARG, "filter %d: implementation variants are not batched", k);
         const Layout L = make_layout(ps[k]);
         if (foff) (*foff)[k] = fbytes;
@@ -657,6 +879,8 @@ static int check_batch(const pf_params* ps, int32_t n, BatchLayout* bl, std::vec
     bl->g_entries = o; o = align256(o + sizeof(BatchEntry) * (size_t)n);  // captured steps' plan
     bl->g_tile_entry = o; o = align256(o + 4 * (size_t)tiles);
     bl->est = o; o = align256(o + 16 * (size_t)n);
+    bl->a_tiles = o; o = align256(o + 4 * (size_t)tiles);
+    bl->g_a_tiles = o; o = align256(o + 4 * (size_t)tiles);
     bl->filters = o; o += fbytes;
     bl->total = o;
     bl->tiles = tiles;
@@ -720,6 +944,8 @@ int pf_batch_init(const pf_params* ps, int32_t n, void* d_workspace, size_t work
     b->d_tile_entry = (int32_t*)(b->ws + bl.tile_entry);
     b->d_g_entries = (BatchEntry*)(b->ws + bl.g_entries);
     b->d_g_tile_entry = (int32_t*)(b->ws + bl.g_tile_entry);
+    b->d_a_tiles = (int32_t*)(b->ws + bl.a_tiles);
+    b->d_g_a_tiles = (int32_t*)(b->ws + bl.g_a_tiles);
     b->d_est = (double*)(b->ws + bl.est);
     b->map_valid = false;
     b->poisoned = false;
@@ -739,21 +965,29 @@ int pf_batch_init(const pf_params* ps, int32_t n, void* d_workspace, size_t work
     std::vector<double> vx((size_t)n), vy((size_t)n);
     b->f.reserve((size_t)n);
     b->cls.resize((size_t)n);
+    b->ta.resize((size_t)n);
     for (int32_t k = 0; k < n; ++k) {
+        pf_params pk;
+        if (resolve_tuned(&ps[k], b->stream, &pk)) {
+            const int rc = fail(PF_ERR_HIP, "filter %d: %s", k, g_err.c_str());
+            batch_free(b);
+            return rc;
+        }
         pf_filter* h = new (std::nothrow) pf_filter{};
         if (!h) {
             batch_free(b);
             return fail(PF_ERR_INVALID_ARG, "out of host memory");
         }
         b->f.push_back(h);
-        setup_filter(h, ps[k], b->ws + bl.filters + foff[k], b->stream, &blocks[k], &vx[k], &vy[k]);
+        setup_filter(h, pk, b->ws + bl.filters + foff[k], b->stream, &blocks[k], &vx[k], &vy[k]);
         h->owner = b;
         args[k] = h->args;
         b->cls[k] = comb_class(h->L.ntiles);
+        b->ta[k] = h->args.threads_a;
         b->slot_bytes[k] = h->L.total;
         b->slot_tiles[k] = h->L.ntiles;
     }
-    b->stage_bytes = sizeof(BatchEntry) * (size_t)n + 4 * (size_t)bl.tiles;
+    b->stage_bytes = sizeof(BatchEntry) * (size_t)n + 8 * (size_t)bl.tiles;
     hipError_t e = hipSuccess;
     for (int i = 0; i < kRing && e == hipSuccess; ++i) {
         e = hipHostMalloc((void**)&b->h_stage[i], b->stage_bytes, hipHostMallocDefault);
@@ -827,6 +1061,7 @@ int pf_batch_step(pf_batch* b, const uint8_t* const* d_frames, const int64_t* pi
     }
     BatchEntry* ent = reinterpret_cast<BatchEntry*>(stage);
     int32_t* tmap = reinterpret_cast<int32_t*>(stage + sizeof(BatchEntry) * (size_t)n);
+    int32_t* alist = tmap + b->total_tiles;
     int32_t cls_begin[kCombClasses + 1];
     int32_t ne = 0, tiles = 0;
     for (int c = 0; c < kCombClasses; ++c) {
@@ -849,20 +1084,52 @@ int pf_batch_step(pf_batch* b, const uint8_t* const* d_frames, const int64_t* pi
     }
     cls_begin[kCombClasses] = ne;
 
+    // pass-A sizes of the stepped filters: one launch per size; with more
+    // than one size, each launch reads its grid tiles from a list
+    static constexpr int kSizesA[3] = {128, 256, 512};
+    int32_t a_count[3] = {0, 0, 0};
+    for (int32_t i = 0; i < ne; ++i) {
+        const pf_filter* h = b->f[ent[i].fid];
+        for (int c = 0; c < 3; ++c)
+            if (b->ta[ent[i].fid] == kSizesA[c]) a_count[c] += h->L.ntiles;
+    }
+    const int sizes_used = (a_count[0] > 0) + (a_count[1] > 0) + (a_count[2] > 0);
+    int32_t a_begin[3] = {0, a_count[0], a_count[0] + a_count[1]};
+    if (sizes_used > 1 && !same) {
+        int32_t fillp[3] = {a_begin[0], a_begin[1], a_begin[2]};
+        for (int32_t i = 0; i < ne; ++i) {
+            const pf_filter* h = b->f[ent[i].fid];
+            const int c = b->ta[ent[i].fid] == 128 ? 0 : b->ta[ent[i].fid] == 256 ? 1 : 2;
+            for (int j = 0; j < h->L.ntiles; ++j) alist[fillp[c]++] = ent[i].tile_base + j;
+        }
+    }
+
     BatchEntry* d_ent = capturing ? b->d_g_entries : b->d_entries;
     int32_t* d_map = capturing ? b->d_g_tile_entry : b->d_tile_entry;
+    int32_t* d_alist = capturing ? b->d_g_a_tiles : b->d_a_tiles;
     e = hipMemcpyAsync(d_ent, ent, sizeof(BatchEntry) * (size_t)ne, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess && !same)
         e = hipMemcpyAsync(d_map, tmap, 4 * (size_t)tiles, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess && !same && sizes_used > 1)
+        e = hipMemcpyAsync(d_alist, alist, 4 * (size_t)tiles, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess && !capturing) e = hipEventRecord(b->ev[slot], b->stream);
     if (e == hipSuccess && !capturing) b->ev_used[slot] = true;
     BatchArgs ba;
     ba.args = b->d_args;
     ba.entries = d_ent;
     ba.tile_entry = d_map;
+    ba.a_tiles = nullptr;
     ba.entry0 = 0;
     ba.tiles = tiles;
-    if (e == hipSuccess) e = launch_batch_pass_a(b->dtype, b->rc, ba, tiles, b->stream);
+    for (int c = 0; c < 3 && e == hipSuccess; ++c) {
+        if (a_count[c] == 0) continue;
+        BatchArgs bp = ba;
+        if (sizes_used > 1) {
+            bp.a_tiles = d_alist;
+            bp.entry0 = a_begin[c];
+        }
+        e = launch_batch_pass_a(b->dtype, b->rc, kSizesA[c], bp, a_count[c], b->stream);
+    }
     for (int c = 0; c < kCombClasses - 1 && e == hipSuccess; ++c) {
         const int32_t cnt = cls_begin[c + 1] - cls_begin[c];
         if (cnt == 0) continue;
@@ -917,13 +1184,17 @@ int pf_batch_estimates(pf_batch* b, double* out_2n)
     return ok();
 }
 
-int pf_batch_reinit(pf_batch* b, int32_t k, const pf_params* p)
+int pf_batch_reinit(pf_batch* b, int32_t k, const pf_params* p_in)
 {
     if (int rc = batch_live(b)) return rc;
     if (k < 0 || k >= b->n) return fail(PF_ERR_INVALID_ARG, "filter index %d outside [0, %d)", k, b->n);
-    if (int rc = check_params(p)) return rc;
-    if (p->dtype != b->dtype) return fail(PF_ERR_INVALID_ARG, "dtype %d differs from the batch's %d", p->dtype, b->dtype);
-    if (p->flags & ~PF_FLAG_DIAGNOSTICS) return fail(PF_ERR_INVALID_ARG, "implementation variants are not batched");
+    if (int rc = check_params(p_in)) return rc;
+    if (p_in->dtype != b->dtype)
+        return fail(PF_ERR_INVALID_ARG, "dtype %d differs from the batch's %d", p_in->dtype, b->dtype);
+    if (p_in->flags & ~kBatchFlags) return fail(PF_ERR_INVALID_ARG, "implementation variants are not batched");
+    pf_params tuned;
+    if (int rc = resolve_tuned(p_in, b->stream, &tuned)) return rc;
+    const pf_params* p = &tuned;
     const Layout L = make_layout(*p);
     if (L.total > b->slot_bytes[k] || L.ntiles > b->slot_tiles[k])
         return fail(PF_ERR_WORKSPACE, "filter %d: %zu bytes / %d tiles needed, its share holds %zu / %d", k, L.total,
@@ -938,6 +1209,7 @@ int pf_batch_reinit(pf_batch* b, int32_t k, const pf_params* p)
     h->owner = b;
     b->args_host[k] = h->args;
     b->cls[k] = comb_class(L.ntiles);
+    b->ta[k] = h->args.threads_a;
     b->map_valid = false;
     bool all5 = true, all8 = true;
     for (const pf_filter* g : b->f) {

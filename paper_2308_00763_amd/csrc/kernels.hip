@@ -1962,15 +1962,18 @@ __device__ __forceinline__ StepArgs batch_args(const BatchArgs& b, int e)
     return a;
 }
 
-template <int DT, int RC>
-__global__ __launch_bounds__(kBlockA) void pass_a_batch_kernel(BatchArgs b)
+// Pass A over grid tiles of members whose pass-A size is kTile / PPT threads:
+// all grid tiles, or the listed ones.
+template <int DT, int RC, int PPT>
+__global__ __launch_bounds__(kTile / PPT) void pass_a_batch_kernel(BatchArgs b)
 {
     __shared__ PassALds lds;
-    const int e = tile_entry_of(b, blockIdx.x);
+    const int gt = b.a_tiles ? cst(b.a_tiles)[b.entry0 + (int)blockIdx.x] : (int)blockIdx.x;
+    const int e = tile_entry_of(b, gt);
     const StepArgs a = batch_args(b, e);
-    const int lt = (int)blockIdx.x - tile_base_of(b, e);
+    const int lt = gt - tile_base_of(b, e);
     if (lt >= a.ntiles) return;  // a plan captured before the filter was re-initialised smaller
-    pass_a_tile<DT, RC, kPPT>(a, lt, lds);
+    pass_a_tile<DT, RC, PPT>(a, lt, lds);
 }
 
 template <int DT, int KPER, int NT>
@@ -2198,13 +2201,25 @@ hipError_t launch_pass_c(int dtype, const StepArgs& a, hipStream_t s, const KTim
     PF_DISPATCH(dtype, launch_pass_c_t<DT>(a, s, tm))
 }
 
-template <int DT>
-static hipError_t launch_batch_pass_a_t(int rc, const BatchArgs& b, int tiles, hipStream_t s, const KTiming& tm)
+template <int DT, int PPT>
+static hipError_t launch_batch_pass_a_p(int rc, const BatchArgs& b, int tiles, hipStream_t s, const KTiming& tm)
 {
-    const dim3 g((unsigned)tiles), blk(kBlockA);
-    if (rc == 5) return launch1(pass_a_batch_kernel<DT, 5>, g, blk, s, tm, b);
-    if (rc == 8) return launch1(pass_a_batch_kernel<DT, 8>, g, blk, s, tm, b);
-    return launch1(pass_a_batch_kernel<DT, 0>, g, blk, s, tm, b);
+    const dim3 g((unsigned)tiles), blk(kTile / PPT);
+    if (rc == 5) return launch1(pass_a_batch_kernel<DT, 5, PPT>, g, blk, s, tm, b);
+    if (rc == 8) return launch1(pass_a_batch_kernel<DT, 8, PPT>, g, blk, s, tm, b);
+    return launch1(pass_a_batch_kernel<DT, 0, PPT>, g, blk, s, tm, b);
+}
+
+template <int DT>
+static hipError_t launch_batch_pass_a_t(int rc, int threads_a, const BatchArgs& b, int tiles, hipStream_t s,
+                                        const KTiming& tm)
+{
+    switch (threads_a) {
+    case 128: return launch_batch_pass_a_p<DT, 8>(rc, b, tiles, s, tm);
+    case 256: return launch_batch_pass_a_p<DT, 4>(rc, b, tiles, s, tm);
+    case 512: return launch_batch_pass_a_p<DT, 2>(rc, b, tiles, s, tm);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <int DT>
@@ -2219,9 +2234,10 @@ static hipError_t launch_batch_combine_t(int cls, const BatchArgs& b, int count,
     }
 }
 
-hipError_t launch_batch_pass_a(int dtype, int rc, const BatchArgs& b, int tiles, hipStream_t s, const KTiming& tm)
+hipError_t launch_batch_pass_a(int dtype, int rc, int threads_a, const BatchArgs& b, int tiles, hipStream_t s,
+                              const KTiming& tm)
 {
-    PF_DISPATCH(dtype, launch_batch_pass_a_t<DT>(rc, b, tiles, s, tm))
+    PF_DISPATCH(dtype, launch_batch_pass_a_t<DT>(rc, threads_a, b, tiles, s, tm))
 }
 
 hipError_t launch_batch_combine(int dtype, int cls, const BatchArgs& b, int count, hipStream_t s, const KTiming& tm)

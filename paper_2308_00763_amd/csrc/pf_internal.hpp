@@ -246,7 +246,11 @@ struct BatchArgs {
     const StepArgs* args;
     const BatchEntry* entries;
     const int32_t* tile_entry;
-    int32_t entry0;     // combine: entry of the launch's first workgroup
+    const int32_t* a_tiles;  // pass A of a batch with members of several pass-A
+                             // sizes: the grid tiles of each size, size by size
+                             // (null: workgroup g takes grid tile g)
+    int32_t entry0;     // combine: entry of the launch's first workgroup;
+                        // listed pass A: index in a_tiles of its first tile
     int32_t tiles;      // pass C: tiles of the step's grid (set by its launcher)
 };
 
@@ -272,8 +276,10 @@ hipError_t launch_fill(int dtype, const StepArgs& a, double vx, double vy, hipSt
 hipError_t launch_diag_weights(int dtype, const StepArgs& a, hipStream_t s);
 // Batched passes: pass A and pass C over `tiles` grid tiles, the combine over
 // `count` entries of one combine class starting at b.entry0.  rc: the common
-// disk radius of the batch when it is 5 or 8, else 0.
-hipError_t launch_batch_pass_a(int dtype, int rc, const BatchArgs& b, int tiles, hipStream_t s,
+// disk radius of the batch when it is 5 or 8, else 0.  Pass A runs the
+// members of pass-A size threads_a (128, 256 or 512): every grid tile when
+// b.a_tiles is null, else the `tiles` listed from b.a_tiles[b.entry0].
+hipError_t launch_batch_pass_a(int dtype, int rc, int threads_a, const BatchArgs& b, int tiles, hipStream_t s,
                                const KTiming& tm = KTiming());
 hipError_t launch_batch_combine(int dtype, int cls, const BatchArgs& b, int count, hipStream_t s,
                                 const KTiming& tm = KTiming());

@@ -79,9 +79,10 @@ def test_batch_workspace_is_the_sum_of_its_filters_plus_the_plan():
     total = pf.pf_batch_workspace_bytes(ps)
     singles = sum(pf.pf_workspace_bytes(p) for p in ps)
     tiles = sum((p.n_particles + 1023) // 1024 for p in ps)
-    # two plans (eager and captured steps): 32 bytes per filter, 4 per tile each
-    assert total >= singles + 2 * (4 * tiles + 32 * len(ps))
-    assert total < singles + 8192 + 8 * tiles + 450 * len(ps)
+    # two plans (eager and captured steps): 32 bytes per filter and, per tile,
+    # 4 for the tile map and 4 for the pass-A tile list, each
+    assert total >= singles + 2 * (8 * tiles + 32 * len(ps))
+    assert total < singles + 8192 + 16 * tiles + 450 * len(ps)
 
 
 def test_batch_params_are_checked_per_filter():
