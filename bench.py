@@ -295,8 +295,18 @@ def _serving_bank(torch, pfsynth, rng):
     return bank
 
 
-def _serving_pools(hbm_gb):
-    from paper_2308_00763_amd.serve import GpuPoolBackend, plan_pool, slot_classes
+SERVE_HANDLES = 4096  # batch members per precision: the most streams served at once
+
+
+def _serving_pools(hbm_gb, admission="bytes"):
+    """The serving backend for HBM budgets hbm_gb = (FP16 GiB, FP32 GiB):
+    admission by bytes (every stream gets exactly its workspace from the
+    budget) or by power-of-two slot classes sized from the budget."""
+    from paper_2308_00763_amd.serve import GpuByteBackend, GpuPoolBackend, plan_pool, slot_classes
+    if admission == "bytes":
+        budgets = {"f16": int(hbm_gb[0] * 2**30), "f32": int(hbm_gb[1] * 2**30)}
+        log(f"[bench] serving: byte budgets {budgets}, {SERVE_HANDLES} handles per precision")
+        return GpuByteBackend(budgets, {"f16": SERVE_HANDLES, "f32": SERVE_HANDLES})
     caps = slot_classes(1000, 1_000_000)
     pools = {"f16": plan_pool(int(hbm_gb[0] * 2**30), "f16", caps),
              "f32": plan_pool(int(hbm_gb[1] * 2**30), "f32", caps)}
@@ -324,7 +334,8 @@ def _serving_request(pf, rng, bank, sid, arrival, fps, frames=None):
                          lambda i, b=base + o * fst, s=fst, q=pitch: (b + i * s, q))
 
 
-def run_serving(pf, torch, pfsynth, seconds, warmup_s, rate=200.0, fps=30.0, hbm_gb=(6.0, 12.0)):
+def run_serving(pf, torch, pfsynth, seconds, warmup_s, rate=200.0, fps=30.0, hbm_gb=(6.0, 12.0),
+                admission="bytes"):
     """Continuous batching of arriving streams: Poisson arrivals at `rate`
     streams/s (PCG64(5)); per stream frames ~ U{20..500} at `fps`, side ~
     U{64, 128, 256, 512, 1024}, N = round(exp(U(ln 1e3, ln 1e6))), FP16 or FP32
@@ -336,7 +347,7 @@ def run_serving(pf, torch, pfsynth, seconds, warmup_s, rate=200.0, fps=30.0, hbm
     from paper_2308_00763_amd.serve import Scheduler
     rng = np.random.Generator(np.random.PCG64(5))
     bank = _serving_bank(torch, pfsynth, rng)
-    be = _serving_pools(hbm_gb)
+    be = _serving_pools(hbm_gb, admission)
     sched = Scheduler(be, stall_timeout=5.0)
     total = warmup_s + seconds
     t = 0.0
@@ -375,12 +386,12 @@ def run_serving(pf, torch, pfsynth, seconds, warmup_s, rate=200.0, fps=30.0, hbm
                 updates_per_s=(sched.updates - (u_warm if n_warm is not None else 0)) /
                               max(t_end - (t_warm if n_warm is not None else t_base), 1e-9),
                 live_at_end=len(sched.live), queued_at_end=len(sched.queue),
-                pool_bytes=be.pool_bytes, streams_submitted=sid)
+                pool_bytes=be.pool_bytes, streams_submitted=sid, admission=admission)
     be.close()
     return summ
 
 
-def run_serving_closed(pf, torch, pfsynth, seconds, n_streams=1770, hbm_gb=(6.0, 12.0)):
+def run_serving_closed(pf, torch, pfsynth, seconds, n_streams=1770, hbm_gb=(6.0, 12.0), admission="bytes"):
     """Closed-loop serving capacity: a constant population of n_streams
     streams of the serving mix (500 frames each; a finished stream is
     replaced at once), every frame already waiting (a frame rate far above
@@ -389,7 +400,7 @@ def run_serving_closed(pf, torch, pfsynth, seconds, n_streams=1770, hbm_gb=(6.0,
     from paper_2308_00763_amd.serve import Scheduler
     rng = np.random.Generator(np.random.PCG64(6))
     bank = _serving_bank(torch, pfsynth, rng)
-    be = _serving_pools(hbm_gb)
+    be = _serving_pools(hbm_gb, admission)
     sched = Scheduler(be, stall_timeout=60.0)
     sid = 0
 
@@ -614,6 +625,8 @@ def run_large(pf, torch, pfsynth, args, modes):
     vl = pfsynth.workload_video(wl)
     fl = torch.from_numpy(vl.frames).to("cuda:0")
     ls, lw = min(args.steps, wl.frames - 6), 5
+    if args.gpu_warmup_s > 0:  # the heavier workload ramps the clocks again
+        warm_gpu(pf, torch, fl, vl.centres, wl, modes[0], args.gpu_warmup_s)
     lres = {}
     for dt in modes:
         secs, _ = run_mode(pf, torch, fl, vl.centres, wl, dt, ls, lw, profile=False)
@@ -719,6 +732,10 @@ def main():
                     help="skip the naive-vs-optimised and workgroup-size runs")
     ap.add_argument("--gpu-warmup-s", type=float, default=1.0,
                     help="seconds of untimed steps before the first timed mode (clock ramp-up)")
+    ap.add_argument("--serve-admission", choices=("bytes", "classes"), default="bytes",
+                    help="serving admission: by bytes from the HBM budget, or by power-of-two slot classes")
+    ap.add_argument("--serve-hbm-gb", default="6,12", metavar="F16,F32",
+                    help="serving HBM budgets in GiB for the FP16 and FP32 streams")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="measured seconds of the serving workload after a 10 s warm-up (0 to skip)")
     ap.add_argument("--variant", default="", metavar="KEY=VAL,...",
@@ -875,8 +892,11 @@ def main():
     if args.fleet:
         section("fleet", lambda: run_fleet(pf, torch, pfsynth, args.fleet, 256, 50, 40, 5))
     if args.serve_seconds > 0:
-        section("serving", lambda: run_serving(pf, torch, pfsynth, args.serve_seconds, 10.0))
-        section("serving_closed_loop", lambda: run_serving_closed(pf, torch, pfsynth, 10.0))
+        hbm = tuple(float(x) for x in args.serve_hbm_gb.split(","))
+        section("serving", lambda: run_serving(pf, torch, pfsynth, args.serve_seconds, 10.0, hbm_gb=hbm,
+                                               admission=args.serve_admission))
+        section("serving_closed_loop", lambda: run_serving_closed(pf, torch, pfsynth, 10.0, hbm_gb=hbm,
+                                                                  admission=args.serve_admission))
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         section("cpu_baseline", lambda: cpu_baseline(w, vid, args.cpu_budget, pfsynth))

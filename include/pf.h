@@ -411,11 +411,39 @@ int pf_batch_estimates_async(pf_batch* b, double* d_out_2n);
 /* Re-initialise filter k of the batch in place with new parameters, as
  * pf_init does (particles at (x0, y0), t = 0): a continuous-batching server
  * hands the share of a finished stream to an arriving one.  The parameters
- * must have the batch's dtype and fit the filter's workspace share (at most
- * the bytes and tiles of the parameters it was created with).  Waits for the
- * stream before and after.  Errors: PF_ERR_INVALID_ARG, PF_ERR_WORKSPACE (the
- * share is too small; nothing changes), PF_ERR_HIP, PF_ERR_STATE. */
+ * must have the batch's dtype and fit the filter's workspace share (the
+ * bytes of the parameters it was created with, or of its last
+ * pf_batch_rebind), and the members' tiles together must fit the batch's
+ * plan (the members' tiles at creation, or pf_batch_init_cap's capacity).
+ * Waits for the stream before and after.  Errors: PF_ERR_INVALID_ARG,
+ * PF_ERR_WORKSPACE (the share or the plan is too small; nothing changes),
+ * PF_ERR_HIP, PF_ERR_STATE. */
 int pf_batch_reinit(pf_batch* b, int32_t k, const pf_params* p);
+
+/* The two calls above with room in the batch's plan for max_tiles tiles in
+ * total (at least the members' own tiles; 0 = exactly those), so that
+ * members can later be rebound (pf_batch_rebind) to larger filters whose
+ * workspace shares lie outside the batch workspace.  The plan costs 16 bytes
+ * of workspace and 32 bytes of pinned host memory per tile of capacity.
+ * Errors as for pf_batch_workspace_bytes and pf_batch_init (max_tiles outside
+ * [0, 2^31 - 1]: PF_ERR_INVALID_ARG). */
+int pf_batch_workspace_bytes_cap(const pf_params* ps, int32_t n, int64_t max_tiles, size_t* out_bytes);
+int pf_batch_init_cap(const pf_params* ps, int32_t n, int64_t max_tiles, void* d_workspace,
+                      size_t workspace_bytes, void* hip_stream, pf_batch** out);
+
+/* Re-initialise filter k of the batch as pf_batch_reinit does, on a new
+ * workspace share: share_bytes bytes of device memory at d_share (256-byte
+ * aligned, at least pf_workspace_bytes(p); owned by the caller, who keeps it
+ * valid and unshared while filter k is bound to it, i.e. until the next
+ * rebind of k or pf_batch_destroy).  Lets a server hand its filters shares
+ * from its own device-memory budget, sized per stream, instead of fixed
+ * shares inside the batch workspace: after a rebind, pf_batch_reinit of k
+ * reuses the new share.  The members' tiles together must stay within the
+ * batch's plan capacity (pf_batch_init_cap).  Waits for the stream before and
+ * after; a graph captured before steps the filter with the old plan (as after
+ * pf_batch_reinit).  Errors: PF_ERR_INVALID_ARG, PF_ERR_WORKSPACE (the share
+ * or the plan is too small; nothing changes), PF_ERR_HIP, PF_ERR_STATE. */
+int pf_batch_rebind(pf_batch* b, int32_t k, const pf_params* p, void* d_share, size_t share_bytes);
 
 /* Handle of filter k (0 <= k < n) of the batch, owned by the batch and valid
  * until pf_batch_destroy.  pf_estimate, pf_estimate_async, pf_export,

@@ -52,7 +52,8 @@ EXPORTS = ("pf_workspace_bytes", "pf_init", "pf_step", "pf_step_static_scratch",
            "pf_abi_version", "pf_profile_start", "pf_profile_read",
            "pf_batch_workspace_bytes", "pf_batch_init", "pf_batch_step", "pf_batch_estimates",
            "pf_batch_estimates_async", "pf_batch_reinit", "pf_batch_filter", "pf_batch_destroy",
-           "pf_tune_set", "pf_tune_load", "pf_tune_clear", "pf_tune_lookup", "pf_launch_config")
+           "pf_tune_set", "pf_tune_load", "pf_tune_clear", "pf_tune_lookup", "pf_launch_config",
+           "pf_batch_workspace_bytes_cap", "pf_batch_init_cap", "pf_batch_rebind")
 
 
 class PfError(RuntimeError):
@@ -126,6 +127,9 @@ def lib():
         L.pf_tune_clear.argtypes = []
         L.pf_tune_lookup.argtypes = [ctypes.c_char_p, i32, ctypes.c_int64, P(i32), P(i32)]
         L.pf_launch_config.argtypes = [vp, P(i32), P(i32)]
+        L.pf_batch_workspace_bytes_cap.argtypes = [P(pf_params), i32, ctypes.c_int64, P(ctypes.c_size_t)]
+        L.pf_batch_init_cap.argtypes = [P(pf_params), i32, ctypes.c_int64, vp, ctypes.c_size_t, vp, P(vp)]
+        L.pf_batch_rebind.argtypes = [vp, i32, P(pf_params), vp, ctypes.c_size_t]
         for name in EXPORTS:
             if name != "pf_last_error":
                 getattr(L, name).restype = ctypes.c_int
@@ -294,6 +298,25 @@ def pf_batch_init(params, d_workspace: int, workspace_bytes: int, hip_stream: in
     return b
 
 
+def pf_batch_workspace_bytes_cap(params, max_tiles: int) -> int:
+    arr = _params_array(params)
+    out = ctypes.c_size_t()
+    _check(lib().pf_batch_workspace_bytes_cap(arr, len(params), int(max_tiles), ctypes.byref(out)))
+    return out.value
+
+
+def pf_batch_init_cap(params, max_tiles: int, d_workspace: int, workspace_bytes: int, hip_stream: int):
+    arr = _params_array(params)
+    b = ctypes.c_void_p()
+    _check(lib().pf_batch_init_cap(arr, len(params), int(max_tiles), ctypes.c_void_p(d_workspace),
+                                   workspace_bytes, ctypes.c_void_p(hip_stream), ctypes.byref(b)))
+    return b
+
+
+def pf_batch_rebind(b, k: int, p: pf_params, d_share: int, share_bytes: int):
+    _check(lib().pf_batch_rebind(b, int(k), ctypes.byref(p), ctypes.c_void_p(d_share), int(share_bytes)))
+
+
 def pf_batch_step(b, d_frames, pitches, active=None):
     """d_frames: uint64 array of device pointers; pitches: int64 array;
     active: uint8 array or None (all)."""
@@ -412,16 +435,18 @@ class Filter:
 class Batch:
     """A batch of filters in one torch-allocated workspace on `device`."""
 
-    def __init__(self, params, device="cuda:0", stream=None):
+    def __init__(self, params, device="cuda:0", stream=None, max_tiles=0):
+        """max_tiles: tile capacity of the batch's plan (0: the members' own
+        tiles), room for members rebound to larger filters."""
         import torch
         self.params = list(params)
         self.n = len(self.params)
         self.device = torch.device(device)
-        nbytes = pf_batch_workspace_bytes(self.params)
+        nbytes = pf_batch_workspace_bytes_cap(self.params, max_tiles)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self.handle = pf_batch_init(self.params, self.workspace.data_ptr(), nbytes,
-                                    self.stream.cuda_stream)
+        self.handle = pf_batch_init_cap(self.params, max_tiles, self.workspace.data_ptr(), nbytes,
+                                        self.stream.cuda_stream)
 
     def step(self, frames, active=None):
         """frames: list of n (H_k, W_k) uint8 CUDA tensors (None where inactive)."""
@@ -446,6 +471,11 @@ class Batch:
 
     def reinit(self, k: int, params: pf_params):
         pf_batch_reinit(self.handle, k, params)
+        self.params[k] = params
+
+    def rebind(self, k: int, params: pf_params, d_share: int, share_bytes: int):
+        """Filter k re-initialised on a workspace share the caller owns."""
+        pf_batch_rebind(self.handle, k, params, d_share, share_bytes)
         self.params[k] = params
 
     def export(self, k: int):

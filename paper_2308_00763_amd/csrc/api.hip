@@ -54,7 +54,8 @@ struct pf_batch {
     int rc;  // common disk radius when 5 or 8, else 0
     hipStream_t stream;
     uint8_t* ws;
-    int64_t total_tiles;
+    int64_t total_tiles;              // tile capacity of the plan buffers
+    int64_t tiles_used;               // tiles of the members as they are now
     StepArgs* d_args;
     BatchEntry* d_entries;
     int32_t* d_tile_entry;
@@ -66,8 +67,7 @@ struct pf_batch {
     std::vector<pf_filter*> f;
     std::vector<int> cls;            // combine class of every filter
     std::vector<int> ta;             // pass-A threads of every filter
-    std::vector<size_t> slot_bytes;  // workspace share of every filter
-    std::vector<int> slot_tiles;     // tiles of every filter at creation (the most it may have)
+    std::vector<size_t> slot_bytes;  // bytes of every filter's workspace share
     std::vector<StepArgs> args_host; // host copy of the filters' StepArgs
     uint8_t* h_stage[kRing];
     uint8_t* h_graph;                 // staging read by the copies of a captured step
@@ -854,7 +854,10 @@ struct BatchLayout {
 constexpr uint32_t kBatchFlags =
     PF_FLAG_DIAGNOSTICS | PF_FLAG_TUNED | (0xFu << PF_THREADS_A_SHIFT) | (0xFu << PF_THREADS_C_SHIFT);
 
-static int check_batch(const pf_params* ps, int32_t n, BatchLayout* bl, std::vector<size_t>* foff)
+// Checks a batch's parameters and lays out its workspace; the plan buffers
+// hold max(max_tiles, the members' tiles) tiles.
+static int check_batch(const pf_params* ps, int32_t n, int64_t max_tiles, BatchLayout* bl,
+                       std::vector<size_t>* foff)
 {
     if (!ps) return fail(PF_ERR_INVALID_ARG, "params is NULL");
     if (n < 1 || n > (1 << 20)) return fail(PF_ERR_INVALID_ARG, "batch size %d outside [1, 2^20]", n);
@@ -871,7 +874,10 @@ static int check_batch(const pf_params* ps, int32_t n, BatchLayout* bl, std::vec
         fbytes += L.total;
         tiles += L.ntiles;
     }
+    if (max_tiles < 0 || max_tiles > INT32_MAX)
+        return fail(PF_ERR_INVALID_ARG, "tile capacity %lld outside [0, 2^31 - 1]", (long long)max_tiles);
     if (tiles > INT32_MAX) return fail(PF_ERR_INVALID_ARG, "batch has %lld tiles, more than 2^31 - 1", (long long)tiles);
+    if (max_tiles > tiles) tiles = max_tiles;
     size_t o = 0;
     bl->args = o; o = align256(o + sizeof(StepArgs) * (size_t)n);
     bl->entries = o; o = align256(o + sizeof(BatchEntry) * (size_t)n);
@@ -895,6 +901,8 @@ static int batch_fail(pf_batch* b, hipError_t e, const char* what)
     return fail(PF_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+static int batch_rebind(pf_batch* b, int32_t k, const pf_params* p, uint8_t* ws, size_t share_bytes);
+
 static void batch_free(pf_batch* b)
 {
     for (pf_filter* h : b->f) {
@@ -910,21 +918,32 @@ static void batch_free(pf_batch* b)
     delete b;
 }
 
-int pf_batch_workspace_bytes(const pf_params* ps, int32_t n, size_t* out_bytes)
+int pf_batch_workspace_bytes_cap(const pf_params* ps, int32_t n, int64_t max_tiles, size_t* out_bytes)
 {
     BatchLayout bl;
-    if (int rc = check_batch(ps, n, &bl, nullptr)) return rc;
+    if (int rc = check_batch(ps, n, max_tiles, &bl, nullptr)) return rc;
     if (!out_bytes) return fail(PF_ERR_INVALID_ARG, "out_bytes is NULL");
     *out_bytes = bl.total;
     return ok();
 }
 
+int pf_batch_workspace_bytes(const pf_params* ps, int32_t n, size_t* out_bytes)
+{
+    return pf_batch_workspace_bytes_cap(ps, n, 0, out_bytes);
+}
+
 int pf_batch_init(const pf_params* ps, int32_t n, void* d_workspace, size_t workspace_bytes, void* hip_stream,
                   pf_batch** out)
 {
+    return pf_batch_init_cap(ps, n, 0, d_workspace, workspace_bytes, hip_stream, out);
+}
+
+int pf_batch_init_cap(const pf_params* ps, int32_t n, int64_t max_tiles, void* d_workspace, size_t workspace_bytes,
+                      void* hip_stream, pf_batch** out)
+{
     BatchLayout bl;
     std::vector<size_t> foff;
-    if (int rc = check_batch(ps, n, &bl, &foff)) return rc;
+    if (int rc = check_batch(ps, n, max_tiles, &bl, &foff)) return rc;
     if (!out) return fail(PF_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (!d_workspace) return fail(PF_ERR_INVALID_ARG, "workspace is NULL");
@@ -961,7 +980,7 @@ int pf_batch_init(const pf_params* ps, int32_t n, void* d_workspace, size_t work
     std::vector<StepArgs>& args = b->args_host;
     args.resize((size_t)n);
     b->slot_bytes.resize((size_t)n);
-    b->slot_tiles.resize((size_t)n);
+    b->tiles_used = 0;
     std::vector<double> vx((size_t)n), vy((size_t)n);
     b->f.reserve((size_t)n);
     b->cls.resize((size_t)n);
@@ -985,7 +1004,7 @@ int pf_batch_init(const pf_params* ps, int32_t n, void* d_workspace, size_t work
         b->cls[k] = comb_class(h->L.ntiles);
         b->ta[k] = h->args.threads_a;
         b->slot_bytes[k] = h->L.total;
-        b->slot_tiles[k] = h->L.ntiles;
+        b->tiles_used += h->L.ntiles;
     }
     b->stage_bytes = sizeof(BatchEntry) * (size_t)n + 8 * (size_t)bl.tiles;
     hipError_t e = hipSuccess;
@@ -1196,17 +1215,54 @@ int pf_batch_reinit(pf_batch* b, int32_t k, const pf_params* p_in)
     if (int rc = resolve_tuned(p_in, b->stream, &tuned)) return rc;
     const pf_params* p = &tuned;
     const Layout L = make_layout(*p);
-    if (L.total > b->slot_bytes[k] || L.ntiles > b->slot_tiles[k])
-        return fail(PF_ERR_WORKSPACE, "filter %d: %zu bytes / %d tiles needed, its share holds %zu / %d", k, L.total,
-                    L.ntiles, b->slot_bytes[k], b->slot_tiles[k]);
     pf_filter* h = b->f[k];
+    if (L.total > b->slot_bytes[k])
+        return fail(PF_ERR_WORKSPACE, "filter %d: %zu bytes needed, its share holds %zu", k, L.total, b->slot_bytes[k]);
+    if (b->tiles_used - h->L.ntiles + L.ntiles > b->total_tiles)
+        return fail(PF_ERR_WORKSPACE, "filter %d: %d tiles would bring the batch to %lld, its plan holds %lld", k,
+                    L.ntiles, (long long)(b->tiles_used - h->L.ntiles + L.ntiles), (long long)b->total_tiles);
+    return batch_rebind(b, k, p, h->ws, b->slot_bytes[k]);
+}
+
+int pf_batch_rebind(pf_batch* b, int32_t k, const pf_params* p_in, void* d_share, size_t share_bytes)
+{
+    if (int rc = batch_live(b)) return rc;
+    if (k < 0 || k >= b->n) return fail(PF_ERR_INVALID_ARG, "filter index %d outside [0, %d)", k, b->n);
+    if (int rc = check_params(p_in)) return rc;
+    if (p_in->dtype != b->dtype)
+        return fail(PF_ERR_INVALID_ARG, "dtype %d differs from the batch's %d", p_in->dtype, b->dtype);
+    if (p_in->flags & ~kBatchFlags) return fail(PF_ERR_INVALID_ARG, "implementation variants are not batched");
+    if (!d_share) return fail(PF_ERR_INVALID_ARG, "share is NULL");
+    if (((uintptr_t)d_share & 255) != 0) return fail(PF_ERR_INVALID_ARG, "share must be 256-byte aligned");
+    pf_params tuned;
+    if (int rc = resolve_tuned(p_in, b->stream, &tuned)) return rc;
+    const Layout L = make_layout(tuned);
+    pf_filter* h = b->f[k];
+    if (L.total > share_bytes)
+        return fail(PF_ERR_WORKSPACE, "filter %d: %zu bytes needed, the share holds %zu", k, L.total, share_bytes);
+    if (b->tiles_used - h->L.ntiles + L.ntiles > b->total_tiles)
+        return fail(PF_ERR_WORKSPACE, "filter %d: %d tiles would bring the batch to %lld, its plan holds %lld", k,
+                    L.ntiles, (long long)(b->tiles_used - h->L.ntiles + L.ntiles), (long long)b->total_tiles);
+    return batch_rebind(b, k, &tuned, (uint8_t*)d_share, share_bytes);
+}
+
+}  // extern "C"
+
+// Re-initialise member k with checked parameters `p` on the share at `ws`
+// (share_bytes long): waits for the stream before and after.
+static int batch_rebind(pf_batch* b, int32_t k, const pf_params* p, uint8_t* ws, size_t share_bytes)
+{
+    pf_filter* h = b->f[k];
+    const Layout L = make_layout(*p);
     hipError_t e = hipStreamSynchronize(b->stream);  // earlier work may still read the slot
-    if (e != hipSuccess) return batch_fail(b, e, "pf_batch_reinit");
+    if (e != hipSuccess) return batch_fail(b, e, "batch member re-initialisation");
     profile_free(h);
     DevBlock blk;
     double vx, vy;
-    setup_filter(h, *p, h->ws, b->stream, &blk, &vx, &vy);
+    b->tiles_used += L.ntiles - h->L.ntiles;
+    setup_filter(h, *p, ws, b->stream, &blk, &vx, &vy);
     h->owner = b;
+    b->slot_bytes[k] = share_bytes;
     b->args_host[k] = h->args;
     b->cls[k] = comb_class(L.ntiles);
     b->ta[k] = h->args.threads_a;
@@ -1221,9 +1277,11 @@ int pf_batch_reinit(pf_batch* b, int32_t k, const pf_params* p_in)
     if (e == hipSuccess) e = hipMemcpyAsync(at(h, h->L.blk), &blk, sizeof blk, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = launch_fill(b->dtype, h->args, vx, vy, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-    if (e != hipSuccess) return batch_fail(b, e, "pf_batch_reinit");
+    if (e != hipSuccess) return batch_fail(b, e, "batch member re-initialisation");
     return ok();
 }
+
+extern "C" {
 
 int pf_batch_filter(pf_batch* b, int32_t k, pf_filter** out)
 {

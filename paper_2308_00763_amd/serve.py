@@ -18,14 +18,25 @@ The server:
     a stream whose step failed, reclaiming the slot either way.
 
 The scheduler is independent of the device: a backend provides slots, the
-batched step and estimates.  `GpuPoolBackend` keeps one `pf_batch` per
-precision whose members are re-initialised in place (pf_batch_reinit) for each
-admitted stream.  A HIP error in a batched step poisons that pool's batch, so
-every stream stepping in it fails; the scheduler then fails exactly those
-streams.
+batched step and estimates.  Two GPU backends keep one `pf_batch` per
+precision:
+
+  * `GpuByteBackend` admits by bytes: every admitted stream gets exactly its
+    workspace (pf_workspace_bytes of its parameters) from a per-precision
+    device arena of the HBM budget (first fit, freed ranges coalesce), and a
+    batch member is rebound to that share (pf_batch_rebind); a stream waits
+    only when no free range of the arena holds its bytes (or every member
+    handle is taken);
+  * `GpuPoolBackend` pre-sizes slots in power-of-two particle classes and
+    re-initialises a free slot in place (pf_batch_reinit): simpler, but a
+    burst of large streams waits while small slots sit idle.
+
+A HIP error in a batched step poisons that pool's batch, so every stream
+stepping in it fails; the scheduler then fails exactly those streams.
 """
 from __future__ import annotations
 
+import bisect
 import heapq
 import math
 import time
@@ -36,6 +47,8 @@ import numpy as np
 
 from . import (PF_F16, PF_F32, PF_F64, PF_BF16, Batch, PfError, make_params, pf_params,
                pf_workspace_bytes)
+
+WS_ALIGN = 256  # workspace shares start on 256-byte boundaries
 
 
 @dataclass
@@ -341,3 +354,142 @@ class GpuPoolBackend:
     def close(self):
         for b in self.batches.values():
             b.close()
+
+
+# ---------------------------------------------------------------------------
+# Byte-budget admission.
+
+class ByteArena:
+    """First-fit allocator of byte ranges of [0, size), each 256-byte aligned;
+    a freed range merges with free neighbours.  Offsets only: the caller maps
+    them onto its device memory."""
+
+    def __init__(self, size: int):
+        self.size = size - size % WS_ALIGN
+        self.starts = [0] if self.size else []   # free ranges, sorted by start
+        self.lens = [self.size] if self.size else []
+        self.used = 0
+        self.high = 0
+
+    @staticmethod
+    def rounded(nbytes: int) -> int:
+        return -(-int(nbytes) // WS_ALIGN) * WS_ALIGN
+
+    def alloc(self, nbytes: int):
+        """Offset of a free range of nbytes (rounded up to 256), or None."""
+        need = self.rounded(nbytes)
+        for i, ln in enumerate(self.lens):
+            if ln >= need:
+                off = self.starts[i]
+                if ln == need:
+                    del self.starts[i], self.lens[i]
+                else:
+                    self.starts[i] += need
+                    self.lens[i] -= need
+                self.used += need
+                self.high = max(self.high, self.used)
+                return off
+        return None
+
+    def release(self, off: int, nbytes: int):
+        need = self.rounded(nbytes)
+        i = bisect.bisect_left(self.starts, off)
+        if (i < len(self.starts) and self.starts[i] < off + need) or \
+                (i > 0 and self.starts[i - 1] + self.lens[i - 1] > off):
+            raise ValueError(f"range [{off}, {off + need}) overlaps a free range")
+        self.starts.insert(i, off)
+        self.lens.insert(i, need)
+        if i + 1 < len(self.starts) and off + need == self.starts[i + 1]:  # merge the next
+            self.lens[i] += self.lens[i + 1]
+            del self.starts[i + 1], self.lens[i + 1]
+        if i > 0 and self.starts[i - 1] + self.lens[i - 1] == off:  # merge into the previous
+            self.lens[i - 1] += self.lens[i]
+            del self.starts[i], self.lens[i]
+        self.used -= need
+
+    def largest_free(self) -> int:
+        return max(self.lens, default=0)
+
+
+class GpuByteBackend(GpuPoolBackend):
+    """One pf_batch per precision with `handles` members and, for the
+    precision's HBM budget, a device arena from which every admitted stream
+    gets exactly its workspace bytes; the member is rebound to that share
+    (pf_batch_rebind).  On release the member moves back to a one-particle
+    filter on a small parking share of its own, so that idle members hold
+    one tile of the batch's plan each."""
+
+    def __init__(self, budgets: dict, handles: dict, device="cuda:0", stream=None):
+        """budgets: {dtype name: arena bytes}; handles: {dtype name: members}."""
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.batches, self.arenas, self.arena_mem, self.park_mem = {}, {}, {}, {}
+        self.free_handles, self.share = {}, {}
+        self.tiny = {}
+        for dt, budget in budgets.items():
+            m = int(handles[dt])
+            tiny = make_params(1, 64, 64, dt)
+            tiny_bytes = ByteArena.rounded(pf_workspace_bytes(tiny))
+            # the most tiles the arena's bytes can hold, plus one per idle member
+            per_tile = pf_workspace_bytes(make_params(1 << 20, 64, 64, dt)) / 1024.0
+            cap = int(budget // per_tile) + m
+            b = Batch([tiny] * m, device=device, stream=self.stream, max_tiles=cap)
+            b._ptrs = np.zeros(m, dtype=np.uint64)
+            b._pitch = np.zeros(m, dtype=np.int64)
+            b._active = np.zeros(m, dtype=np.uint8)
+            self.batches[dt] = b
+            self.arenas[dt] = ByteArena(int(budget))
+            self.arena_mem[dt] = torch.empty(self.arenas[dt].size, dtype=torch.uint8, device=self.device)
+            self.park_mem[dt] = torch.empty(m * tiny_bytes, dtype=torch.uint8, device=self.device)
+            self.tiny[dt] = (tiny, tiny_bytes)
+            self.free_handles[dt] = list(range(m))[::-1]
+        self.pool_bytes = sum(b.workspace.numel() for b in self.batches.values()) + \
+            sum(t.numel() for t in self.arena_mem.values()) + sum(t.numel() for t in self.park_mem.values())
+
+    def validate(self, params):
+        try:
+            need = pf_workspace_bytes(params)
+        except PfError as e:
+            return str(e)
+        dt = self._dtype_name(params.dtype)
+        if dt not in self.batches:
+            return f"no pool for dtype {dt}"
+        if ByteArena.rounded(need) > self.arenas[dt].size:
+            return f"workspace of {need} bytes above the {dt} pool's budget of {self.arenas[dt].size}"
+        return ""
+
+    def try_admit(self, req):
+        dt = self._dtype_name(req.params.dtype)
+        if not self.free_handles[dt]:
+            return None
+        need = pf_workspace_bytes(req.params)
+        off = self.arenas[dt].alloc(need)
+        if off is None:
+            return None
+        k = self.free_handles[dt].pop()
+        try:
+            self.batches[dt].rebind(k, req.params, self.arena_mem[dt].data_ptr() + off,
+                                    ByteArena.rounded(need))
+        except PfError:
+            self.arenas[dt].release(off, need)
+            self.free_handles[dt].append(k)
+            raise
+        self.share[(dt, k)] = (off, need)
+        return (dt, k)
+
+    def release(self, slot):
+        dt, k = slot
+        off, need = self.share.pop(slot)
+        tiny, tiny_bytes = self.tiny[dt]
+        # park the member before its range goes back to the arena
+        self.batches[dt].rebind(k, tiny, self.park_mem[dt].data_ptr() + k * tiny_bytes, tiny_bytes)
+        self.arenas[dt].release(off, need)
+        self.free_handles[dt].append(k)
+
+    def high_water(self):
+        return sum(a.high for a in self.arenas.values())
+
+    def in_use(self):
+        return sum(a.used for a in self.arenas.values())

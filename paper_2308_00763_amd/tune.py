@@ -2,10 +2,11 @@
 it writes.
 
 Pass A (1024 particles per workgroup, 128/256/512 threads) and pass C (one
-tile per workgroup at a time, 64-1024 threads) are timed with the library's
-own per-kernel events, and the fastest sizes are kept.  Results do not depend
-on pass C's size; pass A's size changes only the rounding order of the
-tile-local prefix sums.  This is the threads-per-block study of the paper
+tile per workgroup at a time, 64-1024 threads; timed together with the
+combine between them, which does not depend on pass C's size) are timed
+with the library's own per-kernel events, and the fastest sizes are kept.
+Results do not depend on pass C's size; pass A's size changes only the
+rounding order of the tile-local prefix sums.  This is the threads-per-block study of the paper
 (Sec. 5) turned into configuration: ``sweep`` measures every (dtype,
 particle-count bucket) on the GPU it runs on and ``write_table`` stores the
 result as the text table that the library reads (``pf_tune_load``) and
@@ -44,8 +45,10 @@ def bucket(n: int) -> int:
 
 
 def _time(params, frames, steps, warmup):
-    """Mean microseconds per step of pass A and pass C (dispatch-stamped
-    events) over `steps` steps after `warmup`, stepping through `frames`."""
+    """Mean microseconds per step of pass A and of the rest of the step (the
+    combine and pass C, or a pass C that combines for itself), from
+    dispatch-stamped events over `steps` steps after `warmup`, stepping
+    through `frames`."""
     import ctypes
     f = Filter(params)
     L = lib()
@@ -57,9 +60,9 @@ def _time(params, frames, steps, warmup):
     pf_profile_start(f.handle, steps)
     for t in range(warmup, warmup + steps):
         L.pf_step(f.handle, ptr[t], pitch)
-    a_ms, _, c_ms, n = pf_profile_read(f.handle)
+    a_ms, m_ms, c_ms, n = pf_profile_read(f.handle)
     f.close()
-    return 1e3 * a_ms / n, 1e3 * c_ms / n
+    return 1e3 * a_ms / n, 1e3 * (m_ms + c_ms) / n
 
 
 def autotune(n, width, height, frames, dtype="f16", radius=5, steps=20, warmup=5, rounds=1, **model):
