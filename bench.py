@@ -169,16 +169,16 @@ def run_mode(pf, torch, frames_dev, centres, w, dtype, steps, warmup, profile, *
 
 
 def warm_gpu(pf, torch, frames_dev, centres, w, dtype, seconds, **variant):
-    """Step one filter untimed for about `seconds` so that the GPU's clocks
-    have ramped up before the first timed mode (the first mode timed in a
-    fresh process otherwise runs its pass A about 12 % slower than later
-    modes).  Returns the steps run."""
+    """Run the workload's steps untimed for about `seconds` (a fresh filter
+    for every pass over the video, so every step is a tracking step like the
+    timed ones) so that the GPU's clocks have ramped up before the first
+    timed mode (the first mode timed in a fresh process otherwise runs its
+    pass A about 12 % slower than later modes).  Returns the steps run."""
     import ctypes
     T = frames_dev.shape[0]
     x0, y0 = centres[0]
     p = pf.make_params(w.n_particles, w.width, w.height, dtype, radius=w.radius, x0=x0, y0=y0,
                        drift=w.drift, sigma=w.sigma, seed=w.filter_seed, **variant)
-    f = pf.Filter(p)
     lib = pf.lib()
     pitch = int(frames_dev.stride(1))
     base = int(frames_dev.data_ptr())
@@ -187,12 +187,13 @@ def warm_gpu(pf, torch, frames_dev, centres, w, dtype, seconds, **variant):
     n = 0
     t_end = time.perf_counter() + seconds
     while time.perf_counter() < t_end:
-        for _ in range(32):
+        f = pf.Filter(p)
+        for t in range(1, T):
             n += 1
-            if lib.pf_step(f.handle, ptrs[(n - 1) % (T - 1) + 1], pitch):
+            if lib.pf_step(f.handle, ptrs[t], pitch):
                 raise pf.PfError(-1, pf.pf_last_error())
         torch.cuda.synchronize()
-    f.close()
+        f.close()
     return n
 
 
