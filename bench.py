@@ -296,7 +296,7 @@ def _serving_bank(torch, pfsynth, rng):
     return bank
 
 
-SERVE_HANDLES = 4096  # batch members per precision: the most streams served at once
+SERVE_HANDLES = 2048  # batch members per precision: the most streams served at once
 
 
 def _serving_pools(hbm_gb, admission="bytes"):

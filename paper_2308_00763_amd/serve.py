@@ -415,26 +415,35 @@ class GpuByteBackend(GpuPoolBackend):
     """One pf_batch per precision with `handles` members and, for the
     precision's HBM budget, a device arena from which every admitted stream
     gets exactly its workspace bytes; the member is rebound to that share
-    (pf_batch_rebind).  On release the member moves back to a one-particle
-    filter on a small parking share of its own, so that idle members hold
-    one tile of the batch's plan each."""
+    (pf_batch_rebind).  A released member is left as it is (it is not
+    stepped again, and its stale block is only read by the estimates'
+    gather, from the arena), so a release costs no device work; its tiles
+    still count against the batch's plan, which holds `plan_factor` times
+    the arena's worth of tiles plus one per member.  When an admission would
+    still overflow the plan, the idle members holding the most tiles are
+    first parked on one-particle filters on small shares of their own.
+    Free members are taken largest-stale-first, so a rebind also retires
+    the most stale tiles."""
 
-    def __init__(self, budgets: dict, handles: dict, device="cuda:0", stream=None):
+    def __init__(self, budgets: dict, handles: dict, device="cuda:0", stream=None, plan_factor: float = 2.0):
         """budgets: {dtype name: arena bytes}; handles: {dtype name: members}."""
         import torch
         self.torch = torch
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.batches, self.arenas, self.arena_mem, self.park_mem = {}, {}, {}, {}
-        self.free_handles, self.share = {}, {}
+        self.share = {}
         self.tiny = {}
+        self.free_heap = {}                    # (-stale tiles, member) of the free members
+        self.cur_tiles, self.tiles_used, self.tiles_cap = {}, {}, {}
+        self.parked = 0                        # members parked to make room in a plan
         for dt, budget in budgets.items():
             m = int(handles[dt])
             tiny = make_params(1, 64, 64, dt)
             tiny_bytes = ByteArena.rounded(pf_workspace_bytes(tiny))
-            # the most tiles the arena's bytes can hold, plus one per idle member
+            # tiles the arena's bytes can hold at most
             per_tile = pf_workspace_bytes(make_params(1 << 20, 64, 64, dt)) / 1024.0
-            cap = int(budget // per_tile) + m
+            cap = int(plan_factor * (budget // per_tile)) + m
             b = Batch([tiny] * m, device=device, stream=self.stream, max_tiles=cap)
             b._ptrs = np.zeros(m, dtype=np.uint64)
             b._pitch = np.zeros(m, dtype=np.int64)
@@ -444,9 +453,31 @@ class GpuByteBackend(GpuPoolBackend):
             self.arena_mem[dt] = torch.empty(self.arenas[dt].size, dtype=torch.uint8, device=self.device)
             self.park_mem[dt] = torch.empty(m * tiny_bytes, dtype=torch.uint8, device=self.device)
             self.tiny[dt] = (tiny, tiny_bytes)
-            self.free_handles[dt] = list(range(m))[::-1]
+            self.free_heap[dt] = [(-1, k) for k in range(m)]
+            heapq.heapify(self.free_heap[dt])
+            self.cur_tiles[dt] = [1] * m
+            self.tiles_used[dt] = m
+            self.tiles_cap[dt] = cap
         self.pool_bytes = sum(b.workspace.numel() for b in self.batches.values()) + \
             sum(t.numel() for t in self.arena_mem.values()) + sum(t.numel() for t in self.park_mem.values())
+
+    def _park(self, dt, excess):
+        """Park free members, most tiles first, until `excess` plan tiles are
+        freed; returns what is still missing."""
+        tiny, tiny_bytes = self.tiny[dt]
+        heap, cur = self.free_heap[dt], self.cur_tiles[dt]
+        parked = []
+        while excess > 0 and heap and -heap[0][0] > 1:
+            _, j = heapq.heappop(heap)
+            self.batches[dt].rebind(j, tiny, self.park_mem[dt].data_ptr() + j * tiny_bytes, tiny_bytes)
+            excess -= cur[j] - 1
+            self.tiles_used[dt] -= cur[j] - 1
+            cur[j] = 1
+            parked.append(j)
+            self.parked += 1
+        for j in parked:
+            heapq.heappush(heap, (-1, j))
+        return excess
 
     def validate(self, params):
         try:
@@ -462,31 +493,39 @@ class GpuByteBackend(GpuPoolBackend):
 
     def try_admit(self, req):
         dt = self._dtype_name(req.params.dtype)
-        if not self.free_handles[dt]:
+        heap = self.free_heap[dt]
+        if not heap:
             return None
         need = pf_workspace_bytes(req.params)
         off = self.arenas[dt].alloc(need)
         if off is None:
             return None
-        k = self.free_handles[dt].pop()
+        _, k = heapq.heappop(heap)
+        cur = self.cur_tiles[dt]
+        new_t = -(-int(req.params.n_particles) // 1024)
         try:
+            # room in the plan: the member's stale tiles go, the stream's come
+            excess = self.tiles_used[dt] - cur[k] + new_t - self.tiles_cap[dt]
+            if excess > 0 and self._park(dt, excess) > 0:
+                self.arenas[dt].release(off, need)
+                heapq.heappush(heap, (-cur[k], k))
+                return None
             self.batches[dt].rebind(k, req.params, self.arena_mem[dt].data_ptr() + off,
                                     ByteArena.rounded(need))
         except PfError:
             self.arenas[dt].release(off, need)
-            self.free_handles[dt].append(k)
+            heapq.heappush(heap, (-cur[k], k))
             raise
+        self.tiles_used[dt] += new_t - cur[k]
+        cur[k] = new_t
         self.share[(dt, k)] = (off, need)
         return (dt, k)
 
     def release(self, slot):
         dt, k = slot
         off, need = self.share.pop(slot)
-        tiny, tiny_bytes = self.tiny[dt]
-        # park the member before its range goes back to the arena
-        self.batches[dt].rebind(k, tiny, self.park_mem[dt].data_ptr() + k * tiny_bytes, tiny_bytes)
         self.arenas[dt].release(off, need)
-        self.free_handles[dt].append(k)
+        heapq.heappush(self.free_heap[dt], (-self.cur_tiles[dt][k], k))
 
     def high_water(self):
         return sum(a.high for a in self.arenas.values())

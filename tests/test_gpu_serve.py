@@ -92,12 +92,15 @@ def _stream_requests(n_streams, seed):
     return out
 
 
-def test_streams_through_a_byte_budget_equal_alone_runs():
-    # budgets that hold a few streams at a time: admission waits for bytes
+@pytest.mark.parametrize("plan_factor", [2.0, 0.5])
+def test_streams_through_a_byte_budget_equal_alone_runs(plan_factor):
+    # budgets that hold a few streams at a time: admission waits for bytes;
+    # with half the arena's worth of tiles in the plan, idle members' stale
+    # tiles must be parked to admit new streams
     clk = _Clock()
     budgets = {"f16": 3 * pf.pf_workspace_bytes(pf.make_params(60000, 64, 64, "f16")),
                "f32": 2 * pf.pf_workspace_bytes(pf.make_params(60000, 64, 64, "f32"))}
-    be = GpuByteBackend(budgets, {"f16": 6, "f32": 4})
+    be = GpuByteBackend(budgets, {"f16": 6, "f32": 4}, plan_factor=plan_factor)
     s = Scheduler(be, clock=clk, stall_timeout=10.0)
     reqs = _stream_requests(16, seed=12)
     for r, _ in reqs:
@@ -109,6 +112,8 @@ def test_streams_through_a_byte_budget_equal_alone_runs():
     assert sum(1 for r in s.results.values() if r.admission_wait > 0) > 0
     assert be.in_use() == 0 and all(a.starts == [0] for a in be.arenas.values())
     assert summ["hbm_high_water_bytes"] <= sum(budgets.values())
+    for dt in be.batches:  # the members' tiles as the backend counts them stay within the plan
+        assert be.tiles_used[dt] == sum(be.cur_tiles[dt]) <= be.tiles_cap[dt]
     for r, dev in reqs:
         f = pf.Filter(r.params)
         ests = []
@@ -169,3 +174,44 @@ def test_rebind_to_caller_shares_and_its_refusals():
     b.reinit(0, pf.make_params(40000, 64, 64, "f16", x0=5, y0=6))
     assert pf.pf_estimate(b.filter(0)) == (5.0, 6.0)
     b.close()
+
+
+def test_idle_members_are_parked_when_the_plan_is_full():
+    # three handles, a budget and a plan for two 20000-particle streams (20
+    # tiles each): after A and B finish their members keep 20 stale tiles
+    # each, so admitting C (30000 particles, 30 tiles) on one of them must
+    # park the other; C then runs exactly as it does alone
+    T = 5
+    reqs = _stream_requests(3, seed=21)
+    ps = []
+    for sid, (r, dev) in enumerate(reqs):
+        p = pf.make_params(30000 if sid == 2 else 20000, r.params.width, r.params.height, "f16",
+                           x0=r.params.x0, y0=r.params.y0, drift=(r.params.drift_x, r.params.drift_y),
+                           seed=4, stream_id=sid)
+        ps.append((StreamRequest(sid, 0.0, p, T, 30.0, r.frame), dev))
+    budget = 2 * pf.pf_workspace_bytes(ps[0][0].params)
+    be = GpuByteBackend({"f16": budget}, {"f16": 3}, plan_factor=1.0)
+    assert 41 <= be.tiles_cap["f16"] < 51
+    sa = be.try_admit(ps[0][0])
+    sb = be.try_admit(ps[1][0])
+    assert sa is not None and sb is not None
+    assert be.try_admit(ps[2][0]) is None          # the bytes are taken
+    be.release(sa)
+    be.release(sb)
+    assert be.parked == 0
+    sc = be.try_admit(ps[2][0])
+    assert sc is not None and be.parked >= 1
+    assert be.tiles_used["f16"] == sum(be.cur_tiles["f16"]) <= be.tiles_cap["f16"]
+    r, dev = ps[2]
+    ests = []
+    for t in range(1, T):
+        assert not be.step([(sc, dev[t])])
+        ests.append(be.estimates([sc])[0])
+    f = pf.Filter(r.params)
+    alone = []
+    for t in range(1, T):
+        f.step(dev[t])
+        alone.append(f.estimate())
+    f.close()
+    assert np.array_equal(np.array(ests), np.array(alone))
+    be.close()
