@@ -319,7 +319,7 @@ def _serving_request(pf, rng, bank, sid, arrival, fps, frames=None):
     """One stream of the serving mix: frames ~ U{20..500} (or `frames`), side
     ~ U{64, ..., 1024}, N = round(exp(U(ln 1e3, ln 1e6))), FP16 or FP32 with
     probability 1/2, from a random bank video at a random start frame."""
-    from paper_2308_00763_amd.serve import StreamRequest
+    from paper_2308_00763_amd.serve import FrameSeq, StreamRequest
     frames = int(rng.integers(20, 501)) if frames is None else frames
     side = int(rng.choice(SERVE_SIDES))
     j = int(rng.integers(0, 4))
@@ -331,8 +331,7 @@ def _serving_request(pf, rng, bank, sid, arrival, fps, frames=None):
     p = pf.make_params(n, side, side, dtype, x0=cen[o][0], y0=cen[o][1], drift=(d[0], d[1]),
                        seed=5, stream_id=sid)
     base, fst, pitch = int(vid.data_ptr()), int(vid.stride(0)), int(vid.stride(1))
-    return StreamRequest(sid, arrival, p, frames, fps,
-                         lambda i, b=base + o * fst, s=fst, q=pitch: (b + i * s, q))
+    return StreamRequest(sid, arrival, p, frames, fps, FrameSeq(base + o * fst, fst, pitch))
 
 
 def run_serving(pf, torch, pfsynth, seconds, warmup_s, rate=200.0, fps=30.0, hbm_gb=(6.0, 12.0),

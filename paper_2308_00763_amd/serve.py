@@ -67,12 +67,107 @@ class StreamRequest:
 
 
 @dataclass
+class FrameSeq:
+    """Frames at a fixed stride in device memory: frame i starts at
+    base + i * stride, its rows `pitch` bytes apart.  A frame source like any
+    other (calling it gives the (pointer, pitch) pair); over a backend with
+    the array calls (step_arrays) the scheduler steps such streams from
+    columns of numbers, with no per-stream Python work in a tick."""
+    base: int
+    stride: int
+    pitch: int
+
+    def __call__(self, i):
+        return (self.base + i * self.stride, self.pitch)
+
+
+@dataclass
 class _Live:
     req: StreamRequest
     slot: object
     admitted: float
     next_frame: int = 1
     estimates: list = field(default_factory=list)
+    row: int = -1  # row in the scheduler's column table (FrameSeq streams), or -1
+
+
+class _Columns:
+    """The FrameSeq streams being served, one row each: the numbers a tick
+    needs, as arrays, and their estimates in one store (each stream a
+    contiguous run of n_frames - 1 rows, compacted when the store is full)."""
+
+    def __init__(self, cap: int = 1024):
+        self.cap = 0
+        self.rows_top = 0
+        self.free = []
+        self._grow(cap)
+        self.est = np.zeros((4 * cap, 2))
+        self.top = 0
+
+    def _grow(self, cap):
+        def ext(a, dtype):
+            out = np.zeros(cap, dtype=dtype)
+            if a is not None:
+                out[:a.size] = a
+            return out
+        g = lambda name: getattr(self, name, None)  # noqa: E731
+        self.used = ext(g("used"), bool)
+        self.sid = ext(g("sid"), np.int64)
+        self.code = ext(g("code"), np.int64)
+        self.member = ext(g("member"), np.int64)
+        self.nxt = ext(g("nxt"), np.int64)
+        self.nfr = ext(g("nfr"), np.int64)
+        self.arr = ext(g("arr"), np.float64)
+        self.fps = ext(g("fps"), np.float64)
+        self.due = ext(g("due"), np.float64)
+        self.base = ext(g("base"), np.int64)
+        self.stride = ext(g("stride"), np.int64)
+        self.pitch = ext(g("pitch"), np.int64)
+        self.npart = ext(g("npart"), np.int64)
+        self.eoff = ext(g("eoff"), np.int64)
+        self.cap = cap
+
+    def _alloc_est(self, m):
+        if self.top + m > self.est.shape[0]:
+            rows = np.flatnonzero(self.used)
+            need = int((self.nfr[rows] - 1).sum()) + m
+            new = np.zeros((max(self.est.shape[0], 2 * need), 2))
+            pos = 0
+            for r in rows:  # compaction: rare, a copy per live stream
+                k = int(self.nxt[r]) - 1  # estimates written so far
+                new[pos:pos + k] = self.est[self.eoff[r]:self.eoff[r] + k]
+                self.eoff[r] = pos
+                pos += int(self.nfr[r]) - 1
+            self.est, self.top = new, pos
+        off = self.top
+        self.top += m
+        return off
+
+    def add(self, sid, code, member, req, fs):
+        if self.free:
+            r = self.free.pop()
+        else:
+            if self.rows_top == self.cap:
+                self._grow(2 * self.cap)
+            r = self.rows_top
+            self.rows_top += 1
+        self.used[r] = True
+        self.sid[r], self.code[r], self.member[r] = sid, code, member
+        self.nxt[r], self.nfr[r] = 1, req.n_frames
+        self.arr[r], self.fps[r] = req.arrival, req.fps
+        self.due[r] = req.arrival + 1.0 / req.fps
+        self.base[r], self.stride[r], self.pitch[r] = fs.base, fs.stride, fs.pitch
+        self.npart[r] = req.params.n_particles
+        self.eoff[r] = self._alloc_est(max(req.n_frames - 1, 0))
+        return r
+
+    def estimates_of(self, r):
+        k = int(self.nxt[r]) - 1
+        return self.est[self.eoff[r]:self.eoff[r] + k].copy()
+
+    def remove(self, r):
+        self.used[r] = False
+        self.free.append(r)
 
 
 @dataclass
@@ -98,6 +193,8 @@ class Scheduler:
         self.queue = deque()         # arrived requests waiting for a slot
         self.due = []                # heap of (next frame's arrival, sid) of admitted streams
         self.live = {}               # sid -> _Live
+        # FrameSeq streams step from columns when the backend has array calls
+        self.cols = _Columns() if hasattr(backend, "step_arrays") else None
         self.results = {}            # sid -> StreamResult
         self.latencies = []          # per processed frame: ready - arrival (seconds)
         self.updates = 0             # particle updates done
@@ -131,13 +228,22 @@ class Scheduler:
             if slot is None:
                 waiting.append(req)
                 continue
-            self.live[req.sid] = _Live(req, slot, now)
-            heapq.heappush(self.due, (req.arrival + 1.0 / req.fps, req.sid))
+            lv = _Live(req, slot, now)
+            self.live[req.sid] = lv
+            if self.cols is not None and isinstance(req.frame, FrameSeq) and req.n_frames > 1:
+                code, member = self.backend.slot_code(slot)
+                lv.row = self.cols.add(req.sid, code, member, req, req.frame)
+            else:
+                heapq.heappush(self.due, (req.arrival + 1.0 / req.fps, req.sid))
         self.queue = waiting
 
     def _finish(self, lv: _Live, status: str, reason: str = ""):
         self.backend.release(lv.slot)
         del self.live[lv.req.sid]
+        if lv.row >= 0:
+            lv.next_frame = int(self.cols.nxt[lv.row])
+            lv.estimates = self.cols.estimates_of(lv.row)
+            self.cols.remove(lv.row)
         self.results[lv.req.sid] = StreamResult(
             lv.req.sid, status, reason, lv.admitted - lv.req.arrival, lv.next_frame - 1, lv.estimates)
 
@@ -172,6 +278,8 @@ class Scheduler:
             work.append((lv, fr, t_arr))
         for item in retry:
             heapq.heappush(self.due, item)
+        if self.cols is not None:
+            return self._step_arrays(work, now)
         if not work:
             return 0
         t0 = self.clock()
@@ -184,15 +292,71 @@ class Scheduler:
             if lv.slot in failed:
                 self._finish(lv, "failed", failed[lv.slot])
                 continue
-            self.latencies.append(done - t_arr)
-            self.updates += lv.req.params.n_particles
-            lv.estimates.append(est)
-            lv.next_frame += 1
-            if lv.next_frame >= lv.req.n_frames:
-                self._finish(lv, "done")
-            else:
-                heapq.heappush(self.due, (lv.req.arrival + lv.next_frame / lv.req.fps, lv.req.sid))
+            self._advance(lv, est, done - t_arr)
         return len(work)
+
+    def _advance(self, lv, est, latency):
+        self.latencies.append(latency)
+        self.updates += lv.req.params.n_particles
+        lv.estimates.append(est)
+        lv.next_frame += 1
+        if lv.next_frame >= lv.req.n_frames:
+            self._finish(lv, "done")
+        else:
+            heapq.heappush(self.due, (lv.req.arrival + lv.next_frame / lv.req.fps, lv.req.sid))
+
+    def _step_arrays(self, work, now):
+        """One tick through the backend's array calls: the heap's streams
+        (`work`) and every FrameSeq stream whose next frame has arrived, in
+        one batched step per pool."""
+        c = self.cols
+        rows = np.flatnonzero(c.used[:c.rows_top] & (c.due[:c.rows_top] <= now))
+        ng = len(work)
+        if ng == 0 and rows.size == 0:
+            return 0
+        codes = np.empty(ng + rows.size, dtype=np.int64)
+        members = np.empty_like(codes)
+        ptrs = np.empty_like(codes)
+        pitches = np.empty_like(codes)
+        for j, (lv, fr, _) in enumerate(work):
+            codes[j], members[j] = self.backend.slot_code(lv.slot)
+            if isinstance(fr, tuple):
+                ptrs[j], pitches[j] = fr
+            else:
+                ptrs[j], pitches[j] = fr.data_ptr(), fr.stride(0)
+        nx = c.nxt[rows]
+        codes[ng:] = c.code[rows]
+        members[ng:] = c.member[rows]
+        ptrs[ng:] = c.base[rows] + nx * c.stride[rows]
+        pitches[ng:] = c.pitch[rows]
+        t0 = self.clock()
+        failed = self.backend.step_arrays(codes, members, ptrs, pitches)  # {item index: reason}
+        ests = self.backend.estimates_arrays(codes, members)
+        done = self.clock()
+        self.step_seconds += done - t0
+        self.ticks += 1
+        for j, (lv, _, t_arr) in enumerate(work):
+            if j in failed:
+                self._finish(lv, "failed", failed[j])
+            else:
+                self._advance(lv, tuple(ests[j]), done - t_arr)
+        if rows.size:
+            ok = np.ones(rows.size, dtype=bool)
+            for j in failed:
+                if j >= ng:
+                    ok[j - ng] = False
+            good, nxg = rows[ok], nx[ok]
+            t_arr = c.arr[good] + nxg / c.fps[good]
+            self.latencies.extend((done - t_arr).tolist())
+            self.updates += int(c.npart[good].sum())
+            c.est[c.eoff[good] + nxg - 1] = ests[ng:][ok]
+            c.nxt[good] = nxg + 1
+            c.due[good] = c.arr[good] + (nxg + 1) / c.fps[good]
+            for j in np.flatnonzero(~ok):
+                self._finish(self.live[int(c.sid[rows[j]])], "failed", failed[ng + int(j)])
+            for r in good[nxg + 1 >= c.nfr[good]]:
+                self._finish(self.live[int(c.sid[r])], "done")
+        return ng + rows.size
 
     def idle(self):
         return not self.pending and not self.queue and not self.live
@@ -347,6 +511,42 @@ class GpuPoolBackend:
         for dt in {s[0] for s in slots}:
             out[dt] = self.batches[dt].estimates()
         return [tuple(out[dt][k]) for dt, k in slots]
+
+    # -- array calls: one column per item ------------------------------------
+    _CODE = {"f64": PF_F64, "f32": PF_F32, "f16": PF_F16, "bf16": PF_BF16}
+
+    def slot_code(self, slot):
+        """(pool code, member) of a slot, for the array calls."""
+        return self._CODE[slot[0]], slot[1]
+
+    def step_arrays(self, codes, members, ptrs, pitches):
+        """Step member members[j] of pool codes[j] on the frame at ptrs[j]
+        (row pitch pitches[j]): one pf_batch_step per pool.  Returns {j:
+        error text} for the items whose pool's step failed."""
+        failed = {}
+        for code in np.unique(codes):
+            dt = self._dtype_name(int(code))
+            b = self.batches[dt]
+            m = codes == code
+            ks = members[m]
+            b._active[:] = 0
+            b._active[ks] = 1
+            b._ptrs[ks] = ptrs[m].astype(np.uint64)
+            b._pitch[ks] = pitches[m]
+            try:
+                b.step_ptrs(b._ptrs, b._pitch, b._active)
+            except PfError as e:
+                for j in np.flatnonzero(m):
+                    failed[int(j)] = str(e)
+        return failed
+
+    def estimates_arrays(self, codes, members):
+        """The latest estimates of the items, as an (items, 2) array."""
+        out = np.empty((codes.size, 2))
+        for code in np.unique(codes):
+            m = codes == code
+            out[m] = self.batches[self._dtype_name(int(code))].estimates()[members[m]]
+        return out
 
     def high_water(self):
         return self.high

@@ -81,3 +81,51 @@ class FakeBackend:
 
     def high_water(self):
         return self.high
+
+
+class ArrayFakeBackend(FakeBackend):
+    """FakeBackend with the array calls of the GPU backends, for FrameSeq
+    streams: a frame "pointer" is stream_key << 32 | i << 20, resolved to
+    frame i of the host video registered under that key."""
+
+    STRIDE = 1 << 20
+
+    def __init__(self, caps, clock, fail_on=None, step_cost=0.002):
+        super().__init__(caps, clock, fail_on=fail_on, step_cost=step_cost)
+        self.videos = {}      # key -> (T, H, W) frames
+        self.ids = {}         # member id -> slot
+        self.next_id = 0
+        self.array_steps = 0
+
+    def frame_seq(self, key, frames):
+        from paper_2308_00763_amd.serve import FrameSeq
+        self.videos[key] = frames
+        return FrameSeq(key << 32, self.STRIDE, frames.shape[2])
+
+    def slot_code(self, slot):
+        for k, s in self.ids.items():
+            if s == slot:
+                return 0, k
+        self.ids[self.next_id] = slot
+        self.next_id += 1
+        return 0, self.next_id - 1
+
+    def release(self, slot):
+        self.ids = {k: s for k, s in self.ids.items() if s != slot}
+        super().release(slot)
+
+    def _frame(self, ptr):
+        key = int(ptr) >> 32
+        return self.videos[key][(int(ptr) - (key << 32)) // self.STRIDE]
+
+    def step_arrays(self, codes, members, ptrs, pitches):
+        """Every item is a FrameSeq stream's frame (the tests give this
+        backend no other kind)."""
+        self.array_steps += 1
+        slots = [self.ids[int(k)] for k in members]
+        assert all(int(q) == self.videos[int(p) >> 32].shape[2] for p, q in zip(ptrs, pitches))
+        failed = self.step([(s, self._frame(p)) for s, p in zip(slots, ptrs)])
+        return {j: failed[s] for j, s in enumerate(slots) if s in failed}
+
+    def estimates_arrays(self, codes, members):
+        return np.array(self.estimates([self.ids[int(k)] for k in members]), dtype=float)

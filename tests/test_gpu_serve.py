@@ -7,7 +7,7 @@ import torch
 
 import paper_2308_00763_amd as pf
 import pfsynth
-from paper_2308_00763_amd.serve import GpuByteBackend, GpuPoolBackend, Scheduler, StreamRequest
+from paper_2308_00763_amd.serve import FrameSeq, GpuByteBackend, GpuPoolBackend, Scheduler, StreamRequest
 
 pytestmark = pytest.mark.gpu
 
@@ -214,4 +214,32 @@ def test_idle_members_are_parked_when_the_plan_is_full():
         alone.append(f.estimate())
     f.close()
     assert np.array_equal(np.array(ests), np.array(alone))
+    be.close()
+
+
+def test_frameseq_streams_through_the_byte_backend_equal_alone_runs():
+    # FrameSeq sources: the scheduler steps these streams from its columns
+    # through the backend's array calls
+    clk = _Clock()
+    budgets = {"f16": 3 * pf.pf_workspace_bytes(pf.make_params(60000, 64, 64, "f16")),
+               "f32": 2 * pf.pf_workspace_bytes(pf.make_params(60000, 64, 64, "f32"))}
+    be = GpuByteBackend(budgets, {"f16": 6, "f32": 4})
+    s = Scheduler(be, clock=clk, stall_timeout=10.0)
+    reqs = _stream_requests(12, seed=31)
+    for r, dev in reqs:
+        r.frame = FrameSeq(dev.data_ptr(), dev.stride(0), dev.stride(1))
+        assert s.submit(r)
+    print("[serve] frameseq running", flush=True)
+    summ = s.run(until=1e6, sleep=clk.sleep, poll=0.002)
+    print(f"[serve] {summ}", flush=True)
+    assert summ["streams"] == {"done": 12}
+    assert not s.due and not s.cols.used.any()
+    for r, dev in reqs:
+        f = pf.Filter(r.params)
+        ests = []
+        for i in range(1, r.n_frames):
+            f.step(dev[i])
+            ests.append(f.estimate())
+        f.close()
+        assert np.array_equal(np.array(ests), np.array(s.results[r.sid].estimates)), r.sid
     be.close()

@@ -120,3 +120,91 @@ def test_slot_plan_fits_the_budget():
     plan = plan_pool(2 << 30, "f16", caps)
     used = sum(pf.pf_workspace_bytes(pf.make_params(c, 64, 64, "f16")) * k for c, k in plan.items())
     assert used <= 2 << 30 and used > 0.9 * (2 << 30)
+
+
+# ---------------------------------------------------------------------------
+# FrameSeq streams over a backend with the array calls: the scheduler keeps
+# them in columns and steps them with no per-stream Python work; the results
+# must be those of the generic path.
+
+from paper_2308_00763_amd.serve import FrameSeq  # noqa: E402
+from serve_fake import ArrayFakeBackend  # noqa: E402
+
+
+def _array_sched(caps, fail_on=None, step_cost=0.002, stall_timeout=0.5):
+    clk = VirtualClock()
+    be = ArrayFakeBackend(caps, clk, fail_on=fail_on, step_cost=step_cost)
+    return Scheduler(be, clock=clk, stall_timeout=stall_timeout), clk, be
+
+
+def _seq_stream(be, sid, arrival, n=300, frames=6, fps=10.0):
+    r, vid = _stream(sid, arrival, n=n, frames=frames, fps=fps)
+    r.frame = be.frame_seq(sid + 1, vid.frames)
+    assert isinstance(r.frame, FrameSeq)
+    return r, vid
+
+
+def test_column_streams_match_the_oracle_run_alone():
+    s, clk, be = _array_sched({512: 3})
+    reqs = [_seq_stream(be, i, 0.05 * i, frames=5 + i) for i in range(5)]
+    for r, _ in reqs:
+        assert s.submit(r)
+    s.run(until=100.0, sleep=clk.sleep)
+    assert be.array_steps > 0 and not s.due  # every stream went through the columns
+    for r, vid in reqs:
+        res = s.results[r.sid]
+        assert res.status == "done" and res.frames_done == r.n_frames - 1
+        ref = oracle.run(oracle.make_params(r.params.n_particles, SIDE, SIDE, radius=5,
+                                            drift=(r.params.drift_x, r.params.drift_y),
+                                            seed=0, stream_id=r.sid),
+                         vid.frames, 30, 34)
+        assert np.array_equal(np.array(res.estimates), ref[0][1:])
+    assert be.in_use == 0
+
+
+def test_column_latency_and_updates():
+    s, clk, be = _array_sched({512: 1}, step_cost=0.01)
+    r, _ = _seq_stream(be, 0, 0.0, frames=5)
+    s.submit(r)
+    summ = s.run(until=100.0, sleep=clk.sleep, poll=0.001)
+    lat = np.array(s.latencies)
+    assert lat.size == 4
+    assert np.all(lat >= 0.01 - 1e-12) and np.all(lat <= 0.011 + 1e-9)
+    assert summ["frames"] == 4 and summ["particle_updates"] == 4 * 300
+
+
+def test_column_step_failure_fails_only_that_stream():
+    s, clk, be = _array_sched({512: 2}, fail_on={0: 2})
+    a, _ = _seq_stream(be, 0, 0.0)
+    b, _ = _seq_stream(be, 1, 0.0)
+    s.submit(a)
+    s.submit(b)
+    s.run(until=100.0, sleep=clk.sleep)
+    assert s.results[0].status == "failed" and s.results[0].frames_done == 1
+    assert s.results[1].status == "done" and s.results[1].frames_done == 5
+
+
+def test_column_store_compaction_keeps_every_estimate():
+    # many short streams through few slots: rows and estimate runs are
+    # reused and the store is compacted while streams are live
+    s, clk, be = _array_sched({512: 4}, step_cost=0.0005)
+    s.cols.est = np.zeros((8, 2))  # a tiny store: compaction on most admissions
+    reqs = [_seq_stream(be, i, 0.01 * i, n=64, frames=3 + i % 5) for i in range(24)]
+    for r, _ in reqs:
+        s.submit(r)
+    s.run(until=1000.0, sleep=clk.sleep)
+    for r, vid in reqs:
+        res = s.results[r.sid]
+        assert res.status == "done" and res.frames_done == r.n_frames - 1
+        ref = oracle.run(oracle.make_params(64, SIDE, SIDE, radius=5, drift=(r.params.drift_x, r.params.drift_y),
+                                            seed=0, stream_id=r.sid), vid.frames, 30, 34)
+        assert np.array_equal(np.array(res.estimates), ref[0][1:]), r.sid
+    assert not s.cols.used.any()
+
+
+def test_single_frame_stream_finishes_without_a_step():
+    s, clk, be = _array_sched({512: 1})
+    r, _ = _seq_stream(be, 0, 0.0, frames=1)
+    s.submit(r)
+    s.run(until=100.0, sleep=clk.sleep)
+    assert s.results[0].status == "done" and s.results[0].frames_done == 0
