@@ -1983,57 +1983,90 @@ __global__ __launch_bounds__(NT) void combine_batch_kernel(BatchArgs b)
     combine_filter<DT, KPER, NT>(a);
 }
 
+// A filter's arguments by its index in the batch (pass C needs no entry
+// fields: no frame, pitch or step index).
+__device__ __forceinline__ StepArgs batch_args_of(const BatchArgs& b, int fid)
+{
+    StepArgs a;
+    const cst_t<uint32_t>* src = reinterpret_cast<const cst_t<uint32_t>*>(cst(b.args) + fid);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&a);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(StepArgs) / 4); ++i) dst[i] = src[i];
+    return a;
+}
+
 // Batched pass C over a grid of G <= b.tiles workgroups, streaming as the
 // single-filter kernel does: workgroup g takes grid tiles g, g + G, ... of
-// whatever filters they belong to, loading each tile's arguments and inputs
-// while it scatters the one before.
+// whatever filters they belong to.  A grid tile's arguments take three
+// dependent scalar loads (its map word, its entry, its filter's arguments),
+// so they are pipelined over the stream: while tile t is filled, the inputs
+// and slot-map words of t + G are in flight (issued from its arguments,
+// complete since the last tile), and so are the arguments of t + 2G, the
+// entry of t + 3G and the map word of t + 4G -- one round trip, not three,
+// in front of each tile.  A tile past its filter's tiles (a plan captured
+// before a smaller re-initialisation) is skipped.
 template <int DT>
 __global__ __launch_bounds__(pass_c_threads(DT, 1 << 30), 6) void pass_c_batch_kernel(BatchArgs b)
 {
     constexpr int BC = pass_c_threads(DT, 1 << 30);
     __shared__ PassCLds<DT> lds;
-    const int G = gridDim.x;
-    // a grid tile's filter arguments and tile index in its filter
-    // (past the filter's tiles: a plan captured before a smaller
-    // re-initialisation; such a tile is skipped)
-    auto resolve = [&](int gt, StepArgs& a, int& lt) {
-        const int e = tile_entry_of(b, gt);
-        a = batch_args(b, e);
-        lt = gt - tile_base_of(b, e);
-    };
-    int gt = blockIdx.x;
-    StepArgs a;
-    int lt;
-    resolve(gt, a, lt);
+    const int G = gridDim.x, T = b.tiles;
+    const int g0 = blockIdx.x;  // < T: the grid has at most T workgroups
+    // tile g0: everything now
+    int e = tile_entry_of(b, g0);
+    StepArgs a0 = batch_args_of(b, cst(b.entries)[e].fid);
+    int lt0 = g0 - tile_base_of(b, e);
     PassCIn<DT, BC> cur;
     TileSlotsT<DT> ts;
-    if (lt < a.ntiles) {
+    if (lt0 < a0.ntiles) {
         typename TileSlotsT<DT>::Raw r0;
-        r0.load(a, lt);
-        cur.load(a, lt);
+        r0.load(a0, lt0);
+        cur.load(a0, lt0);
         cur.settle();
         ts = TileSlotsT<DT>(r0);
     }
-    for (;;) {
-        const int gn = gt + G;
-        StepArgs an;
-        int ln = 0;
+    // tile g0 + G: its arguments; g0 + 2G: its entry's filter and first
+    // tile; g0 + 3G: its entry index (each stage only for tiles of the grid)
+    StepArgs a1 = a0;
+    int lt1 = 0, fid2 = 0, base2 = 0, e3 = 0;
+    if (g0 + G < T) {
+        e = tile_entry_of(b, g0 + G);
+        a1 = batch_args_of(b, cst(b.entries)[e].fid);
+        lt1 = g0 + G - tile_base_of(b, e);
+    }
+    if (g0 + 2 * G < T) {
+        e = tile_entry_of(b, g0 + 2 * G);
+        fid2 = cst(b.entries)[e].fid;
+        base2 = tile_base_of(b, e);
+    }
+    if (g0 + 3 * G < T) e3 = tile_entry_of(b, g0 + 3 * G);
+    for (int g = g0;; g += G) {
+        const int g1 = g + G, g2 = g + 2 * G, g3 = g + 3 * G, g4 = g + 4 * G;
         typename TileSlotsT<DT>::Raw rn;
         PassCIn<DT, BC> nxt;
-        if (gn < b.tiles) {  // uniform
-            resolve(gn, an, ln);
-            if (ln < an.ntiles) {
-                rn.load(an, ln);
-                nxt.load(an, ln);
-            }
+        if (g1 < T && lt1 < a1.ntiles) {  // uniform: the next tile's words and inputs
+            rn.load(a1, lt1);
+            nxt.load(a1, lt1);
         }
-        if (lt < a.ntiles) pass_c_run<DT, BC>(a, lt, lds, cur, ts);
-        if (gn >= b.tiles) break;
-        gt = gn;
-        a = an;
-        lt = ln;
+        StepArgs a2 = a1;
+        int fid3 = 0, base3 = 0, e4 = 0;
+        if (g2 < T) a2 = batch_args_of(b, fid2);
+        if (g3 < T) {
+            fid3 = cst(b.entries)[e3].fid;
+            base3 = tile_base_of(b, e3);
+        }
+        if (g4 < T) e4 = tile_entry_of(b, g4);
+        if (lt0 < a0.ntiles) pass_c_run<DT, BC>(a0, lt0, lds, cur, ts);
+        if (g1 >= T) break;
+        a0 = a1;
+        lt0 = lt1;
         cur = nxt;
-        if (lt < a.ntiles) ts = TileSlotsT<DT>(rn);
+        if (lt0 < a0.ntiles) ts = TileSlotsT<DT>(rn);
+        a1 = a2;
+        lt1 = g2 - base2;
+        fid2 = fid3;
+        base2 = base3;
+        e3 = e4;
     }
 }
 
