@@ -27,7 +27,7 @@
  *     frame are clamped to the nearest edge.
  *   - Random numbers come from the counter-based Philox4x32-10 generator
  *     (Salmon et al., SC'11) and Box-Muller; the paper draws in double and
- *     converts (Sec. 4, after Eq. (2)); the counter layout is this build's.
+ *     converts (Sec. 4, after Eq. (2)); the counter layout is this implementation's.
  *
  * parity pinned: Philox against numpy's Philox4x64-10 (same code, 64-bit
  * words) and known-answer values; every other function by closed forms,
@@ -102,7 +102,7 @@ void or_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out
     out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
 }
 
-/* Counter layout of the random streams (this build's choice; the paper only
+/* Counter layout of the random streams (this implementation's choice; the paper only
  * says one seed is shared across precisions, Sec. 5):
  *   particle draw of particle k at step t: ctr = (k, t, stream_id, 0)
  *   resampling offset of step t:           ctr = (0, t, stream_id, 1)
@@ -294,7 +294,7 @@ void or_reweight_resample(int64_t n, const double *L, const double *w_prev,
  * step proposes a particle i uniformly and moves there with probability
  * min(1, w_i / w_k) = min(1, exp(L_i - L_k)).  Only ratios of weights enter:
  * no maximum, sum or cumulative distribution.
- * Random numbers of slot j at step t (this build's layout): steps b = 2m and
+ * Random numbers of slot j at step t (this implementation's layout): steps b = 2m and
  * 2m + 1 share ctr = (j, t, stream_id, 2 + m); step 2m uses words 0 and 1,
  * step 2m + 1 words 2 and 3; the first picks i = floor(word * n / 2^32), the
  * second gives u = (word + 1/2) 2^-32 in (0, 1), and the move is taken when
@@ -341,7 +341,7 @@ void or_metropolis(int64_t n, const double *L, int32_t B, uint64_t seed, uint32_
  * expected number of trials of slot j is 1 + (1 - r_j) N w_max / sum(w).
  * At most `cap` trials: a slot that rejects all of them keeps the particle
  * of its last trial (a bias the cap bounds).
- * Random numbers of slot j at step t (this build's layout): trials m = 2q
+ * Random numbers of slot j at step t (this implementation's layout): trials m = 2q
  * and 2q + 1 share ctr = (j, t, stream_id, 2 + q); trial 2q uses words 0
  * and 1, trial 2q + 1 words 2 and 3; the first word gives u = (word + 1/2)
  * 2^-32, the test u <= exp(L_c - M), and the second the next proposal

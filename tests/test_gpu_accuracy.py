@@ -81,7 +81,7 @@ BF16_BOUNCE_RMS_PX = 1.37
 
 @pytest.mark.parametrize("dtype", ["f16", pytest.param("bf16", marks=pytest.mark.skip(
     reason=f"BF16 track RMS vs FP64 measured {BF16_BOUNCE_RMS_PX} px > 0.5 px on the 128-particle "
-           f"bounce video (positions rounded to 8 significant bits); stated in DESIGN.md"))])
+           f"bounce video (positions rounded to 8 significant bits): a known failure of the mode"))])
 def test_bounce_track_within_half_pixel_of_fp64(dtype):
     _, _, tr = _bounce_tracks()
     r = _rms(tr[dtype], tr["f64"])
