@@ -54,6 +54,42 @@ __device__ __forceinline__ gbl_t<T>* gbl(T* p)
 {
     return (gbl_t<T>*)p;
 }
+
+// The bulk outputs that the next kernel reads (pass A's propagated positions
+// and tile prefix sums, pass C's resampled state) of a small single filter in
+// a 16-bit mode (StepArgs::wt) are stored at device scope: such stores are
+// written through the XCD's L2, so the release that ends the kernel finds none
+// of them dirty there to write back, and the next kernel, on any XCD, reads
+// them from memory as it would in any case.  That pays where the kernels are
+// short (2^20 FP16: 19.6 against 21.0 us per step) and costs where they are
+// large or the stores wide (2^24 FP16 +2 %, the 4096-stream batch +20 %, FP32
+// and FP64 at 2^20 +6 % and +53 %: the written-through partial lines), so the
+// kernels that use it (WT) are separate instantiations, launched for 16-bit
+// filters of at most 1024 tiles stepped alone at the default sizes.
+template <bool WT, typename T>
+__device__ __forceinline__ void put(gbl_t<T>* p, const T& v)
+{
+    static_assert(sizeof(T) == 2 || sizeof(T) == 4 || sizeof(T) % 8 == 0, "store width");
+    if constexpr (!WT) {
+        *p = v;
+    } else if constexpr (sizeof(T) == 2) {
+        uint16_t b;
+        __builtin_memcpy(&b, &v, 2);
+        __hip_atomic_store(reinterpret_cast<gbl_t<uint16_t>*>(p), b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else if constexpr (sizeof(T) == 4) {
+        uint32_t b;
+        __builtin_memcpy(&b, &v, 4);
+        __hip_atomic_store(reinterpret_cast<gbl_t<uint32_t>*>(p), b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+#pragma unroll
+        for (int i = 0; i < (int)(sizeof(T) / 8); ++i) {
+            uint64_t b;
+            __builtin_memcpy(&b, reinterpret_cast<const char*>(&v) + 8 * i, 8);
+            __hip_atomic_store(reinterpret_cast<gbl_t<uint64_t>*>(p) + i, b, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
 // Tile records through such pointers, member by member (a structure's
 // implicit copy does not bind to global-memory references).
 __device__ __forceinline__ TileRec64 load_rec(const gbl_t<const TileRec64>* p)
@@ -193,12 +229,12 @@ struct ModeT<PF_F64> {
             v[2 * i] = a.x; v[2 * i + 1] = a.y;
         }
     }
-    template <int PPT>
+    template <int PPT, bool WT = false>
     static __device__ __forceinline__ void store(void* p, int k0, const Val* v)
     {
         auto* q = gbl(reinterpret_cast<double2_t*>(static_cast<double*>(p) + k0));
 #pragma unroll
-        for (int i = 0; i < PPT / 2; ++i) q[i] = double2_t{v[2 * i], v[2 * i + 1]};
+        for (int i = 0; i < PPT / 2; ++i) put<WT>(q + i, double2_t{v[2 * i], v[2 * i + 1]});
     }
     // x <- x + (d + sigma z), each operation rounded (library built without
     // contraction), as Eq. (1)-(2) are written.
@@ -240,12 +276,12 @@ struct ModeT<PF_F32> {
             v[2 * i] = a.x; v[2 * i + 1] = a.y;
         }
     }
-    template <int PPT>
+    template <int PPT, bool WT = false>
     static __device__ __forceinline__ void store(void* p, int k0, const Val* v)
     {
         auto* q = gbl(reinterpret_cast<float2_t*>(static_cast<float*>(p) + k0));
 #pragma unroll
-        for (int i = 0; i < PPT / 2; ++i) q[i] = float2_t{v[2 * i], v[2 * i + 1]};
+        for (int i = 0; i < PPT / 2; ++i) put<WT>(q + i, float2_t{v[2 * i], v[2 * i + 1]});
     }
     template <int PPT>
     static __device__ __forceinline__ void propagate(Val* x, Val* y, const Prop& pr, const StepArgs& a,
@@ -285,14 +321,14 @@ struct ModeT<PF_F16> {
             v[2 * i] = h.x; v[2 * i + 1] = h.y;
         }
     }
-    template <int PPT>
+    template <int PPT, bool WT = false>
     static __device__ __forceinline__ void store(void* p, int k0, const Val* v)
     {
         auto* q = gbl(reinterpret_cast<uint32_t*>(static_cast<_Float16*>(p) + k0));
 #pragma unroll
         for (int i = 0; i < PPT / 2; ++i) {
             const half2_t h = {v[2 * i], v[2 * i + 1]};
-            q[i] = __builtin_bit_cast(uint32_t, h);
+            put<WT>(q + i, __builtin_bit_cast(uint32_t, h));
         }
     }
     template <int PPT>
@@ -384,12 +420,12 @@ struct ModeT<PF_BF16> {
         const __bf16 a = (__bf16)lo, b = (__bf16)hi;
         return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
     }
-    template <int PPT>
+    template <int PPT, bool WT = false>
     static __device__ __forceinline__ void store(void* p, int k0, const Val* v)
     {
         auto* q = gbl(reinterpret_cast<uint32_t*>(static_cast<uint16_t*>(p) + k0));
 #pragma unroll
-        for (int i = 0; i < PPT / 2; ++i) q[i] = pack(v[2 * i], v[2 * i + 1]);
+        for (int i = 0; i < PPT / 2; ++i) put<WT>(q + i, pack(v[2 * i], v[2 * i + 1]));
     }
     template <int PPT>
     static __device__ __forceinline__ void propagate(Val* x, Val* y, const Prop& pr, const StepArgs& a,
@@ -443,7 +479,7 @@ struct PassALds {
 
 // Pass A of tile `tile` of the filter described by `a`, PPT particles per
 // thread (kTile / PPT threads).
-template <int DT, int RC, int PPT, bool SCALAR_HALF = false>
+template <int DT, int RC, int PPT, bool SCALAR_HALF = false, bool WT = false>
 __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALds& lds)
 {
     static_assert(!SCALAR_HALF || DT == PF_F16, "the unpacked propagation is a half-precision variant");
@@ -478,8 +514,8 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
     M::template load<PPT>(a.sy, k0, y);
     if constexpr (SCALAR_HALF) M::template propagate_scalar<PPT>(x, y, pr, a, k0, tn);
     else M::template propagate<PPT>(x, y, pr, a, k0, tn);
-    M::template store<PPT>(a.px, k0, x);
-    M::template store<PPT>(a.py, k0, y);
+    M::template store<PPT, WT>(a.px, k0, x);
+    M::template store<PPT, WT>(a.py, k0, y);
 
     // Pixel cells, clamped to where clamping the disk pixels changes nothing.
     const int lox = -(r - 1), hix = a.W - 1 + (r - 1);
@@ -671,11 +707,11 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
     if constexpr (DT == PF_F64) {
         auto* qp = gbl(reinterpret_cast<double2_t*>(static_cast<double*>(a.q) + k0));
 #pragma unroll
-        for (int i = 0; i < PPT / 2; ++i) qp[i] = double2_t{q[2 * i], q[2 * i + 1]};
+        for (int i = 0; i < PPT / 2; ++i) put<WT>(qp + i, double2_t{q[2 * i], q[2 * i + 1]});
     } else {
         auto* qp = gbl(reinterpret_cast<float2_t*>(static_cast<float*>(a.q) + k0));
 #pragma unroll
-        for (int i = 0; i < PPT / 2; ++i) qp[i] = float2_t{q[2 * i], q[2 * i + 1]};
+        for (int i = 0; i < PPT / 2; ++i) put<WT>(qp + i, float2_t{q[2 * i], q[2 * i + 1]});
     }
     if (a.dg_s) {
 #pragma unroll
@@ -703,11 +739,11 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
     }
 }
 
-template <int DT, int RC, int PPT, bool SCALAR_HALF = false>
+template <int DT, int RC, int PPT, bool SCALAR_HALF = false, bool WT = false>
 __global__ __launch_bounds__(kTile / PPT) void pass_a_kernel(StepArgs a)
 {
     __shared__ PassALds lds;
-    pass_a_tile<DT, RC, PPT, SCALAR_HALF>(a, blockIdx.x, lds);
+    pass_a_tile<DT, RC, PPT, SCALAR_HALF, WT>(a, blockIdx.x, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1547,7 +1583,7 @@ struct PassCIn {
 // inputs `in` and slot map `ts`: end slots and positions to LDS, then the
 // slot fill and the scatter.  Every thread takes part; the workgroup is free
 // for the next tile when it returns.
-template <int DT, int BC>
+template <int DT, int BC, bool WT = false>
 __device__ __forceinline__ void pass_c_run(const StepArgs& a, int t, PassCLds<DT>& lds, const PassCIn<DT, BC>& in,
                                            const TileSlotsT<DT>& ts)
 {
@@ -1629,8 +1665,8 @@ __device__ __forceinline__ void pass_c_run(const StepArgs& a, int t, PassCLds<DT
                 const u16x4 v = *reinterpret_cast<const u16x4*>(&lds.anc[4 * q]);
                 if (i0 >= 0 && i0 + 4 <= nj) {  // the whole group lies in the round
                     const XY p0 = lds.xy[v.x], p1 = lds.xy[v.y], p2 = lds.xy[v.z], p3 = lds.xy[v.w];
-                    *reinterpret_cast<gbl_t<Store4>*>(gx + gs) = Store4{p0.x, p1.x, p2.x, p3.x};
-                    *reinterpret_cast<gbl_t<Store4>*>(gy + gs) = Store4{p0.y, p1.y, p2.y, p3.y};
+                    put<WT>(reinterpret_cast<gbl_t<Store4>*>(gx + gs), Store4{p0.x, p1.x, p2.x, p3.x});
+                    put<WT>(reinterpret_cast<gbl_t<Store4>*>(gy + gs), Store4{p0.y, p1.y, p2.y, p3.y});
                     if (anc_out) {
                         typedef int32_t I4 __attribute__((ext_vector_type(4)));
                         *reinterpret_cast<gbl_t<I4>*>(anc_out + gs) =
@@ -1643,8 +1679,8 @@ __device__ __forceinline__ void pass_c_run(const StepArgs& a, int t, PassCLds<DT
                         if (i >= 0 && i < nj) {
                             const int k = v[u];
                             const XY pk = lds.xy[k];
-                            gx[gs + u] = pk.x;
-                            gy[gs + u] = pk.y;
+                            put<WT>(gx + gs + u, pk.x);
+                            put<WT>(gy + gs + u, pk.y);
                             if (anc_out) anc_out[gs + u] = first + k;
                         }
                     }
@@ -1659,7 +1695,7 @@ __device__ __forceinline__ void pass_c_run(const StepArgs& a, int t, PassCLds<DT
 // Pass C of one filter over a grid of G <= ntiles workgroups: workgroup g
 // takes tiles g, g + G, ... and loads each tile's inputs while it scatters
 // the one before, so a workgroup's memory latency overlaps its own slot fill.
-template <int DT, int BC>
+template <int DT, int BC, bool WT = false>
 __global__ __launch_bounds__(BC, BC >= 256 ? 8 : 1) void pass_c_kernel(StepArgs a)
 {
     __shared__ PassCLds<DT> lds;
@@ -1681,7 +1717,7 @@ __global__ __launch_bounds__(BC, BC >= 256 ? 8 : 1) void pass_c_kernel(StepArgs 
             rn.load(a, tn);
             nxt.load(a, tn);
         }
-        pass_c_run<DT, BC>(a, t, lds, cur, ts);
+        pass_c_run<DT, BC, WT>(a, t, lds, cur, ts);
         if (tn >= nt) break;
         t = tn;
         cur = nxt;
@@ -2110,6 +2146,13 @@ static hipError_t launch_pass_a_t(const StepArgs& a, hipStream_t s, const KTimin
         return launch1(pass_a_kernel<DT, 0, 2>, g, dim3(512), s, tm, a);
     }
     const dim3 blk(kBlockA);
+    if constexpr (DT == PF_F16 || DT == PF_BF16) {
+        if (a.wt && !a.naive_half) {  // a short 16-bit step: outputs written through the L2
+            if (a.r == 5) return launch1(pass_a_kernel<DT, 5, kPPT, false, true>, g, blk, s, tm, a);
+            if (a.r == 8) return launch1(pass_a_kernel<DT, 8, kPPT, false, true>, g, blk, s, tm, a);
+            return launch1(pass_a_kernel<DT, 0, kPPT, false, true>, g, blk, s, tm, a);
+        }
+    }
     if constexpr (DT == PF_F16) {
         if (a.naive_half) {  // the unpacked half propagation
             if (a.r == 5) return launch1(pass_a_kernel<DT, 5, kPPT, true>, g, blk, s, tm, a);
@@ -2148,6 +2191,12 @@ static int resident_cap(K kernel, int threads)
 template <int DT, int BC>
 static hipError_t launch_pass_c_stream(const StepArgs& a, hipStream_t s, const KTiming& tm)
 {
+    if constexpr ((DT == PF_F16 || DT == PF_BF16) && BC == 256) {
+        if (a.wt) {  // a short 16-bit step: the state written through the L2
+            static const int capw = resident_cap(pass_c_kernel<DT, BC, true>, BC);
+            return launch1(pass_c_kernel<DT, BC, true>, dim3((unsigned)min(a.ntiles, capw)), dim3(BC), s, tm, a);
+        }
+    }
     static const int cap = resident_cap(pass_c_kernel<DT, BC>, BC);
     return launch1(pass_c_kernel<DT, BC>, dim3((unsigned)min(a.ntiles, cap)), dim3(BC), s, tm, a);
 }
