@@ -90,6 +90,15 @@ __device__ __forceinline__ void put(gbl_t<T>* p, const T& v)
         }
     }
 }
+
+// 16 bytes per lane written through the L2 (the atomic stores above are at
+// most 8 bytes, and two 8-byte stores per lane would each leave every other
+// 8 bytes of a line to a later store).
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void put16_wt(gbl_t<u32x4_t>* p, u32x4_t v)
+{
+    __asm__ volatile("global_store_dwordx4 %0, %1, off sc1" ::"v"(p), "v"(v) : "memory");
+}
 // Tile records through such pointers, member by member (a structure's
 // implicit copy does not bind to global-memory references).
 __device__ __forceinline__ TileRec64 load_rec(const gbl_t<const TileRec64>* p)
@@ -325,10 +334,20 @@ struct ModeT<PF_F16> {
     static __device__ __forceinline__ void store(void* p, int k0, const Val* v)
     {
         auto* q = gbl(reinterpret_cast<uint32_t*>(static_cast<_Float16*>(p) + k0));
+        if constexpr (WT && PPT % 4 == 0) {  // one 8-byte store per four particles
 #pragma unroll
-        for (int i = 0; i < PPT / 2; ++i) {
-            const half2_t h = {v[2 * i], v[2 * i + 1]};
-            put<WT>(q + i, __builtin_bit_cast(uint32_t, h));
+            for (int i = 0; i < PPT / 4; ++i) {
+                const half2_t lo = {v[4 * i], v[4 * i + 1]}, hi = {v[4 * i + 2], v[4 * i + 3]};
+                const uint64_t w = (uint64_t)__builtin_bit_cast(uint32_t, lo) |
+                                   ((uint64_t)__builtin_bit_cast(uint32_t, hi) << 32);
+                put<true>(reinterpret_cast<gbl_t<uint64_t>*>(q) + i, w);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < PPT / 2; ++i) {
+                const half2_t h = {v[2 * i], v[2 * i + 1]};
+                put<WT>(q + i, __builtin_bit_cast(uint32_t, h));
+            }
         }
     }
     template <int PPT>
@@ -424,8 +443,17 @@ struct ModeT<PF_BF16> {
     static __device__ __forceinline__ void store(void* p, int k0, const Val* v)
     {
         auto* q = gbl(reinterpret_cast<uint32_t*>(static_cast<uint16_t*>(p) + k0));
+        if constexpr (WT && PPT % 4 == 0) {  // one 8-byte store per four particles
 #pragma unroll
-        for (int i = 0; i < PPT / 2; ++i) put<WT>(q + i, pack(v[2 * i], v[2 * i + 1]));
+            for (int i = 0; i < PPT / 4; ++i) {
+                const uint64_t w = (uint64_t)pack(v[4 * i], v[4 * i + 1]) |
+                                   ((uint64_t)pack(v[4 * i + 2], v[4 * i + 3]) << 32);
+                put<true>(reinterpret_cast<gbl_t<uint64_t>*>(q) + i, w);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < PPT / 2; ++i) put<WT>(q + i, pack(v[2 * i], v[2 * i + 1]));
+        }
     }
     template <int PPT>
     static __device__ __forceinline__ void propagate(Val* x, Val* y, const Prop& pr, const StepArgs& a,
@@ -710,8 +738,16 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
         for (int i = 0; i < PPT / 2; ++i) put<WT>(qp + i, double2_t{q[2 * i], q[2 * i + 1]});
     } else {
         auto* qp = gbl(reinterpret_cast<float2_t*>(static_cast<float*>(a.q) + k0));
+        if constexpr (WT && PPT % 4 == 0) {  // one 16-byte store per four particles
 #pragma unroll
-        for (int i = 0; i < PPT / 2; ++i) put<WT>(qp + i, float2_t{q[2 * i], q[2 * i + 1]});
+            for (int i = 0; i < PPT / 4; ++i)
+                put16_wt(reinterpret_cast<gbl_t<u32x4_t>*>(qp) + i,
+                         u32x4_t{__float_as_uint(q[4 * i]), __float_as_uint(q[4 * i + 1]),
+                                 __float_as_uint(q[4 * i + 2]), __float_as_uint(q[4 * i + 3])});
+        } else {
+#pragma unroll
+            for (int i = 0; i < PPT / 2; ++i) put<WT>(qp + i, float2_t{q[2 * i], q[2 * i + 1]});
+        }
     }
     if (a.dg_s) {
 #pragma unroll
