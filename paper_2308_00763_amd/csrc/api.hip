@@ -411,7 +411,7 @@ void setup_filter(pf_filter* h, const pf_params& pr, uint8_t* ws, hipStream_t st
     a.naive_half = (p->flags & PF_FLAG_NAIVE_HALF) ? 1 : 0;
     // a short 16-bit step stores its bulk outputs written through the L2
     // (single-filter launches at the default sizes; batches store plainly)
-    a.wt = (p->dtype == PF_F16 || p->dtype == PF_BF16) && a.ntiles <= kWtMaxTiles ? 1 : 0;
+    a.wt = p->dtype != PF_F64 && a.ntiles <= kWtMaxTiles ? 1 : 0;
     a.threads_a = threads_of((p->flags >> PF_THREADS_A_SHIFT) & 0xF, kBlockA);
     a.threads_c = threads_of((p->flags >> PF_THREADS_C_SHIFT) & 0xF, 0);
     a.cdf = a.naive_res ? at(h, L.cdf) : nullptr;

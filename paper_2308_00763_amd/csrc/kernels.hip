@@ -93,11 +93,14 @@ __device__ __forceinline__ void put(gbl_t<T>* p, const T& v)
 
 // 16 bytes per lane written through the L2 (the atomic stores above are at
 // most 8 bytes, and two 8-byte stores per lane would each leave every other
-// 8 bytes of a line to a later store).
+// 8 bytes of a line to a later store).  A store of more than 8 bytes reads its
+// data registers after it issues, and the next instruction must not rewrite
+// them before: the compiler keeps that distance for the stores it emits, but
+// cannot see into this one, so the wait states follow it here.
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ void put16_wt(gbl_t<u32x4_t>* p, u32x4_t v)
 {
-    __asm__ volatile("global_store_dwordx4 %0, %1, off sc1" ::"v"(p), "v"(v) : "memory");
+    __asm__ volatile("global_store_dwordx4 %0, %1, off sc1\n\ts_nop 1" ::"v"(p), "v"(v) : "memory");
 }
 // Tile records through such pointers, member by member (a structure's
 // implicit copy does not bind to global-memory references).
@@ -289,8 +292,16 @@ struct ModeT<PF_F32> {
     static __device__ __forceinline__ void store(void* p, int k0, const Val* v)
     {
         auto* q = gbl(reinterpret_cast<float2_t*>(static_cast<float*>(p) + k0));
+        if constexpr (WT && PPT % 4 == 0) {  // one 16-byte store per four particles
 #pragma unroll
-        for (int i = 0; i < PPT / 2; ++i) put<WT>(q + i, float2_t{v[2 * i], v[2 * i + 1]});
+            for (int i = 0; i < PPT / 4; ++i)
+                put16_wt(reinterpret_cast<gbl_t<u32x4_t>*>(q) + i,
+                         u32x4_t{__float_as_uint(v[4 * i]), __float_as_uint(v[4 * i + 1]),
+                                 __float_as_uint(v[4 * i + 2]), __float_as_uint(v[4 * i + 3])});
+        } else {
+#pragma unroll
+            for (int i = 0; i < PPT / 2; ++i) put<WT>(q + i, float2_t{v[2 * i], v[2 * i + 1]});
+        }
     }
     template <int PPT>
     static __device__ __forceinline__ void propagate(Val* x, Val* y, const Prop& pr, const StepArgs& a,
@@ -1701,8 +1712,15 @@ __device__ __forceinline__ void pass_c_run(const StepArgs& a, int t, PassCLds<DT
                 const u16x4 v = *reinterpret_cast<const u16x4*>(&lds.anc[4 * q]);
                 if (i0 >= 0 && i0 + 4 <= nj) {  // the whole group lies in the round
                     const XY p0 = lds.xy[v.x], p1 = lds.xy[v.y], p2 = lds.xy[v.z], p3 = lds.xy[v.w];
-                    put<WT>(reinterpret_cast<gbl_t<Store4>*>(gx + gs), Store4{p0.x, p1.x, p2.x, p3.x});
-                    put<WT>(reinterpret_cast<gbl_t<Store4>*>(gy + gs), Store4{p0.y, p1.y, p2.y, p3.y});
+                    if constexpr (WT && sizeof(Store4) == 16) {  // one 16-byte store per group
+                        put16_wt(reinterpret_cast<gbl_t<u32x4_t>*>(gx + gs),
+                                 __builtin_bit_cast(u32x4_t, Store4{p0.x, p1.x, p2.x, p3.x}));
+                        put16_wt(reinterpret_cast<gbl_t<u32x4_t>*>(gy + gs),
+                                 __builtin_bit_cast(u32x4_t, Store4{p0.y, p1.y, p2.y, p3.y}));
+                    } else {
+                        put<WT>(reinterpret_cast<gbl_t<Store4>*>(gx + gs), Store4{p0.x, p1.x, p2.x, p3.x});
+                        put<WT>(reinterpret_cast<gbl_t<Store4>*>(gy + gs), Store4{p0.y, p1.y, p2.y, p3.y});
+                    }
                     if (anc_out) {
                         typedef int32_t I4 __attribute__((ext_vector_type(4)));
                         *reinterpret_cast<gbl_t<I4>*>(anc_out + gs) =
@@ -2182,8 +2200,8 @@ static hipError_t launch_pass_a_t(const StepArgs& a, hipStream_t s, const KTimin
         return launch1(pass_a_kernel<DT, 0, 2>, g, dim3(512), s, tm, a);
     }
     const dim3 blk(kBlockA);
-    if constexpr (DT == PF_F16 || DT == PF_BF16) {
-        if (a.wt && !a.naive_half) {  // a short 16-bit step: outputs written through the L2
+    if constexpr (DT != PF_F64) {
+        if (a.wt && !a.naive_half) {  // a short step: outputs written through the L2
             if (a.r == 5) return launch1(pass_a_kernel<DT, 5, kPPT, false, true>, g, blk, s, tm, a);
             if (a.r == 8) return launch1(pass_a_kernel<DT, 8, kPPT, false, true>, g, blk, s, tm, a);
             return launch1(pass_a_kernel<DT, 0, kPPT, false, true>, g, blk, s, tm, a);
@@ -2227,8 +2245,8 @@ static int resident_cap(K kernel, int threads)
 template <int DT, int BC>
 static hipError_t launch_pass_c_stream(const StepArgs& a, hipStream_t s, const KTiming& tm)
 {
-    if constexpr ((DT == PF_F16 || DT == PF_BF16) && BC == 256) {
-        if (a.wt) {  // a short 16-bit step: the state written through the L2
+    if constexpr (DT != PF_F64 && BC == 256) {
+        if (a.wt) {  // a short step: the state written through the L2
             static const int capw = resident_cap(pass_c_kernel<DT, BC, true>, BC);
             return launch1(pass_c_kernel<DT, BC, true>, dim3((unsigned)min(a.ntiles, capw)), dim3(BC), s, tm, a);
         }
