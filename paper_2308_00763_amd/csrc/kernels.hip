@@ -56,16 +56,18 @@ __device__ __forceinline__ gbl_t<T>* gbl(T* p)
 }
 
 // The bulk outputs that the next kernel reads (pass A's propagated positions
-// and tile prefix sums, pass C's resampled state) of a small single filter in
-// a 16-bit mode (StepArgs::wt) are stored at device scope: such stores are
-// written through the XCD's L2, so the release that ends the kernel finds none
-// of them dirty there to write back, and the next kernel, on any XCD, reads
-// them from memory as it would in any case.  That pays where the kernels are
-// short (2^20 FP16: 19.6 against 21.0 us per step) and costs where they are
-// large or the stores wide (2^24 FP16 +2 %, the 4096-stream batch +20 %, FP32
-// and FP64 at 2^20 +6 % and +53 %: the written-through partial lines), so the
-// kernels that use it (WT) are separate instantiations, launched for 16-bit
-// filters of at most 1024 tiles stepped alone at the default sizes.
+// and tile prefix sums, pass C's resampled state) of a single filter that is
+// not FP64 and has at most kWtMaxTiles tiles (StepArgs::wt) are stored at
+// device scope: such stores are written through the XCD's L2, so the release
+// that ends the kernel finds none of them dirty there to write back, and the
+// next kernel, on any XCD, reads them from memory as it would in any case.
+// Each store covers whole lines across the wave (one 8- or 16-byte store per
+// lane).  That pays where the kernels are short (2^20 FP16 21.0 -> 19.1 us per
+// step, FP32 23.2 -> 21.5 us, 2^21 -10 %, 2^23 -2 %) and is even or costs
+// where they are long or the stores wide (2^24 FP16 even, the 4096-stream
+// batch +20 %, FP64 at 2^20 +53 %), so the kernels that use it (WT) are
+// separate instantiations, launched for such filters stepped alone at the
+// default sizes.
 template <bool WT, typename T>
 __device__ __forceinline__ void put(gbl_t<T>* p, const T& v)
 {

@@ -37,9 +37,9 @@ __host__ __device__ constexpr int comb_class(int nt)
     return nt <= 256 ? 0 : nt <= 1024 ? 1 : nt <= 4096 ? 2 : 3;
 }
 constexpr int kCombClasses = 4;
-// Single 16-bit filters of at most this many tiles store their bulk outputs
-// written through the L2 (StepArgs::wt).
-constexpr int kWtMaxTiles = 1024;
+// Single FP16, BF16 and FP32 filters of at most this many tiles (2^23
+// particles) store their bulk outputs written through the L2 (StepArgs::wt).
+constexpr int kWtMaxTiles = 8192;
 
 // Particles per thread and tile size per precision mode.
 __host__ __device__ constexpr int tile_of(int /*dtype*/) { return kTile; }
@@ -222,7 +222,7 @@ struct StepArgs {
     int32_t naive_lik;  // disk sums read every pixel from the frame
     int32_t naive_res;  // normalised CDF + per-slot binary search instead of pass C
     int32_t naive_half; // FP16: propagation one particle at a time in scalar half arithmetic
-    int32_t wt;         // single-filter launches: the write-through pass A and pass C (16-bit, small)
+    int32_t wt;         // single-filter launches: the write-through pass A and pass C (not FP64, <= kWtMaxTiles)
     int32_t threads_a;  // pass A threads per tile: 128, 256 (default) or 512
     int32_t threads_c;  // pass C / naive resampler threads per workgroup: 64 .. 1024 (0: by tile count)
     void* cdf;          // naive resampler: normalised cumulative weights
