@@ -941,7 +941,7 @@ using TileSlotsT = TileSlots<DT == PF_F64 ? PF_F64 : PF_F32>;
 
 // ---------------------------------------------------------------------------
 // Combine: one workgroup per filter turns the tile records into the tile
-// table.  Every thread owns KPER consecutive tiles per round; the carried
+// table.  Every thread owns KPER consecutive tiles; the carried
 // offsets come from a two-level scan (per wave, then over the wave totals)
 // whose total is the normaliser Z; the estimate sums ride on the same
 // exchange.  The tiles' end slots are made non-decreasing by an integer
@@ -1052,14 +1052,17 @@ struct SlotMap<false> {
 
 // The per-filter block after a combine: normaliser, maximum, u0, R, the
 // estimate (sx, sy: weighted position sums relative to the maximum) and, in
-// the reduced modes, the origin of the next propagation.  One thread.
+// the reduced modes, the origin of the next propagation (cnx, cny: the
+// block's origin cells as the step found them, read by the caller before its
+// first store, so that they come from a scalar load issued at the start and
+// not from a memory round trip at the end).  One thread.
 template <int DT>
 __device__ __forceinline__ void write_block(const StepArgs& a,
                                            typename std::conditional<DT == PF_F64, double, ff>::type Z,
                                            typename std::conditional<DT == PF_F64, double, int>::type gm,
                                            typename std::conditional<DT == PF_F64, double, float>::type sx,
                                            typename std::conditional<DT == PF_F64, double, float>::type sy,
-                                           const SlotMap<DT == PF_F64>& sm, uint32_t t)
+                                           const SlotMap<DT == PF_F64>& sm, uint32_t t, int cnx, int cny)
 {
     auto* b = gbl(a.blk);
     b->t = t;
@@ -1072,7 +1075,6 @@ __device__ __forceinline__ void write_block(const StepArgs& a,
         b->est_y = sy / Z;
     } else {
         const float Zf = Z.hi + Z.lo;
-        const int cnx = b->cn_x, cny = b->cn_y;
         const float ox = (float)cnx + sx / Zf;
         const float oy = (float)cny + sy / Zf;
         // the estimate leaves the device as double (conversion only)
@@ -1095,7 +1097,59 @@ __device__ __forceinline__ void write_block(const StepArgs& a,
     }
 }
 
-// Combine of the filter described by `a`, run by one workgroup of NT threads.
+// Origin cells of the next propagation as the block holds them before the
+// combine (the double mode has none).
+template <bool F64>
+__device__ __forceinline__ void read_cells(const StepArgs& a, int& cnx, int& cny)
+{
+    cnx = 0;
+    cny = 0;
+    if constexpr (!F64) {
+        const auto* b = gbl(a.blk);
+        cnx = b->cn_x;
+        cny = b->cn_y;
+    }
+}
+
+// Value of a uniform lane l of v.
+__device__ __forceinline__ double lane_at(double v, int l)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+__device__ __forceinline__ ff lane_at(ff v, int l)
+{
+    return ff{__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.hi), l)),
+              __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.lo), l))};
+}
+__device__ __forceinline__ int lane_at(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+// One table entry in a single store (the double mode's entry has a pad word).
+__device__ __forceinline__ void put_tab(gbl_t<TileTab32>* p, ff off, float f, int E)
+{
+    u32x4_t w;
+    w[0] = __float_as_uint(off.hi);
+    w[1] = __float_as_uint(off.lo);
+    w[2] = __float_as_uint(f);
+    w[3] = (uint32_t)E;
+    *reinterpret_cast<gbl_t<u32x4_t>*>(p) = w;
+}
+__device__ __forceinline__ void put_tab(gbl_t<TileTab64>* p, double off, double f, int E)
+{
+    p->off = off;
+    p->f = f;
+    p->E = E;
+}
+
+// Combine of the filter described by `a`, run by one workgroup of NT threads
+// that owns KPER consecutive tiles each (at most KPER * NT tiles: one round).
+// Its chain is short because it is on the step's critical path: the records
+// are loaded once and kept in registers; every wave scans the wave totals
+// itself (the same operations on the same values in every wave, so the same
+// bits) instead of waiting for one wave to publish them; the end-slot maxima
+// travel with the last offsets of the waves in one more exchange; and each
+// table entry is stored whole once its end slot is known.  A single-wave
+// combine exchanges nothing.
 template <int DT, int KPER, int NT>
 __device__ __forceinline__ void combine_filter(const StepArgs& a)
 {
@@ -1111,175 +1165,147 @@ __device__ __forceinline__ void combine_filter(const StepArgs& a)
 
     __shared__ Mx red_m[NW];
     __shared__ T red_s[NW];
-    __shared__ T wave_off[NW + 1];
     __shared__ Fv red_x[NW], red_y[NW];
     __shared__ int red_e[NW];
-    __shared__ int woff_e[NW + 1];
+    __shared__ T red_last[NW];
 
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int nt = a.ntiles;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    // A plan captured before the filter was re-initialised larger can hand a
+    // filter of more tiles to this class: only the first CHUNK are combined
+    // (in bounds; that step's results are meaningless, as documented).
+    const int nt = min((int)a.ntiles, CHUNK);
     const int n = (int)a.n;
     const auto* rec = gbl(static_cast<const Rec*>(a.rec));
     auto* tab = gbl(static_cast<Tab*>(a.tab));
-    const uint32_t tn = gbl(a.blk)->t + 1u;  // this step (thread 0 advances the count at the end)
-    // the resampling offset's random words do not depend on the weights: drawn
-    // first, they overlap the loads of the records
-    const u32x4 wu0 = u0_words(a, tn);
 
-    // global maximum of the tile maxima; with a single round the records stay
-    // in registers for the scan
-    constexpr bool KEEP = KPER <= 4;
-    const bool one_round = KEEP && nt <= CHUNK;
-    Rec r_keep[KEEP ? KPER : 1];
-    Mx m = F64 ? (Mx)-INFINITY : (Mx)INT32_MIN;
-    for (int base = 0; base < nt; base += CHUNK) {
+    // global maximum of the tile maxima (the loads are unconditional, from a
+    // clamped index, so that all of them are in flight at once)
+    Rec r[KPER];
 #pragma unroll
-        for (int k = 0; k < KPER; ++k) {
-            const int t = base + tid * KPER + k;
-            if (t < nt) {
-                Mx mt;
-                if (one_round) {
-                    r_keep[KEEP ? k : 0] = load_rec(rec + t);
-                    if constexpr (F64) mt = r_keep[KEEP ? k : 0].m; else mt = r_keep[KEEP ? k : 0].smax;
-                } else {
-                    if constexpr (F64) mt = rec[t].m; else mt = rec[t].smax;
-                }
-                m = mt > m ? mt : m;
-            }
-        }
+    for (int k = 0; k < KPER; ++k) r[k] = load_rec(rec + min(tid * KPER + k, nt - 1));
+    const uint32_t tn = gbl(a.blk)->t + 1u;  // this step (thread 0 advances the count at the end)
+    int cnx, cny;
+    read_cells<F64>(a, cnx, cny);
+    // the block's words are needed now (the compiler would otherwise sink
+    // their loads to the end of the chain); the resampling offset's random
+    // words do not depend on the weights: drawn now, they overlap the loads
+    // of the records
+    __asm__ volatile("" ::"s"(tn), "s"(cnx), "s"(cny));
+    const u32x4 wu0 = u0_words(a, tn);
+    Mx m = F64 ? (Mx)-INFINITY : (Mx)INT32_MIN;
+#pragma unroll
+    for (int k = 0; k < KPER; ++k) {
+        Mx mt;
+        if constexpr (F64) mt = r[k].m; else mt = r[k].smax;
+        if (tid * KPER + k < nt) m = mt > m ? mt : m;
     }
     m = wave_max(m);
-    if (lane == 0) red_m[wv] = m;
-    __syncthreads();
-    Mx gm = red_m[0];
+    Mx gm = m;
+    if constexpr (NW > 1) {
+        if (lane == 0) red_m[wv] = m;
+        __syncthreads();
+        gm = red_m[0];
 #pragma unroll
-    for (int w = 1; w < NW; ++w) gm = red_m[w] > gm ? red_m[w] : gm;
+        for (int w = 1; w < NW; ++w) gm = red_m[w] > gm ? red_m[w] : gm;
+    }
 
-    // carried offsets: kPER consecutive tiles per thread, a wave scan, then a
-    // scan of the wave totals by wave 0; the total is the normaliser
-    T carry = A::zero();
+    // factors, weighted sums and the inclusive scan of the thread totals
+    Fv f[KPER];
+    T v[KPER];
+    T loc = A::zero();
     Fv ex = 0, ey = 0;
-    T o_keep[KEEP ? KPER : 1];  // offsets kept in registers for the end slots
-    for (int base = 0; base < nt; base += CHUNK) {
-        Fv f[KPER];
-        T v[KPER];
-        T loc = A::zero();
 #pragma unroll
-        for (int k = 0; k < KPER; ++k) {
-            const int t = base + tid * KPER + k;
-            f[k] = 0;
-            v[k] = A::zero();
-            if (t < nt) {
-                const Rec rr = one_round ? r_keep[KEEP ? k : 0] : load_rec(rec + t);
-                if constexpr (F64) {
-                    f[k] = exp(rr.m - gm);
-                    v[k] = f[k] * rr.s;
-                } else {
-                    f[k] = __builtin_amdgcn_exp2f((float)(rr.smax - gm) * a.beta);
-                    v[k] = two_prod(f[k], rr.s);
-                }
-                ex = ex + f[k] * rr.sx;
-                ey = ey + f[k] * rr.sy;
+    for (int k = 0; k < KPER; ++k) {
+        const int t = tid * KPER + k;
+        f[k] = 0;
+        v[k] = A::zero();
+        if (t < nt) {
+            if constexpr (F64) {
+                f[k] = exp(r[k].m - gm);
+                v[k] = f[k] * r[k].s;
+            } else {
+                f[k] = __builtin_amdgcn_exp2f((float)(r[k].smax - gm) * a.beta);
+                v[k] = two_prod(f[k], r[k].s);
             }
-            loc = A::add(loc, v[k]);
+            ex = ex + f[k] * r[k].sx;
+            ey = ey + f[k] * r[k].sy;
         }
-        const T sw = A::sum_scan(loc);
-        if (one_round) {
-            // the estimate sums are complete after the only round: their
-            // wave totals ride on this round's exchange
-            const Fv wx = wave_sum(ex), wy = wave_sum(ey);
-            if (lane == 0) { red_x[wv] = wx; red_y[wv] = wy; }
-        }
+        loc = A::add(loc, v[k]);
+    }
+    const T sw = A::sum_scan(loc);
+    const Fv wx = wave_sum(ex), wy = wave_sum(ey);
+    T off = A::zero();  // offset of this wave's first tile
+    T Z;
+    Fv sx = wx, sy = wy;
+    if constexpr (NW > 1) {
         if (lane == 63) red_s[wv] = sw;
+        if (lane == 0) { red_x[wv] = wx; red_y[wv] = wy; }
         __syncthreads();
-        if (wv == 0) {
-            T tv = lane < NW ? red_s[lane] : A::zero();
-            tv = A::sum_scan(tv);
-            if (lane < NW) wave_off[lane + 1] = A::add(carry, tv);
-            if (lane == 0) wave_off[0] = carry;
-        }
-        __syncthreads();
-        const T off = wave_off[wv];
-        const T excl = A::up1(A::add(off, sw), off);
-        T run = excl;
+        T tv = lane < NW ? red_s[lane] : A::zero();
+        tv = A::sum_scan(tv);
+        if (wv > 0) off = lane_at(tv, wv - 1);
+        Z = lane_at(tv, NW - 1);
+        sx = red_x[0];
+        sy = red_y[0];
 #pragma unroll
-        for (int k = 0; k < KPER; ++k) {
-            const int t = base + tid * KPER + k;
-            run = A::add(run, v[k]);
-            if constexpr (KEEP) o_keep[k] = run;
-            if (t < nt) {
-                tab[t].f = f[k];
-                if constexpr (F64) tab[t + 1].off = run;
-                else { tab[t + 1].off_hi = run.hi; tab[t + 1].off_lo = run.lo; }
-            }
-        }
-        carry = wave_off[NW];
-        if (base + CHUNK < nt) __syncthreads();  // the next round rewrites the exchange
+        for (int w = 1; w < NW; ++w) { sx = sx + red_x[w]; sy = sy + red_y[w]; }
+    } else {
+        Z = A::last(sw);
     }
-    const T Z = carry;
-    if (!one_round) {
-        ex = wave_sum(ex);
-        ey = wave_sum(ey);
-        if (lane == 0) { red_x[wv] = ex; red_y[wv] = ey; }
-        __syncthreads();
-    }
-    Fv sx = red_x[0], sy = red_y[0];
+
+    // inclusive offsets of the thread's tiles
+    const T excl = A::up1(A::add(off, sw), off);
+    T o[KPER];
+    T run = excl;
 #pragma unroll
-    for (int w = 1; w < NW; ++w) { sx = sx + red_x[w]; sy = sy + red_y[w]; }
+    for (int k = 0; k < KPER; ++k) {
+        run = A::add(run, v[k]);
+        o[k] = run;
+    }
 
     // End slot of every tile, y = R off_{t+1} - u0 (the expression pass C caps
     // its tiles with), made non-decreasing by a prefix maximum so that the
     // tiles' slot ranges [E_{t-1}, E_t) partition [0, N) whatever the
     // rounding of the offsets; the last tile ends at N.
     const SlotMap<F64> smap(a, Z, wu0);
-    auto end_of = [&](T o) -> int { return smap.end_of(o, n); };
-    int carry_e = 0;
-    for (int base = 0; base < nt; base += CHUNK) {
-        int Ek[KPER];
-        int mx = carry_e;
+    int Ek[KPER];
+    int mx = 0;
 #pragma unroll
-        for (int k = 0; k < KPER; ++k) {
-            const int t = base + tid * KPER + k;
-            Ek[k] = 0;
-            if (t < nt) {
-                T o;
-                if (one_round) o = o_keep[KEEP ? k : 0];
-                else if constexpr (F64) o = tab[t + 1].off;
-                else o = ff{tab[t + 1].off_hi, tab[t + 1].off_lo};
-                Ek[k] = t == nt - 1 ? n : end_of(o);
-            }
-            mx = max(mx, Ek[k]);
-        }
-        const int sm = wave_incl_scan<OpMax>(mx);
-        if (lane == 63) red_e[wv] = sm;
+    for (int k = 0; k < KPER; ++k) {
+        const int t = tid * KPER + k;
+        Ek[k] = 0;
+        if (t < nt) Ek[k] = t == nt - 1 ? n : smap.end_of(o[k], n);
+        mx = max(mx, Ek[k]);
+    }
+    const int sm = wave_incl_scan<OpMax>(mx);
+    int e_off = 0;          // end slot of the earlier waves' tiles
+    T last_prev = A::zero();  // inclusive offset of the tile before this wave's first
+    if constexpr (NW > 1) {
+        if (lane == 63) { red_e[wv] = sm; red_last[wv] = run; }
         __syncthreads();
-        if (wv == 0) {
-            int tv = lane < NW ? red_e[lane] : carry_e;
-            tv = wave_incl_scan<OpMax>(tv);
-            if (lane < NW) woff_e[lane + 1] = max(carry_e, tv);
-            if (lane == 0) woff_e[0] = carry_e;
+        int tv = lane < NW ? red_e[lane] : 0;
+        tv = wave_incl_scan<OpMax>(tv);
+        if (wv > 0) {
+            e_off = lane_at(tv, wv - 1);
+            last_prev = red_last[wv - 1];
         }
-        __syncthreads();
-        int run = max(woff_e[wv], wave_shift_up1(sm, carry_e));
+    }
+    int erun = max(e_off, wave_shift_up1(sm, e_off));
+    // entry t holds the inclusive offset of tile t - 1 (zero for the first)
+    T before = A::up1(run, last_prev);
 #pragma unroll
-        for (int k = 0; k < KPER; ++k) {
-            const int t = base + tid * KPER + k;
-            run = max(run, Ek[k]);
-            if (t < nt) tab[t].E = run;
+    for (int k = 0; k < KPER; ++k) {
+        const int t = tid * KPER + k;
+        erun = max(erun, Ek[k]);
+        if (t < nt) put_tab(tab + t, before, f[k], erun);
+        before = o[k];
+        if (t == nt - 1) {  // entry nt: the last tile's inclusive offset
+            if constexpr (F64) tab[nt].off = o[k];
+            else { tab[nt].off_hi = o[k].hi; tab[nt].off_lo = o[k].lo; }
         }
-        carry_e = woff_e[NW];
-        if (base + CHUNK < nt) __syncthreads();
     }
-
-    if (tid == 0) {
-        if constexpr (F64) {
-            tab[0].off = 0.0;
-        } else {
-            tab[0].off_hi = 0.f;
-            tab[0].off_lo = 0.f;
-        }
-        write_block<DT>(a, Z, gm, sx, sy, smap, tn);
-    }
+    if (tid == 0) write_block<DT>(a, Z, gm, sx, sy, smap, tn, cnx, cny);
 }
 
 template <int DT, int KPER, int NT>
@@ -1413,6 +1439,8 @@ __global__ __launch_bounds__(kTopThreads) void combine_top_kernel(StepArgs a)
     const int n = (int)a.n;
     const int ng = (a.ntiles + kGroupTiles - 1) / kGroupTiles;
     const bool valid = tid < ng;
+    int cnx, cny;
+    read_cells<F64>(a, cnx, cny);
     const uint32_t tn = a.blk->t + 1u;  // this step (thread 0 advances the count at the end)
     GRec gr{};
     if (valid) gr = static_cast<const GRec*>(a.grec)[tid];
@@ -1484,7 +1512,7 @@ __global__ __launch_bounds__(kTopThreads) void combine_top_kernel(StepArgs a)
         Tab* tab = static_cast<Tab*>(a.tab);
         if constexpr (F64) tab[a.ntiles].off = Z;
         else { tab[a.ntiles].off_hi = Z.hi; tab[a.ntiles].off_lo = Z.lo; }
-        write_block<DT>(a, Z, gm, sx, sy, smap, tn);
+        write_block<DT>(a, Z, gm, sx, sy, smap, tn, cnx, cny);
     }
 }
 
@@ -2308,8 +2336,8 @@ template <int DT>
 static hipError_t launch_combine_t(const StepArgs& a, hipStream_t s, const KTiming& tm)
 {
     switch (comb_class(a.ntiles)) {
-    case 0: return launch1(combine_kernel<DT, 1, 256>, dim3(1), dim3(256), s, tm, a);
-    case 1: return launch1(combine_kernel<DT, 1, 1024>, dim3(1), dim3(1024), s, tm, a);
+    case 0: return launch1(combine_kernel<DT, 4, 64>, dim3(1), dim3(64), s, tm, a);
+    case 1: return launch1(combine_kernel<DT, 4, 256>, dim3(1), dim3(256), s, tm, a);
     case 2: return launch1(combine_kernel<DT, 4, 1024>, dim3(1), dim3(1024), s, tm, a);
     default: return launch_combine_grouped<DT>(a, s, tm);
     }
@@ -2365,8 +2393,8 @@ static hipError_t launch_batch_combine_t(int cls, const BatchArgs& b, int count,
 {
     const dim3 g((unsigned)count);
     switch (cls) {
-    case 0: return launch1(combine_batch_kernel<DT, 1, 256>, g, dim3(256), s, tm, b);
-    case 1: return launch1(combine_batch_kernel<DT, 1, 1024>, g, dim3(1024), s, tm, b);
+    case 0: return launch1(combine_batch_kernel<DT, 4, 64>, g, dim3(64), s, tm, b);
+    case 1: return launch1(combine_batch_kernel<DT, 4, 256>, g, dim3(256), s, tm, b);
     case 2: return launch1(combine_batch_kernel<DT, 4, 1024>, g, dim3(1024), s, tm, b);
     default: return hipErrorInvalidValue;  // class 3 combines per filter (launch_combine)
     }

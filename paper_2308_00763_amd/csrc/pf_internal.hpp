@@ -29,9 +29,9 @@ constexpr int kPrefRows = 64;      // LDS row-prefix table: window rows
 constexpr int kWinMaxW = 128;      // widest frame window staged in LDS
 constexpr int kMaxRadius = 32;
 
-// Combine configuration of a filter of nt tiles: class 0 = 256 threads, one
-// tile per thread and round; 1 = 1024 threads, one tile; 2 = 1024 threads,
-// four tiles; 3 = 1024 threads, sixteen tiles.
+// Combine configuration of a filter of nt tiles: class 0 = one wave of 64
+// threads, four tiles per thread; 1 = 256 threads, four tiles each; 2 = 1024
+// threads, four tiles each; 3 = the grouped combine (groups of 1024 tiles).
 __host__ __device__ constexpr int comb_class(int nt)
 {
     return nt <= 256 ? 0 : nt <= 1024 ? 1 : nt <= 4096 ? 2 : 3;
