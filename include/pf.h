@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define PF_ABI_VERSION 5
+#define PF_ABI_VERSION 6
 
 typedef enum pf_status {
     PF_OK = 0,
@@ -199,10 +199,16 @@ typedef struct pf_params {
 
 typedef struct pf_filter pf_filter;
 
-/* Device bytes a filter with these parameters needs.  Pure function: touches
- * no device.  Errors: PF_ERR_INVALID_ARG for out-of-range parameters or a
- * NULL pointer. */
+/* Device bytes a filter with these parameters needs (pf_init).  Pure
+ * function: touches no device.  Errors: PF_ERR_INVALID_ARG for out-of-range
+ * parameters or a NULL pointer. */
 int pf_workspace_bytes(const pf_params* p, size_t* out_bytes);
+
+/* Device bytes a batch member with these parameters needs (a share for
+ * pf_batch_rebind): pf_workspace_bytes less what only a filter of its own
+ * uses (the buffers of the deferred resampling, see pf_step).  Pure
+ * function.  Errors as pf_workspace_bytes. */
+int pf_member_bytes(const pf_params* p, size_t* out_bytes);
 
 /* Initialisation (paper Sec. 4, Fig. 1: the filter starts after an
  * initialization phase): all N particles at (x0, y0) with weight 1/N, step
@@ -222,7 +228,12 @@ int pf_init(const pf_params* p, void* d_workspace, size_t workspace_bytes, void*
  * the weighted mean position before resampling becomes the estimate; the
  * normalised cumulative weights are resampled systematically with the offset
  * drawn from stream (0, t, stream_id, purpose 1) (Sec. 4, resampling
- * paragraph).  Asynchronous on the filter's stream; `d_frame` must stay valid
+ * paragraph).  An FP64 filter of at most 2^20 particles resampling
+ * systematically, without diagnostics or measurement variants, at the default
+ * pass-A size, defers the resampling of each step into the next step, whose first kernel
+ * gathers the resampled particles for its tiles (two kernels per step instead
+ * of three); pf_export runs a pending resampling first, and every result is
+ * bit-identical to resampling at once.  Asynchronous on the filter's stream; `d_frame` must stay valid
  * until the step has run.  The call enqueues kernels only (no host wait,
  * allocation or memset), so it may be captured into a HIP graph by stream
  * capture on the filter's stream: the step count lives on the device, and
@@ -260,8 +271,9 @@ int pf_estimate(pf_filter* h, double out_xy[2]);
  * (`d_out_xy`: 2 doubles, device pointer); does not wait. */
 int pf_estimate_async(pf_filter* h, double* d_out_xy);
 
-/* Copy the filter's state to host memory (waits for the stream).  Each
- * pointer may be NULL to skip it; arrays hold N elements.
+/* Copy the filter's state to host memory (waits for the stream; a pending
+ * resampling of the latest step, see pf_step, is run first when x or y is
+ * requested).  Each pointer may be NULL to skip it; arrays hold N elements.
  *   x, y    -- particle positions after the latest resampling (the next
  *              step's ancestors), in absolute pixels;
  *   w_norm  -- normalised weights of the latest step before resampling, in
@@ -301,7 +313,8 @@ const char* pf_last_error(void);
  * summed durations in milliseconds: out_ms[0] = pass A (propagate, likelihood, tile
  * maximum, weights, tile prefix sums), out_ms[1] = combine (global maximum,
  * normaliser, carried offsets, estimate, resampling offset), out_ms[2] = pass C
- * (systematic-resampling scatter), and the number of steps recorded; it then
+ * (systematic-resampling scatter; 0 for a filter that defers its resampling,
+ * see pf_step: pass A gathers it), and the number of steps recorded; it then
  * stops recording and frees the events.  Errors: PF_ERR_INVALID_ARG,
  * PF_ERR_HIP. */
 int pf_profile_start(pf_filter* h, uint32_t max_steps);
@@ -433,7 +446,7 @@ int pf_batch_init_cap(const pf_params* ps, int32_t n, int64_t max_tiles, void* d
 
 /* Re-initialise filter k of the batch as pf_batch_reinit does, on a new
  * workspace share: share_bytes bytes of device memory at d_share (256-byte
- * aligned, at least pf_workspace_bytes(p); owned by the caller, who keeps it
+ * aligned, at least pf_member_bytes(p); owned by the caller, who keeps it
  * valid and unshared while filter k is bound to it, i.e. until the next
  * rebind of k or pf_batch_destroy).  Lets a server hand its filters shares
  * from its own device-memory budget, sized per stream, instead of fixed

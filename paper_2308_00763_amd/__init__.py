@@ -43,10 +43,10 @@ PF_FLAG_STATE_ONLY = 1 << 26
 PF_FLAG_TUNED = 1 << 30
 PF_STATIC_SCRATCH_BYTES = 24 * 1024 * 1024 + 64 * 1024
 
-PF_ABI_VERSION = 5
+PF_ABI_VERSION = 6
 
 # Every function the C header declares (checked against include/pf.h by the tests).
-EXPORTS = ("pf_workspace_bytes", "pf_init", "pf_step", "pf_step_static_scratch", "pf_estimate",
+EXPORTS = ("pf_workspace_bytes", "pf_member_bytes", "pf_init", "pf_step", "pf_step_static_scratch", "pf_estimate",
            "pf_estimate_async",
            "pf_export", "pf_export_step", "pf_import", "pf_destroy", "pf_last_error",
            "pf_abi_version", "pf_profile_start", "pf_profile_read",
@@ -99,6 +99,7 @@ def lib():
         P = ctypes.POINTER
         vp = ctypes.c_void_p
         L.pf_workspace_bytes.argtypes = [P(pf_params), P(ctypes.c_size_t)]
+        L.pf_member_bytes.argtypes = [P(pf_params), P(ctypes.c_size_t)]
         L.pf_init.argtypes = [P(pf_params), vp, ctypes.c_size_t, vp, P(vp)]
         L.pf_step.argtypes = [vp, vp, ctypes.c_int64]
         L.pf_step_static_scratch.argtypes = [vp, vp, ctypes.c_int64]
@@ -196,6 +197,12 @@ def make_params(n, width, height, dtype="f64", radius=5, x0=0.0, y0=0.0, drift=(
 def pf_workspace_bytes(p: pf_params) -> int:
     out = ctypes.c_size_t()
     _check(lib().pf_workspace_bytes(ctypes.byref(p), ctypes.byref(out)))
+    return out.value
+
+
+def pf_member_bytes(p: pf_params) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().pf_member_bytes(ctypes.byref(p), ctypes.byref(out)))
     return out.value
 
 

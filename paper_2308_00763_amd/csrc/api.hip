@@ -346,11 +346,13 @@ int floor_cell(double v) { return (int)floor(v + 0.5); }
 
 // Fill the handle for a filter with params p (checked) over workspace ws, and
 // return its initial device block and the stored value of every particle.
+// `single`: a filter of its own (pf_init), which defers its resampling when
+// it can; batch members never do.
 void setup_filter(pf_filter* h, const pf_params& pr, uint8_t* ws, hipStream_t stream, DevBlock* blk,
-                  double* vx, double* vy)
+                  double* vx, double* vy, bool single = false)
 {
     const pf_params* p = &pr;
-    const Layout L = make_layout(pr);
+    const Layout L = make_layout(pr, single);
     h->p = pr;
     h->L = L;
     h->stream = stream;
@@ -428,6 +430,13 @@ void setup_filter(pf_filter* h, const pf_params& pr, uint8_t* ws, hipStream_t st
     }
     a.s_all = (p->flags & (PF_FLAG_METROPOLIS | PF_FLAG_GUMBEL_MAX | PF_FLAG_REJECTION)) ? (int32_t*)at(h, L.s_all)
                                                                                         : nullptr;
+    // deferred resampling: at the default pass-A size (the gather assigns four
+    // slots to each of 256 threads)
+    a.gather = L.px2 != 0 && a.threads_a == kBlockA ? 1 : 0;
+    a.px2 = a.gather ? at(h, L.px2) : nullptr;
+    a.py2 = a.gather ? at(h, L.py2) : nullptr;
+    a.q2 = a.gather ? at(h, L.q2) : nullptr;
+    a.ecol = a.gather ? (int32_t*)at(h, L.ecol) : nullptr;
 
     DevBlock b{};
     *vx = p->x0;
@@ -542,6 +551,14 @@ int pf_workspace_bytes(const pf_params* p, size_t* out_bytes)
 {
     if (int rc = check_params(p)) return rc;
     if (!out_bytes) return fail(PF_ERR_INVALID_ARG, "out_bytes is NULL");
+    *out_bytes = make_layout(*p, true).total;
+    return ok();
+}
+
+int pf_member_bytes(const pf_params* p, size_t* out_bytes)
+{
+    if (int rc = check_params(p)) return rc;
+    if (!out_bytes) return fail(PF_ERR_INVALID_ARG, "out_bytes is NULL");
     *out_bytes = make_layout(*p).total;
     return ok();
 }
@@ -556,7 +573,7 @@ int pf_init(const pf_params* p_in, void* d_workspace, size_t workspace_bytes, vo
     const pf_params* p = &tuned;
     if (!d_workspace) return fail(PF_ERR_INVALID_ARG, "workspace is NULL");
     if (((uintptr_t)d_workspace & 255) != 0) return fail(PF_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
-    const Layout L = make_layout(*p);
+    const Layout L = make_layout(*p, true);
     if (workspace_bytes < L.total)
         return fail(PF_ERR_WORKSPACE, "workspace %zu bytes < %zu needed", workspace_bytes, L.total);
 
@@ -564,7 +581,7 @@ int pf_init(const pf_params* p_in, void* d_workspace, size_t workspace_bytes, vo
     if (!h) return fail(PF_ERR_INVALID_ARG, "out of host memory");
     DevBlock b;
     double vx, vy;
-    setup_filter(h, *p, (uint8_t*)d_workspace, (hipStream_t)hip_stream, &b, &vx, &vy);
+    setup_filter(h, *p, (uint8_t*)d_workspace, (hipStream_t)hip_stream, &b, &vx, &vy, true);
     hipError_t e = hipSuccess;
     if (p->flags & PF_FLAG_STATE_ONLY) {
         // set-up of the static step scratch on the stream's device, with that
@@ -612,7 +629,7 @@ int pf_step(pf_filter* h, const uint8_t* d_frame, int64_t row_pitch)
         tc.start = ev[4]; tc.stop = ev[5];
         e = launch_pass_a(h->p.dtype, a, h->stream, ta);
         if (e == hipSuccess) e = launch_combine(h->p.dtype, a, h->stream, tb);
-        if (e == hipSuccess) e = launch_pass_c(h->p.dtype, a, h->stream, tc);
+        if (e == hipSuccess && !a.gather) e = launch_pass_c(h->p.dtype, a, h->stream, tc);
         ++h->prof_used;
     } else {
         e = launch_step(h->p.dtype, a, h->stream);
@@ -697,15 +714,53 @@ static int export_positions(pf_filter* h, size_t off_x, size_t off_y, double* x,
     return PF_OK;
 }
 
+// The arguments of a filter that defers its resampling with set 0 pointing
+// at the set that step t wrote (the passes read set 0 unless they gather).
+static StepArgs args_of_set(const pf_filter* h, uint32_t t)
+{
+    StepArgs a = h->args;
+    if (a.gather && (t & 1u)) {
+        a.px = a.px2;
+        a.py = a.py2;
+        a.q = a.q2;
+    }
+    return a;
+}
+
+// Offsets of the propagated positions that step t wrote.
+static void prop_offsets(const pf_filter* h, uint32_t t, size_t* ox, size_t* oy)
+{
+    const bool odd = h->args.gather && (t & 1u);
+    *ox = odd ? h->L.px2 : h->L.px;
+    *oy = odd ? h->L.py2 : h->L.py;
+}
+
+// Runs the pending resampling of the latest step (pass C over the set it
+// wrote) and clears the flag in *b and on the device.
+static int materialize(pf_filter* h, DevBlock* b)
+{
+    const StepArgs a = args_of_set(h, b->t);
+    hipError_t e = launch_pass_c(h->p.dtype, a, h->stream);
+    if (e == hipSuccess) {
+        b->pend = 0;
+        e = write_block(h, *b);
+    }
+    if (e != hipSuccess) return hip_fail(h, e, "resampling of the latest step");
+    return PF_OK;
+}
+
 int pf_export(pf_filter* h, double* x, double* y, double* w_norm, int32_t* anc, uint32_t* t)
 {
     if (int rc = live(h)) return rc;
     const bool diag = (h->p.flags & PF_FLAG_DIAGNOSTICS) != 0;
     if ((w_norm || anc) && !diag) return fail(PF_ERR_INVALID_ARG, "w_norm/anc need PF_FLAG_DIAGNOSTICS");
     hipError_t e;
-    const DevBlock b = read_block(h, &e);
+    DevBlock b = read_block(h, &e);
     if (e != hipSuccess) return hip_fail(h, e, "pf_export");
     if ((w_norm || anc) && b.t == 0) return fail(PF_ERR_INVALID_ARG, "no step taken yet");
+    if ((x || y) && b.pend) {
+        if (int rc = materialize(h, &b)) return rc;
+    }
     if (int rc = export_positions(h, h->L.sx, h->L.sy, x, y, b)) return rc;
     const int64_t n = h->p.n_particles;
     if (w_norm) {
@@ -734,7 +789,9 @@ int pf_export_step(pf_filter* h, double* x_prop, double* y_prop, int32_t* disk_s
     if (b.t == 0) return fail(PF_ERR_INVALID_ARG, "no step taken yet");
     if ((x_prop || y_prop) && (h->p.flags & PF_FLAG_STATE_ONLY))
         return fail(PF_ERR_INVALID_ARG, "a PF_FLAG_STATE_ONLY filter keeps no propagated positions");
-    if (int rc = export_positions(h, h->L.px, h->L.py, x_prop, y_prop, b)) return rc;
+    size_t ox, oy;
+    prop_offsets(h, b.t, &ox, &oy);
+    if (int rc = export_positions(h, ox, oy, x_prop, y_prop, b)) return rc;
     if (disk_sum) {
         e = hipMemcpyAsync(disk_sum, at(h, h->L.dg_s), (size_t)h->p.n_particles * 4, hipMemcpyDeviceToHost,
                            h->stream);
@@ -774,6 +831,7 @@ int pf_import(pf_filter* h, const double* x, const double* y, uint32_t t)
     b.est_x = mx;
     b.est_y = my;
     b.t = t;
+    b.pend = 0;  // the imported state is the state
     const int elt = elt_of(dt);
     std::vector<uint8_t> bx((size_t)n * elt), by((size_t)n * elt);
     for (int64_t k = 0; k < n; ++k) {
@@ -823,7 +881,8 @@ int pf_profile_read(pf_filter* h, double out_ms[3], uint32_t* steps)
     hipError_t e = hipStreamSynchronize(h->stream);
     double acc[3] = {0, 0, 0};
     for (uint32_t i = 0; e == hipSuccess && i < h->prof_used; ++i) {
-        for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+        // a filter that defers its resampling runs no pass C (its events stay unused)
+        for (int k = 0; k < (h->args.gather ? 2 : 3) && e == hipSuccess; ++k) {
             float ms = 0;
             e = hipEventElapsedTime(&ms, h->prof_ev[kProfEv * i + 2 * k], h->prof_ev[kProfEv * i + 2 * k + 1]);
             acc[k] += ms;

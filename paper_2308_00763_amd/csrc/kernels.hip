@@ -233,6 +233,7 @@ struct ModeT<PF_F64> {
     struct Prop {
         double dx, dy, sx, sy;
     };
+    static __device__ __forceinline__ Val widen(Store v) { return v; }
     template <int PPT>
     static __device__ __forceinline__ void load(const void* p, int k0, Val* v)
     {
@@ -280,6 +281,7 @@ struct ModeT<PF_F32> {
     struct Prop {
         float dx, dy, sx, sy;
     };
+    static __device__ __forceinline__ Val widen(Store v) { return v; }
     template <int PPT>
     static __device__ __forceinline__ void load(const void* p, int k0, Val* v)
     {
@@ -333,6 +335,7 @@ struct ModeT<PF_F16> {
     struct Prop {
         half2_t dx, dy, sx, sy;
     };
+    static __device__ __forceinline__ Val widen(Store v) { return v; }
     template <int PPT>
     static __device__ __forceinline__ void load(const void* p, int k0, Val* v)
     {
@@ -436,6 +439,7 @@ struct ModeT<PF_BF16> {
     struct Prop {
         float dx, dy, sx, sy;
     };
+    static __device__ __forceinline__ Val widen(Store v) { return __uint_as_float((uint32_t)v << 16); }
     template <int PPT>
     static __device__ __forceinline__ void load(const void* p, int k0, Val* v)
     {
@@ -518,10 +522,46 @@ struct PassALds {
     int red_i[kMaxWavesA];
 };
 
+// Source tiles whose prefix sums and propagated positions a gathered state
+// loads at once and stages in LDS (a tracking step's output tile has two
+// owners on average, at most four in the measured workloads; with the double
+// mode's 16-byte positions, two keep four workgroups per CU).  Further
+// owners, if any, are taken one at a time from memory.
+__host__ __device__ constexpr int gather_stage(int /*dtype*/) { return 2; }
+
+// LDS of a pass A that gathers its state, used before the pass's own LDS (the
+// two share the space): slot marks, the candidate tiles' positions, and two
+// small exchanges.
+template <int DT>
+struct GatherLds {
+    using Store = typename ModeT<DT>::Store;
+    struct alignas(2 * sizeof(Store)) XY {
+        Store x, y;
+    };
+    int32_t marks[kTile];
+    XY stage[gather_stage(DT)][kTile];
+    int32_t cand[2];
+    int32_t red[4];
+};
+
+template <int DT>
+union PassAGatherLds {
+    PassALds a;
+    GatherLds<DT> g;
+};
+
+template <int DT, int PPT>
+__device__ void gather_state(const StepArgs& a, int tile, bool prev_odd, GatherLds<DT>& lds, const int* ev,
+                             typename ModeT<DT>::Val* x, typename ModeT<DT>::Val* y);
+
 // Pass A of tile `tile` of the filter described by `a`, PPT particles per
-// thread (kTile / PPT threads).
-template <int DT, int RC, int PPT, bool SCALAR_HALF = false, bool WT = false>
-__device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALds& lds)
+// thread (kTile / PPT threads).  GATHER: the filter defers its resampling
+// (StepArgs::gather): this step's outputs go to set tn mod 2, and a pending
+// resampling of the previous step is gathered for the tile's slots instead
+// of loading the state arrays.
+template <int DT, int RC, int PPT, bool SCALAR_HALF = false, bool WT = false, bool GATHER = false>
+__device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALds& lds,
+                                            GatherLds<DT>* glds = nullptr)
 {
     static_assert(!SCALAR_HALF || DT == PF_F16, "the unpacked propagation is a half-precision variant");
     using M = ModeT<DT>;
@@ -534,6 +574,19 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
     const int k0 = tile * kTile + tid * PPT;
     const int n = (int)a.n;
     const int r = RC > 0 ? RC : a.r;
+
+    // A gathering pass A loads the previous step's end-slot column (wave 0)
+    // together with the block, before it knows whether a resampling is
+    // pending (the column is in bounds either way).
+    constexpr int kEv = GATHER ? kGatherMaxTiles / 64 : 1;
+    int ev[kEv];
+    if constexpr (GATHER) {
+        if (wv == 0) {
+            const auto* ec = gbl(static_cast<const int32_t*>(a.ecol));
+#pragma unroll
+            for (int j = 0; j < kEv; ++j) ev[j] = ec[min(lane + 64 * j, (int)a.ntiles - 1)];
+        }
+    }
 
     // Origins (reduced modes): stored offsets are relative to ci, the
     // propagated ones to cn; the drift is applied minus the origin change.
@@ -550,13 +603,36 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
     }
     const typename M::Prop pr = make_prop<DT>(a, ddx, ddy);
 
+    void* out_px = a.px;
+    void* out_py = a.py;
+    void* out_q = a.q;
     typename M::Val x[PPT], y[PPT];
-    M::template load<PPT>(a.sx, k0, x);
-    M::template load<PPT>(a.sy, k0, y);
+    if constexpr (GATHER) {
+        const bool odd = (tn & 1u) != 0;
+        if (odd) {
+            out_px = a.px2;
+            out_py = a.py2;
+            out_q = a.q2;
+        }
+        if (wv == 0) {  // the column's loads complete here, with the block's
+#pragma unroll
+            for (int j = 0; j < kEv; ++j) __asm__ volatile("" ::"v"(ev[j]));
+        }
+        if (blk->pend) {  // uniform
+            gather_state<DT, PPT>(a, tile, !odd, *glds, ev, x, y);
+            __syncthreads();  // the gather's LDS is the pass's from here on
+        } else {
+            M::template load<PPT>(a.sx, k0, x);
+            M::template load<PPT>(a.sy, k0, y);
+        }
+    } else {
+        M::template load<PPT>(a.sx, k0, x);
+        M::template load<PPT>(a.sy, k0, y);
+    }
     if constexpr (SCALAR_HALF) M::template propagate_scalar<PPT>(x, y, pr, a, k0, tn);
     else M::template propagate<PPT>(x, y, pr, a, k0, tn);
-    M::template store<PPT, WT>(a.px, k0, x);
-    M::template store<PPT, WT>(a.py, k0, y);
+    M::template store<PPT, WT>(out_px, k0, x);
+    M::template store<PPT, WT>(out_py, k0, y);
 
     // Pixel cells, clamped to where clamping the disk pixels changes nothing.
     const int lox = -(r - 1), hix = a.W - 1 + (r - 1);
@@ -746,11 +822,11 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
         q[i] = v < incl ? v : incl;
     }
     if constexpr (DT == PF_F64) {
-        auto* qp = gbl(reinterpret_cast<double2_t*>(static_cast<double*>(a.q) + k0));
+        auto* qp = gbl(reinterpret_cast<double2_t*>(static_cast<double*>(out_q) + k0));
 #pragma unroll
         for (int i = 0; i < PPT / 2; ++i) put<WT>(qp + i, double2_t{q[2 * i], q[2 * i + 1]});
     } else {
-        auto* qp = gbl(reinterpret_cast<float2_t*>(static_cast<float*>(a.q) + k0));
+        auto* qp = gbl(reinterpret_cast<float2_t*>(static_cast<float*>(out_q) + k0));
         if constexpr (WT && PPT % 4 == 0) {  // one 16-byte store per four particles
 #pragma unroll
             for (int i = 0; i < PPT / 4; ++i)
@@ -788,11 +864,27 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
     }
 }
 
-template <int DT, int RC, int PPT, bool SCALAR_HALF = false, bool WT = false>
+// Tile of workgroup b when consecutive tiles should share an XCD: workgroups
+// are dispatched to the 8 XCDs in turn (b mod 8), and XCD x takes a
+// contiguous range of tiles (a bijection of [0, nt) for any nt).
+__device__ __forceinline__ int xcd_tile(int b, int nt)
+{
+    const int x = b & 7, r = b >> 3, q = nt >> 3, rem = nt & 7;
+    return x * q + min(x, rem) + r;
+}
+
+template <int DT, int RC, int PPT, bool SCALAR_HALF = false, bool WT = false, bool GATHER = false>
 __global__ __launch_bounds__(kTile / PPT) void pass_a_kernel(StepArgs a)
 {
-    __shared__ PassALds lds;
-    pass_a_tile<DT, RC, PPT, SCALAR_HALF, WT>(a, blockIdx.x, lds);
+    if constexpr (GATHER) {
+        // consecutive output tiles mostly gather from the same source tiles:
+        // on one XCD, the second reads them from its L2
+        __shared__ PassAGatherLds<DT> lds;
+        pass_a_tile<DT, RC, PPT, SCALAR_HALF, WT, GATHER>(a, xcd_tile((int)blockIdx.x, a.ntiles), lds.a, &lds.g);
+    } else {
+        __shared__ PassALds lds;
+        pass_a_tile<DT, RC, PPT, SCALAR_HALF, WT, GATHER>(a, blockIdx.x, lds);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -940,6 +1032,158 @@ template <int DT>
 using TileSlotsT = TileSlots<DT == PF_F64 ? PF_F64 : PF_F32>;
 
 // ---------------------------------------------------------------------------
+// Deferred resampling.  A single FP64 filter of at most kGatherMaxTiles tiles
+// does not run pass C after its combine: the resampled state that pass C would
+// write is defined by the step's propagated positions and prefix sums (set t
+// mod 2), its table, block and end-slot column, and the next step's pass A
+// gathers, for its own tile's slots [lo, hi), exactly the particles that
+// pass C would have copied there.  The end slots of a source tile's
+// particles are pass C's (TileSlots::of of the same prefix sums, raised to
+// the tile's first slot, the last particle ending at the tile's end slot), a
+// particle k owning the slots from the end slot of particle k - 1 (or the
+// tile's first slot) up to its own.  The source tiles that own [lo, hi) are
+// those from the one holding slot lo to the one holding slot hi - 1 (counted
+// from the end-slot column: slot s lies in the tile whose index is the
+// number of tiles before the last that end at or before s); every particle
+// of theirs whose slots meet [lo, hi) marks the first of them, and an
+// inclusive maximum scan over the tile's slots gives every slot its owner
+// (pass C's fill, over output slots instead of one source tile's slots).
+// So the gathered state is bit for bit the state pass C would have written.
+template <int DT, int PPT>
+__device__ void gather_state(const StepArgs& a, int tile, bool prev_odd, GatherLds<DT>& lds, const int* ev,
+                             typename ModeT<DT>::Val* x, typename ModeT<DT>::Val* y)
+{
+    static_assert(PPT == 4 && kTile / PPT == 256, "gathered state: 256 threads, four slots each");
+    using M = ModeT<DT>;
+    using Store = typename M::Store;
+    using XY = typename GatherLds<DT>::XY;
+    using Q = typename std::conditional<DT == PF_F64, double, float>::type;
+    typedef int32_t I4 __attribute__((ext_vector_type(4)));
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int n = (int)a.n, nt = a.ntiles;
+    const int lo = tile * kTile, hi = min(lo + kTile, n);
+    const auto* qin = gbl(static_cast<const Q*>(prev_odd ? a.q2 : a.q));
+    const auto* xin = gbl(static_cast<const Store*>(prev_odd ? a.px2 : a.px));
+    const auto* yin = gbl(static_cast<const Store*>(prev_odd ? a.py2 : a.py));
+
+    // the source tiles holding slots lo and hi - 1 (wave 0, from the end-slot
+    // column loaded with the block)
+    if (wv == 0) {
+        int c0 = 0, c1 = 0;
+#pragma unroll
+        for (int j = 0; j < kGatherMaxTiles / 64; ++j) {
+            if (lane + 64 * j < nt - 1) {
+                c0 += ev[j] <= lo ? 1 : 0;
+                c1 += ev[j] <= hi - 1 ? 1 : 0;
+            }
+        }
+        c0 = wave_sum(c0);
+        c1 = wave_sum(c1);
+        if (lane == 0) {
+            lds.cand[0] = c0;
+            lds.cand[1] = c1;
+        }
+    }
+    *reinterpret_cast<I4*>(lds.marks + PPT * tid) = I4{0, 0, 0, 0};
+    __syncthreads();
+    const int c0 = __builtin_amdgcn_readfirstlane(lds.cand[0]);
+    const int c1 = __builtin_amdgcn_readfirstlane(lds.cand[1]);
+
+    // marks: particle k of candidate c (the c - c0-th) marks the first of its
+    // slots in [lo, hi) with (c - c0) kTile + k + 1.  The first S candidates'
+    // words, prefix sums and positions are loaded together (one round trip)
+    // and their positions staged in LDS; any further candidate is loaded and
+    // marked on its own, its owners' positions read from memory.
+    constexpr int S = gather_stage(DT);
+    const int k = PPT * tid;  // this thread's particles k .. k + 3, and k - 1
+    struct Cand {
+        typename TileSlotsT<DT>::Raw raw;
+        Q q[PPT + 1];
+        Store px[PPT], py[PPT];
+    };
+    auto load_cand = [&](int c, Cand& cd, bool pos) {
+        cd.raw.load(a, c);
+        const int first = c * kTile, tt = min(kTile, n - first);
+#pragma unroll
+        for (int i = 0; i <= PPT; ++i) cd.q[i] = qin[first + min(max(k - 1 + i, 0), tt - 1)];
+        if (pos) {
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) {
+                cd.px[i] = xin[first + min(k + i, tt - 1)];
+                cd.py[i] = yin[first + min(k + i, tt - 1)];
+            }
+        }
+    };
+    auto mark_cand = [&](int c, const Cand& cd) {
+        const int first = c * kTile, tt = min(kTile, n - first);
+        const TileSlotsT<DT> ts(cd.raw);
+        int e[PPT + 1];
+#pragma unroll
+        for (int i = 0; i <= PPT; ++i) {
+            const int kk = k - 1 + i;
+            e[i] = kk < 0 ? ts.Eprev : max(kk == tt - 1 ? ts.E : ts.of(cd.q[i], n), ts.Eprev);
+        }
+#pragma unroll
+        for (int i = 1; i <= PPT; ++i) {
+            const int kk = k - 1 + i, b = e[i - 1], en = e[i];
+            if (kk < tt && en > b && b < hi && en > lo) lds.marks[max(b, lo) - lo] = (c - c0) * kTile + kk + 1;
+        }
+    };
+    Cand cs[S];
+#pragma unroll
+    for (int j = 0; j < S; ++j)
+        if (c0 + j <= c1) load_cand(c0 + j, cs[j], true);  // uniform
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        if (c0 + j <= c1) {
+            mark_cand(c0 + j, cs[j]);
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) lds.stage[j][k + i] = XY{cs[j].px[i], cs[j].py[i]};
+        }
+    }
+    for (int c = c0 + S; c <= c1; ++c) {
+        Cand cd;
+        load_cand(c, cd, false);
+        mark_cand(c, cd);
+    }
+    __syncthreads();
+
+    // owners of this thread's four slots: the last mark at or before each
+    const I4 mv = *reinterpret_cast<const I4*>(lds.marks + PPT * tid);
+    int mk[PPT];
+    mk[0] = mv.x;
+    mk[1] = max(mk[0], mv.y);
+    mk[2] = max(mk[1], mv.z);
+    mk[3] = max(mk[2], mv.w);
+    const int sc = wave_incl_scan<OpMax>(mk[PPT - 1]);
+    if (lane == 63) lds.red[wv] = sc;
+    __syncthreads();
+    int carry = wave_shift_up1(sc, 0);
+    for (int w = 0; w < wv; ++w) carry = max(carry, lds.red[w]);
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+        const int slot = lo + k + i;
+        x[i] = 0;
+        y[i] = 0;
+        if (slot < hi) {
+            // every slot of [lo, hi) has an owner; the clamps only keep the
+            // reads inside the arrays
+            const int m = max(max(carry, mk[i]) - 1, 0);
+            const int cr = m / kTile, kk = m - cr * kTile;
+            if (cr < S) {
+                const XY v = lds.stage[cr][kk];
+                x[i] = M::widen(v.x);
+                y[i] = M::widen(v.y);
+            } else {
+                const int src = min(c0 * kTile + m, n - 1);
+                x[i] = M::widen(xin[src]);
+                y[i] = M::widen(yin[src]);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Combine: one workgroup per filter turns the tile records into the tile
 // table.  Every thread owns KPER consecutive tiles; the carried
 // offsets come from a two-level scan (per wave, then over the wave totals)
@@ -1066,6 +1310,7 @@ __device__ __forceinline__ void write_block(const StepArgs& a,
 {
     auto* b = gbl(a.blk);
     b->t = t;
+    b->pend = a.gather ? 1u : 0u;  // without pass C the resampling stays pending
     if constexpr (DT == PF_F64) {
         b->M = gm;
         b->Z = Z;
@@ -1294,15 +1539,34 @@ __device__ __forceinline__ void combine_filter(const StepArgs& a)
     int erun = max(e_off, wave_shift_up1(sm, e_off));
     // entry t holds the inclusive offset of tile t - 1 (zero for the first)
     T before = A::up1(run, last_prev);
+    int ek[KPER];
 #pragma unroll
     for (int k = 0; k < KPER; ++k) {
         const int t = tid * KPER + k;
         erun = max(erun, Ek[k]);
+        ek[k] = erun;
         if (t < nt) put_tab(tab + t, before, f[k], erun);
         before = o[k];
         if (t == nt - 1) {  // entry nt: the last tile's inclusive offset
             if constexpr (F64) tab[nt].off = o[k];
             else { tab[nt].off_hi = o[k].hi; tab[nt].off_lo = o[k].lo; }
+        }
+    }
+    if (a.ecol) {  // a filter that defers its resampling: the end slots once more, as a column
+        auto* ec = gbl(a.ecol);
+        if constexpr (KPER == 4) {
+            if (tid * KPER + KPER <= nt) {
+                typedef int32_t I4 __attribute__((ext_vector_type(4)));
+                *reinterpret_cast<gbl_t<I4>*>(ec + tid * KPER) = I4{ek[0], ek[1], ek[2], ek[3]};
+            } else {
+#pragma unroll
+                for (int k = 0; k < KPER; ++k)
+                    if (tid * KPER + k < nt) ec[tid * KPER + k] = ek[k];
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < KPER; ++k)
+                if (tid * KPER + k < nt) ec[tid * KPER + k] = ek[k];
         }
     }
     if (tid == 0) write_block<DT>(a, Z, gm, sx, sy, smap, tn, cnx, cny);
@@ -2230,6 +2494,13 @@ static hipError_t launch_pass_a_t(const StepArgs& a, hipStream_t s, const KTimin
         return launch1(pass_a_kernel<DT, 0, 2>, g, dim3(512), s, tm, a);
     }
     const dim3 blk(kBlockA);
+    if constexpr (DT == PF_F64) {
+        if (a.gather) {  // the previous step's resampling gathered in (never with the variants)
+            if (a.r == 5) return launch1(pass_a_kernel<DT, 5, kPPT, false, false, true>, g, blk, s, tm, a);
+            if (a.r == 8) return launch1(pass_a_kernel<DT, 8, kPPT, false, false, true>, g, blk, s, tm, a);
+            return launch1(pass_a_kernel<DT, 0, kPPT, false, false, true>, g, blk, s, tm, a);
+        }
+    }
     if constexpr (DT != PF_F64) {
         if (a.wt && !a.naive_half) {  // a short step: outputs written through the L2
             if (a.r == 5) return launch1(pass_a_kernel<DT, 5, kPPT, false, true>, g, blk, s, tm, a);
@@ -2436,7 +2707,7 @@ hipError_t launch_step(int dtype, const StepArgs& a, hipStream_t s)
 {
     hipError_t e = launch_pass_a(dtype, a, s);
     if (e == hipSuccess) e = launch_combine(dtype, a, s);
-    if (e == hipSuccess) e = launch_pass_c(dtype, a, s);
+    if (e == hipSuccess && !a.gather) e = launch_pass_c(dtype, a, s);  // else the next pass A resamples
     return e;
 }
 

@@ -40,6 +40,10 @@ constexpr int kCombClasses = 4;
 // Single FP16, BF16 and FP32 filters of at most this many tiles (2^23
 // particles) store their bulk outputs written through the L2 (StepArgs::wt).
 constexpr int kWtMaxTiles = 8192;
+// Single FP64 filters of at most this many tiles resampling systematically
+// defer the resampling of each step into the next step's pass A
+// (StepArgs::gather).
+constexpr int kGatherMaxTiles = 1024;
 
 // Particles per thread and tile size per precision mode.
 __host__ __device__ constexpr int tile_of(int /*dtype*/) { return kTile; }
@@ -49,7 +53,10 @@ __host__ __device__ constexpr int elt_of(int dtype) { return dtype == PF_F64 ? 8
 struct DevBlock {
     uint32_t t;           // steps taken; the combine advances it, so a step
                           // replayed from a captured graph draws fresh streams
-    uint32_t pad0;
+    uint32_t pend;        // 1: the latest step's resampling is pending (the
+                          // state arrays are stale; it is defined by that
+                          // step's propagated positions, prefix sums, table
+                          // and block, and the next pass A gathers it)
     int32_t ci_x, ci_y;   // reduced modes: origin cell of the stored positions
     int32_t cn_x, cn_y;   // reduced modes: origin cell of the next propagation
     double est_x, est_y;  // estimate of the latest step
@@ -110,8 +117,24 @@ struct GroupTab32 {
 struct Layout {
     int64_t n, n_pad;
     int tile, ntiles;
-    size_t blk, rec, tab, grec, gtab, sx, sy, px, py, q, dg_s, dg_w, dg_anc, cdf, s_all, total;
+    size_t blk, rec, tab, grec, gtab, sx, sy, px, py, q, dg_s, dg_w, dg_anc, cdf, s_all, px2, py2, q2, ecol, total;
 };
+
+// Whether a filter with parameters p defers its resampling into the next
+// step (the second set of propagated positions and prefix sums and the
+// end-slot column are then part of its workspace): the double mode,
+// systematic resampling, no diagnostics, variants or static scratch, at most
+// kGatherMaxTiles tiles.  Batch members never do.  (The gather reads every
+// source tile's prefix sums and positions about twice, at the start of pass
+// A; that costs less than pass C only where pass C moves the double mode's
+// bytes.)
+inline bool gather_eligible(const pf_params& p, int ntiles)
+{
+    const uint32_t off = PF_FLAG_DIAGNOSTICS | PF_FLAG_STATE_ONLY | PF_FLAG_NAIVE_LIKELIHOOD |
+                         PF_FLAG_NAIVE_RESAMPLE | PF_FLAG_NAIVE_HALF | PF_FLAG_METROPOLIS | PF_FLAG_REJECTION |
+                         PF_FLAG_GUMBEL_MAX;
+    return p.dtype == PF_F64 && !(p.flags & off) && ntiles <= kGatherMaxTiles;
+}
 
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -145,8 +168,10 @@ inline ScratchLayout make_scratch_layout(const pf_params& p, int ntiles, int64_t
 // Workspace layout: the block and the state (positions), then the step
 // scratch (absent with PF_FLAG_STATE_ONLY: those offsets are 0 and the step
 // points them into the static scratch), then the optional diagnostics and
-// variant buffers.
-inline Layout make_layout(const pf_params& p)
+// variant buffers, and, for a single filter (`single`) that defers its
+// resampling, the second set of propagated positions and prefix sums and the
+// end-slot column.
+inline Layout make_layout(const pf_params& p, bool single = false)
 {
     Layout L{};
     L.n = p.n_particles;
@@ -189,6 +214,14 @@ inline Layout make_layout(const pf_params& p)
     } else {
         L.s_all = 0;
     }
+    if (single && gather_eligible(p, L.ntiles)) {
+        L.px2 = o; o = align256(o + elt * (size_t)L.n_pad);
+        L.py2 = o; o = align256(o + elt * (size_t)L.n_pad);
+        L.q2 = o; o = align256(o + qel * (size_t)L.n_pad);
+        L.ecol = o; o = align256(o + 4 * (size_t)L.ntiles);
+    } else {
+        L.px2 = L.py2 = L.q2 = L.ecol = 0;
+    }
     L.total = o;
     return L;
 }
@@ -230,6 +263,17 @@ struct StepArgs {
     int32_t rj_cap;     // rejection resampling: most trials per slot (0: systematic)
     int32_t gumbel;     // Gumbel-max multinomial resampling
     int32_t* s_all;     // Metropolis / Gumbel-max: integer disk terms of all particles
+    // Deferred resampling (single FP64 filters, systematic resampling, at
+    // most kGatherMaxTiles tiles): pass A of step t writes its propagated
+    // positions and prefix sums to set t mod 2 (set 0: px, py, q; set 1:
+    // px2, py2, q2) and, when the block's pend flag is set, takes its state
+    // from the previous step's set, gathered through that step's table; the
+    // combine writes the tiles' end slots to ecol as well and sets pend.
+    int32_t gather;
+    void* px2;
+    void* py2;
+    void* q2;
+    int32_t* ecol;
 };
 
 // One filter of a batched step: the per-step part of its arguments.
@@ -271,7 +315,8 @@ struct KTiming {
 hipError_t static_scratch_setup(int device, uint8_t** out);
 
 // Host-side launchers (kernels.hip).  launch_step = launch_pass_a,
-// launch_combine, launch_pass_c on the same stream.
+// launch_combine, launch_pass_c on the same stream (no pass C for a filter
+// that defers its resampling).
 hipError_t launch_step(int dtype, const StepArgs& a, hipStream_t s);
 hipError_t launch_pass_a(int dtype, const StepArgs& a, hipStream_t s, const KTiming& tm = KTiming());
 hipError_t launch_combine(int dtype, const StepArgs& a, hipStream_t s, const KTiming& tm = KTiming());

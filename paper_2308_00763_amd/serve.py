@@ -22,7 +22,7 @@ batched step and estimates.  Two GPU backends keep one `pf_batch` per
 precision:
 
   * `GpuByteBackend` admits by bytes: every admitted stream gets exactly its
-    workspace (pf_workspace_bytes of its parameters) from a per-precision
+    workspace (pf_member_bytes of its parameters) from a per-precision
     device arena of the HBM budget (first fit, freed ranges coalesce), and a
     batch member is rebound to that share (pf_batch_rebind); a stream waits
     only when no free range of the arena holds its bytes (or every member
@@ -46,7 +46,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import (PF_F16, PF_F32, PF_F64, PF_BF16, Batch, PfError, make_params, pf_params,
-               pf_workspace_bytes)
+               pf_member_bytes)
 
 WS_ALIGN = 256  # workspace shares start on 256-byte boundaries
 
@@ -406,7 +406,7 @@ def plan_pool(budget_bytes: int, dtype: str, caps, weights=None):
     """Slots per class for one precision so that the pool's workspace fits
     `budget_bytes`: counts proportional to `weights` (default equal)."""
     w = np.ones(len(caps)) if weights is None else np.asarray(weights, dtype=float)
-    per = [pf_workspace_bytes(make_params(c, 64, 64, dtype)) for c in caps]
+    per = [pf_member_bytes(make_params(c, 64, 64, dtype)) for c in caps]
     scale = budget_bytes / float(np.dot(w, per))
     counts = [max(1, int(scale * wi)) for wi in w]
     return dict(zip(caps, counts))
@@ -441,7 +441,7 @@ class GpuPoolBackend:
             for k, cap in enumerate(caps):
                 self.free[dt].setdefault(cap, []).append(k)
                 self.slot_cap[(dt, k)] = cap
-                self.slot_bytes[(dt, k)] = pf_workspace_bytes(params[k])
+                self.slot_bytes[(dt, k)] = pf_member_bytes(params[k])
             for cap in self.free[dt]:
                 self.free[dt][cap].reverse()
             b._ptrs = np.zeros(n, dtype=np.uint64)
@@ -455,7 +455,7 @@ class GpuPoolBackend:
 
     def validate(self, params):
         try:
-            pf_workspace_bytes(params)
+            pf_member_bytes(params)
         except PfError as e:
             return str(e)
         dt = self._dtype_name(params.dtype)
@@ -640,9 +640,9 @@ class GpuByteBackend(GpuPoolBackend):
         for dt, budget in budgets.items():
             m = int(handles[dt])
             tiny = make_params(1, 64, 64, dt)
-            tiny_bytes = ByteArena.rounded(pf_workspace_bytes(tiny))
+            tiny_bytes = ByteArena.rounded(pf_member_bytes(tiny))
             # tiles the arena's bytes can hold at most
-            per_tile = pf_workspace_bytes(make_params(1 << 20, 64, 64, dt)) / 1024.0
+            per_tile = pf_member_bytes(make_params(1 << 20, 64, 64, dt)) / 1024.0
             cap = int(plan_factor * (budget // per_tile)) + m
             b = Batch([tiny] * m, device=device, stream=self.stream, max_tiles=cap)
             b._ptrs = np.zeros(m, dtype=np.uint64)
@@ -681,7 +681,7 @@ class GpuByteBackend(GpuPoolBackend):
 
     def validate(self, params):
         try:
-            need = pf_workspace_bytes(params)
+            need = pf_member_bytes(params)
         except PfError as e:
             return str(e)
         dt = self._dtype_name(params.dtype)
@@ -696,7 +696,7 @@ class GpuByteBackend(GpuPoolBackend):
         heap = self.free_heap[dt]
         if not heap:
             return None
-        need = pf_workspace_bytes(req.params)
+        need = pf_member_bytes(req.params)
         off = self.arenas[dt].alloc(need)
         if off is None:
             return None

@@ -42,7 +42,9 @@ def test_workspace_sizes():
     assert b16 >= (1 << 20) * (4 * 2 + 4)
     assert b16 < b64 / 2.5
     pd = pf.make_params(1 << 20, 1024, 1024, "f16", diagnostics=True)
-    assert pf.pf_workspace_bytes(pd) >= b16 + (1 << 20) * 16
+    # (a filter with diagnostics resamples at once: compare with the layout
+    # without the deferred-resampling buffers)
+    assert pf.pf_workspace_bytes(pd) >= pf.pf_member_bytes(p16) + (1 << 20) * 16
 
 
 @pytest.mark.parametrize("field,value", [
@@ -77,12 +79,31 @@ def test_null_pointers_are_rejected_without_a_device():
 def test_batch_workspace_is_the_sum_of_its_filters_plus_the_plan():
     ps = [pf.make_params(n, 256, 256, "f16", stream_id=i) for i, n in enumerate([256, 1000, 5000, 65536])]
     total = pf.pf_batch_workspace_bytes(ps)
-    singles = sum(pf.pf_workspace_bytes(p) for p in ps)
+    singles = sum(pf.pf_member_bytes(p) for p in ps)
     tiles = sum((p.n_particles + 1023) // 1024 for p in ps)
     # two plans (eager and captured steps): 32 bytes per filter and, per tile,
     # 4 for the tile map and 4 for the pass-A tile list, each
     assert total >= singles + 2 * (8 * tiles + 32 * len(ps))
     assert total < singles + 8192 + 16 * tiles + 450 * len(ps)
+
+
+def test_member_bytes_leave_out_the_deferred_resampling_buffers():
+    # an FP64 filter of its own that defers its resampling (at most 2^20
+    # particles, systematic, no diagnostics or variants) holds a second set of
+    # propagated positions (2 planes) and prefix sums and an end-slot column;
+    # a batch member does not, and neither does a filter in a reduced mode
+    for dt, elt, qel in (("f64", 8, 8), ("f32", 4, 4), ("f16", 2, 4), ("bf16", 2, 4)):
+        for n in (1, 1000, 1025, 1 << 20):
+            pad = -(-n // 1024) * 1024
+            tiles = pad // 1024
+            p = pf.make_params(n, 1024, 1024, dt)
+            extra = 2 * (-(-elt * pad // 256) * 256) + (-(-qel * pad // 256) * 256) + (-(-4 * tiles // 256) * 256)
+            if dt != "f64":
+                extra = 0
+            assert pf.pf_workspace_bytes(p) == pf.pf_member_bytes(p) + extra, (dt, n)
+        for p in (pf.make_params((1 << 20) + 1, 1024, 1024, dt), pf.make_params(5000, 1024, 1024, dt, diagnostics=True),
+                  pf.make_params(5000, 1024, 1024, dt, metropolis_steps=8), pf.make_params(5000, 1024, 1024, dt, state_only=True)):
+            assert pf.pf_workspace_bytes(p) == pf.pf_member_bytes(p)
 
 
 def test_batch_params_are_checked_per_filter():

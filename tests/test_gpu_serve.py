@@ -98,8 +98,8 @@ def test_streams_through_a_byte_budget_equal_alone_runs(plan_factor):
     # with half the arena's worth of tiles in the plan, idle members' stale
     # tiles must be parked to admit new streams
     clk = _Clock()
-    budgets = {"f16": 3 * pf.pf_workspace_bytes(pf.make_params(60000, 64, 64, "f16")),
-               "f32": 2 * pf.pf_workspace_bytes(pf.make_params(60000, 64, 64, "f32"))}
+    budgets = {"f16": 3 * pf.pf_member_bytes(pf.make_params(60000, 64, 64, "f16")),
+               "f32": 2 * pf.pf_member_bytes(pf.make_params(60000, 64, 64, "f32"))}
     be = GpuByteBackend(budgets, {"f16": 6, "f32": 4}, plan_factor=plan_factor)
     s = Scheduler(be, clock=clk, stall_timeout=10.0)
     reqs = _stream_requests(16, seed=12)
@@ -142,7 +142,7 @@ def test_rebind_to_caller_shares_and_its_refusals():
     tiny = pf.make_params(1, 64, 64, "f16")
     # plan capacity: two one-tile members plus the 49 tiles of p0
     b = pf.Batch([tiny, tiny], max_tiles=2 + 48)
-    need = pf.pf_workspace_bytes(p0)
+    need = pf.pf_member_bytes(p0)
     share = torch.empty(need + 512, dtype=torch.uint8, device="cuda:0")
     base = share.data_ptr()
     with pytest.raises(pf.PfError) as ei:   # misaligned
@@ -189,7 +189,7 @@ def test_idle_members_are_parked_when_the_plan_is_full():
                            x0=r.params.x0, y0=r.params.y0, drift=(r.params.drift_x, r.params.drift_y),
                            seed=4, stream_id=sid)
         ps.append((StreamRequest(sid, 0.0, p, T, 30.0, r.frame), dev))
-    budget = 2 * pf.pf_workspace_bytes(ps[0][0].params)
+    budget = 2 * pf.pf_member_bytes(ps[0][0].params)
     be = GpuByteBackend({"f16": budget}, {"f16": 3}, plan_factor=1.0)
     assert 41 <= be.tiles_cap["f16"] < 51
     sa = be.try_admit(ps[0][0])
@@ -221,8 +221,8 @@ def test_frameseq_streams_through_the_byte_backend_equal_alone_runs():
     # FrameSeq sources: the scheduler steps these streams from its columns
     # through the backend's array calls
     clk = _Clock()
-    budgets = {"f16": 3 * pf.pf_workspace_bytes(pf.make_params(60000, 64, 64, "f16")),
-               "f32": 2 * pf.pf_workspace_bytes(pf.make_params(60000, 64, 64, "f32"))}
+    budgets = {"f16": 3 * pf.pf_member_bytes(pf.make_params(60000, 64, 64, "f16")),
+               "f32": 2 * pf.pf_member_bytes(pf.make_params(60000, 64, 64, "f32"))}
     be = GpuByteBackend(budgets, {"f16": 6, "f32": 4})
     s = Scheduler(be, clock=clk, stall_timeout=10.0)
     reqs = _stream_requests(12, seed=31)

@@ -118,7 +118,7 @@ def test_slot_plan_fits_the_budget():
     caps = slot_classes(1000, 1_000_000)
     assert caps[0] == 1024 and caps[-1] == 1 << 20
     plan = plan_pool(2 << 30, "f16", caps)
-    used = sum(pf.pf_workspace_bytes(pf.make_params(c, 64, 64, "f16")) * k for c, k in plan.items())
+    used = sum(pf.pf_member_bytes(pf.make_params(c, 64, 64, "f16")) * k for c, k in plan.items())
     assert used <= 2 << 30 and used > 0.9 * (2 << 30)
 
 
