@@ -475,8 +475,11 @@ def run_ablation(pf, torch, frames_dev, centres, w, steps, warmup, dtypes=("f16"
             secs, _ = run_mode(pf, torch, frames_dev, centres, w, dt, steps, warmup, False, **var)
             _, prof = run_mode(pf, torch, frames_dev, centres, w, dt, steps, warmup, True, **var)
             a_ms, m_ms, c_ms, n = prof
+            # resample_us 0: an FP64 filter at the default sizes resamples in
+            # the next step's pass A (deferred resampling)
             rows[name] = dict(ms_per_step=1e3 * secs / steps, pass_a_us=1e3 * a_ms / n,
-                              combine_us=1e3 * m_ms / n, resample_us=1e3 * c_ms / n)
+                              combine_us=1e3 * m_ms / n, resample_us=1e3 * c_ms / n,
+                              resample_in_pass_a=c_ms == 0.0)
         res[dt] = rows
     return res
 
@@ -503,7 +506,8 @@ def run_resamplers(pf, torch, frames_dev, centres, w, steps, warmup, dtypes=("f1
             est = track(pf, frames_dev, centres, wl, dt, nsteps, **var)
             rms = float(np.sqrt(np.mean(np.sum((est - centres[:nsteps + 1]) ** 2, axis=1))))
             rows.append(dict(resampler=name, n_particles=wl.n_particles, ms_per_step=1e3 * secs / steps,
-                             resample_us=1e3 * prof[2] / prof[3], track_rms_vs_truth_px=rms))
+                             resample_us=1e3 * prof[2] / prof[3], resample_in_pass_a=prof[2] == 0.0,
+                             track_rms_vs_truth_px=rms))
         res[dt] = rows
     return res
 

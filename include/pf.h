@@ -230,7 +230,8 @@ int pf_init(const pf_params* p, void* d_workspace, size_t workspace_bytes, void*
  * drawn from stream (0, t, stream_id, purpose 1) (Sec. 4, resampling
  * paragraph).  An FP64 filter of at most 2^20 particles resampling
  * systematically, without diagnostics or measurement variants, at the default
- * pass-A size, defers the resampling of each step into the next step, whose first kernel
+ * pass-A and pass-C sizes, defers the resampling of each step into the next
+ * step, whose first kernel
  * gathers the resampled particles for its tiles (two kernels per step instead
  * of three); pf_export runs a pending resampling first, and every result is
  * bit-identical to resampling at once.  Asynchronous on the filter's stream; `d_frame` must stay valid

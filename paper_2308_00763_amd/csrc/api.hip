@@ -430,9 +430,9 @@ void setup_filter(pf_filter* h, const pf_params& pr, uint8_t* ws, hipStream_t st
     }
     a.s_all = (p->flags & (PF_FLAG_METROPOLIS | PF_FLAG_GUMBEL_MAX | PF_FLAG_REJECTION)) ? (int32_t*)at(h, L.s_all)
                                                                                         : nullptr;
-    // deferred resampling: at the default pass-A size (the gather assigns four
-    // slots to each of 256 threads)
-    a.gather = L.px2 != 0 && a.threads_a == kBlockA ? 1 : 0;
+    // deferred resampling: at the default sizes (the gather assigns four slots
+    // to each of 256 threads; a filter given a pass-C size wants its pass C)
+    a.gather = L.px2 != 0 && a.threads_a == kBlockA && ((p->flags >> PF_THREADS_C_SHIFT) & 0xF) == 0 ? 1 : 0;
     a.px2 = a.gather ? at(h, L.px2) : nullptr;
     a.py2 = a.gather ? at(h, L.py2) : nullptr;
     a.q2 = a.gather ? at(h, L.q2) : nullptr;
