@@ -228,7 +228,7 @@ int pf_init(const pf_params* p, void* d_workspace, size_t workspace_bytes, void*
  * the weighted mean position before resampling becomes the estimate; the
  * normalised cumulative weights are resampled systematically with the offset
  * drawn from stream (0, t, stream_id, purpose 1) (Sec. 4, resampling
- * paragraph).  An FP64 filter of at most 2^20 particles resampling
+ * paragraph).  An FP64 or FP32 filter of at most 2^20 particles resampling
  * systematically, without diagnostics or measurement variants, at the default
  * pass-A and pass-C sizes, defers the resampling of each step into the next
  * step, whose first kernel

@@ -524,10 +524,11 @@ struct PassALds {
 
 // Source tiles whose prefix sums and propagated positions a gathered state
 // loads at once and stages in LDS (a tracking step's output tile has two
-// owners on average, at most four in the measured workloads; with the double
-// mode's 16-byte positions, two keep four workgroups per CU).  Further
-// owners, if any, are taken one at a time from memory.
-__host__ __device__ constexpr int gather_stage(int /*dtype*/) { return 2; }
+// owners on average, at most four in the measured workloads; the double
+// mode's 16-byte positions stage two, to keep four workgroups per CU:
+// 37 KB of LDS in both modes).  Further owners, if any, are taken one at a
+// time from memory.
+__host__ __device__ constexpr int gather_stage(int dtype) { return dtype == PF_F64 ? 2 : 4; }
 
 // LDS of a pass A that gathers its state, used before the pass's own LDS (the
 // two share the space): slot marks, the candidate tiles' positions, and two
@@ -1032,8 +1033,8 @@ template <int DT>
 using TileSlotsT = TileSlots<DT == PF_F64 ? PF_F64 : PF_F32>;
 
 // ---------------------------------------------------------------------------
-// Deferred resampling.  A single FP64 filter of at most kGatherMaxTiles tiles
-// does not run pass C after its combine: the resampled state that pass C would
+// Deferred resampling.  A single FP64 or FP32 filter of at most
+// kGatherMaxTiles tiles does not run pass C after its combine: the resampled state that pass C would
 // write is defined by the step's propagated positions and prefix sums (set t
 // mod 2), its table, block and end-slot column, and the next step's pass A
 // gathers, for its own tile's slots [lo, hi), exactly the particles that
@@ -1096,26 +1097,52 @@ __device__ void gather_state(const StepArgs& a, int tile, bool prev_odd, GatherL
     // marked on its own, its owners' positions read from memory.
     constexpr int S = gather_stage(DT);
     const int k = PPT * tid;  // this thread's particles k .. k + 3, and k - 1
+    // A whole candidate tile is read with one vector load per array and
+    // thread (the particles k .. k + 3 are contiguous and aligned); particle
+    // k - 1's prefix sum then comes from the neighbouring lane, and lane 0
+    // loads its own.  (Element-wise loads issued several times the cache-line
+    // requests of pass A's state load and took three times as long.)  The
+    // last, partial tile is read element by element from clamped indices.
+    typedef Q Q4 __attribute__((ext_vector_type(4)));
+    typedef Store S4 __attribute__((ext_vector_type(4)));
     struct Cand {
         typename TileSlotsT<DT>::Raw raw;
-        Q q[PPT + 1];
+        Q q[PPT + 1];  // q[0] of a whole tile: lane 0's own load of particle k - 1
         Store px[PPT], py[PPT];
     };
     auto load_cand = [&](int c, Cand& cd, bool pos) {
         cd.raw.load(a, c);
         const int first = c * kTile, tt = min(kTile, n - first);
+        if (tt == kTile) {  // uniform
+            const Q4 qq = *reinterpret_cast<const gbl_t<Q4>*>(qin + first + k);
 #pragma unroll
-        for (int i = 0; i <= PPT; ++i) cd.q[i] = qin[first + min(max(k - 1 + i, 0), tt - 1)];
-        if (pos) {
+            for (int i = 0; i < PPT; ++i) cd.q[i + 1] = qq[i];
+            cd.q[0] = 0;
+            if (lane == 0 && k > 0) cd.q[0] = qin[first + k - 1];
+            if (pos) {
+                const S4 xx = *reinterpret_cast<const gbl_t<S4>*>(xin + first + k);
+                const S4 yy = *reinterpret_cast<const gbl_t<S4>*>(yin + first + k);
 #pragma unroll
-            for (int i = 0; i < PPT; ++i) {
-                cd.px[i] = xin[first + min(k + i, tt - 1)];
-                cd.py[i] = yin[first + min(k + i, tt - 1)];
+                for (int i = 0; i < PPT; ++i) {
+                    cd.px[i] = xx[i];
+                    cd.py[i] = yy[i];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i <= PPT; ++i) cd.q[i] = qin[first + min(max(k - 1 + i, 0), tt - 1)];
+            if (pos) {
+#pragma unroll
+                for (int i = 0; i < PPT; ++i) {
+                    cd.px[i] = xin[first + min(k + i, tt - 1)];
+                    cd.py[i] = yin[first + min(k + i, tt - 1)];
+                }
             }
         }
     };
-    auto mark_cand = [&](int c, const Cand& cd) {
+    auto mark_cand = [&](int c, Cand& cd) {
         const int first = c * kTile, tt = min(kTile, n - first);
+        if (tt == kTile) cd.q[0] = wave_shift_up1(cd.q[PPT], cd.q[0]);  // particle k - 1 (uniform branch)
         const TileSlotsT<DT> ts(cd.raw);
         int e[PPT + 1];
 #pragma unroll
@@ -2494,12 +2521,19 @@ static hipError_t launch_pass_a_t(const StepArgs& a, hipStream_t s, const KTimin
         return launch1(pass_a_kernel<DT, 0, 2>, g, dim3(512), s, tm, a);
     }
     const dim3 blk(kBlockA);
-    if constexpr (DT == PF_F64) {
-        if (a.gather) {  // the previous step's resampling gathered in (never with the variants)
-            if (a.r == 5) return launch1(pass_a_kernel<DT, 5, kPPT, false, false, true>, g, blk, s, tm, a);
-            if (a.r == 8) return launch1(pass_a_kernel<DT, 8, kPPT, false, false, true>, g, blk, s, tm, a);
-            return launch1(pass_a_kernel<DT, 0, kPPT, false, false, true>, g, blk, s, tm, a);
+    if constexpr (DT == PF_F64 || DT == PF_F32) {
+    if (a.gather) {  // the previous step's resampling gathered in (never with the variants)
+        if constexpr (DT != PF_F64) {
+            if (a.wt) {
+                if (a.r == 5) return launch1(pass_a_kernel<DT, 5, kPPT, false, true, true>, g, blk, s, tm, a);
+                if (a.r == 8) return launch1(pass_a_kernel<DT, 8, kPPT, false, true, true>, g, blk, s, tm, a);
+                return launch1(pass_a_kernel<DT, 0, kPPT, false, true, true>, g, blk, s, tm, a);
+            }
         }
+        if (a.r == 5) return launch1(pass_a_kernel<DT, 5, kPPT, false, false, true>, g, blk, s, tm, a);
+        if (a.r == 8) return launch1(pass_a_kernel<DT, 8, kPPT, false, false, true>, g, blk, s, tm, a);
+        return launch1(pass_a_kernel<DT, 0, kPPT, false, false, true>, g, blk, s, tm, a);
+    }
     }
     if constexpr (DT != PF_F64) {
         if (a.wt && !a.naive_half) {  // a short step: outputs written through the L2

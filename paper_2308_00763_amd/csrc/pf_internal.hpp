@@ -40,9 +40,9 @@ constexpr int kCombClasses = 4;
 // Single FP16, BF16 and FP32 filters of at most this many tiles (2^23
 // particles) store their bulk outputs written through the L2 (StepArgs::wt).
 constexpr int kWtMaxTiles = 8192;
-// Single FP64 filters of at most this many tiles resampling systematically
-// defer the resampling of each step into the next step's pass A
-// (StepArgs::gather).
+// Single FP64 and FP32 filters of at most this many tiles resampling
+// systematically defer the resampling of each step into the next step's
+// pass A (StepArgs::gather).
 constexpr int kGatherMaxTiles = 1024;
 
 // Particles per thread and tile size per precision mode.
@@ -122,18 +122,17 @@ struct Layout {
 
 // Whether a filter with parameters p defers its resampling into the next
 // step (the second set of propagated positions and prefix sums and the
-// end-slot column are then part of its workspace): the double mode,
-// systematic resampling, no diagnostics, variants or static scratch, at most
+// end-slot column are then part of its workspace): FP64 or FP32, systematic
+// resampling, no diagnostics, variants or static scratch, at most
 // kGatherMaxTiles tiles.  Batch members never do.  (The gather reads every
 // source tile's prefix sums and positions about twice, at the start of pass
-// A; that costs less than pass C only where pass C moves the double mode's
-// bytes.)
+// A; in the 16-bit modes that costs as much as the pass C it saves.)
 inline bool gather_eligible(const pf_params& p, int ntiles)
 {
     const uint32_t off = PF_FLAG_DIAGNOSTICS | PF_FLAG_STATE_ONLY | PF_FLAG_NAIVE_LIKELIHOOD |
                          PF_FLAG_NAIVE_RESAMPLE | PF_FLAG_NAIVE_HALF | PF_FLAG_METROPOLIS | PF_FLAG_REJECTION |
                          PF_FLAG_GUMBEL_MAX;
-    return p.dtype == PF_F64 && !(p.flags & off) && ntiles <= kGatherMaxTiles;
+    return (p.dtype == PF_F64 || p.dtype == PF_F32) && !(p.flags & off) && ntiles <= kGatherMaxTiles;
 }
 
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -263,8 +262,8 @@ struct StepArgs {
     int32_t rj_cap;     // rejection resampling: most trials per slot (0: systematic)
     int32_t gumbel;     // Gumbel-max multinomial resampling
     int32_t* s_all;     // Metropolis / Gumbel-max: integer disk terms of all particles
-    // Deferred resampling (single FP64 filters, systematic resampling, at
-    // most kGatherMaxTiles tiles): pass A of step t writes its propagated
+    // Deferred resampling (single FP64 and FP32 filters, systematic
+    // resampling, at most kGatherMaxTiles tiles): pass A of step t writes its propagated
     // positions and prefix sums to set t mod 2 (set 0: px, py, q; set 1:
     // px2, py2, q2) and, when the block's pend flag is set, takes its state
     // from the previous step's set, gathered through that step's table; the

@@ -1,6 +1,7 @@
-"""GPU tests of the deferred resampling of single filters: an FP64 filter of
-at most 2^20 particles resampling systematically skips pass C and the next
-step's pass A gathers the resampled particles for its tiles.  Every step must give
+"""GPU tests of the deferred resampling of single filters: an FP64 or FP32
+filter of at most 2^20 particles resampling systematically skips pass C and
+the next step's pass A gathers the resampled particles for its tiles (the
+16-bit modes resample at once and must give the same results as well).  Every step must give
 the results of resampling at once (a batch member, which always runs pass C)
 bit for bit: estimates after every step, the state exported mid-run (which
 runs the pending resampling) and at the end, the propagated positions of odd
@@ -36,7 +37,7 @@ def _same_state(a, b):
     return a["t"] == b["t"] and np.array_equal(a["x"], b["x"]) and np.array_equal(a["y"], b["y"])
 
 
-@pytest.mark.parametrize("dtype", ["f64"])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f16", "bf16"])
 @pytest.mark.parametrize("n", [1, 1000, 1023, 5000, 70001, 300001, 1 << 20])
 def test_deferred_resampling_equals_resampling_at_once(dtype, n):
     T = 10
@@ -65,13 +66,14 @@ def test_deferred_filters_run_no_pass_c():
     # a deferring filter leaves its resampling pending after each step (the
     # device block's flag, the word after the step count) and runs no pass C;
     # an export runs the pending resampling and clears the flag; a filter with
-    # diagnostics, and a filter in a reduced mode, resample at once
+    # diagnostics, with an explicit pass-C size or in a 16-bit mode resamples
+    # at once
     T = 6
     s, vid, _ = _stream(1 << 20, T, seed=17)
     res = {}
-    for dt, diag in (("f64", False), ("f64", True), ("f16", False)):
+    for dt, diag, tc in (("f32", False, None), ("f32", True, None), ("f64", False, 256), ("f16", False, None)):
         p = pf.make_params(1 << 20, SIDE, SIDE, dt, x0=s.start[0], y0=s.start[1], drift=s.velocity, seed=11,
-                           diagnostics=diag)
+                           diagnostics=diag, threads_c=tc)
         f = pf.Filter(p)
         pend = lambda: int(f.workspace[4:8].view(torch.int32).item())  # noqa: E731
         assert pend() == 0
@@ -81,17 +83,17 @@ def test_deferred_filters_run_no_pass_c():
             f.step(vid[t])
         res[(dt, diag)] = pf.pf_profile_read(f.handle)
         torch.cuda.synchronize()
-        defers = dt == "f64" and not diag
+        defers = not diag and tc is None and dt in ("f32", "f64")
         assert pend() == (1 if defers else 0)
         f.export()
         assert pend() == 0
         f.close()
-    a_ms, _, c_ms, steps = res[("f64", False)]
+    a_ms, _, c_ms, steps = res[("f32", False)]
     assert steps == 4 and a_ms > 0 and c_ms == 0.0, res
-    assert res[("f64", True)][2] > 0.0 and res[("f16", False)][2] > 0.0, res
+    assert res[("f32", True)][2] > 0.0 and res[("f64", False)][2] > 0.0 and res[("f16", False)][2] > 0.0, res
 
 
-@pytest.mark.parametrize("dtype,n", [("f64", 70001), ("f64", 1 << 20), ("f64", 3000)])
+@pytest.mark.parametrize("dtype,n", [("f32", 70001), ("f32", 1 << 20), ("f64", 3000)])
 def test_deferred_graph_replays_equal_eager_steps(dtype, n):
     # one captured step replayed; eager steps of a reference filter between
     # the replays; an export after the third replay runs the pending
