@@ -252,19 +252,37 @@ struct ModeT<PF_F64> {
         for (int i = 0; i < PPT / 2; ++i) put<WT>(q + i, double2_t{v[2 * i], v[2 * i + 1]});
     }
     // x <- x + (d + sigma z), each operation rounded (library built without
-    // contraction), as Eq. (1)-(2) are written.
+    // contraction), as Eq. (1)-(2) are written.  draw: the particles' normals;
+    // apply: the move (propagate = draw, then apply).
     template <int PPT>
-    static __device__ __forceinline__ void propagate(Val* x, Val* y, const Prop& pr, const StepArgs& a,
-                                                     int k0, uint32_t t)
+    struct Noise {
+        double zx[PPT], zy[PPT];
+    };
+    template <int PPT>
+    static __device__ __forceinline__ void draw(Noise<PPT>& z, const StepArgs& a, int k0, uint32_t t)
     {
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
             const u32x4 w = philox4x32_10((uint32_t)(k0 + i), t, a.stream_id, 0u, a.key0, a.key1);
-            double zx, zy;
-            normal_pair_f64(w, zx, zy);
-            x[i] = x[i] + (pr.dx + pr.sx * zx);
-            y[i] = y[i] + (pr.dy + pr.sy * zy);
+            normal_pair_f64(w, z.zx[i], z.zy[i]);
         }
+    }
+    template <int PPT>
+    static __device__ __forceinline__ void apply(Val* x, Val* y, const Prop& pr, const Noise<PPT>& z)
+    {
+#pragma unroll
+        for (int i = 0; i < PPT; ++i) {
+            x[i] = x[i] + (pr.dx + pr.sx * z.zx[i]);
+            y[i] = y[i] + (pr.dy + pr.sy * z.zy[i]);
+        }
+    }
+    template <int PPT>
+    static __device__ __forceinline__ void propagate(Val* x, Val* y, const Prop& pr, const StepArgs& a,
+                                                     int k0, uint32_t t)
+    {
+        Noise<PPT> z;
+        draw<PPT>(z, a, k0, t);
+        apply<PPT>(x, y, pr, z);
     }
     static __device__ __forceinline__ int cell(Val v, int /*origin*/, int lo, int hi)
     {
@@ -308,17 +326,34 @@ struct ModeT<PF_F32> {
         }
     }
     template <int PPT>
-    static __device__ __forceinline__ void propagate(Val* x, Val* y, const Prop& pr, const StepArgs& a,
-                                                     int k0, uint32_t t)
+    struct Noise {
+        float zx[PPT], zy[PPT];
+    };
+    template <int PPT>
+    static __device__ __forceinline__ void draw(Noise<PPT>& z, const StepArgs& a, int k0, uint32_t t)
     {
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
             const u32x4 w = philox4x32_10((uint32_t)(k0 + i), t, a.stream_id, 0u, a.key0, a.key1);
-            float zx, zy;
-            normal_pair_f32(w, zx, zy);
-            x[i] = x[i] + __builtin_fmaf(pr.sx, zx, pr.dx);
-            y[i] = y[i] + __builtin_fmaf(pr.sy, zy, pr.dy);
+            normal_pair_f32(w, z.zx[i], z.zy[i]);
         }
+    }
+    template <int PPT>
+    static __device__ __forceinline__ void apply(Val* x, Val* y, const Prop& pr, const Noise<PPT>& z)
+    {
+#pragma unroll
+        for (int i = 0; i < PPT; ++i) {
+            x[i] = x[i] + __builtin_fmaf(pr.sx, z.zx[i], pr.dx);
+            y[i] = y[i] + __builtin_fmaf(pr.sy, z.zy[i], pr.dy);
+        }
+    }
+    template <int PPT>
+    static __device__ __forceinline__ void propagate(Val* x, Val* y, const Prop& pr, const StepArgs& a,
+                                                     int k0, uint32_t t)
+    {
+        Noise<PPT> z;
+        draw<PPT>(z, a, k0, t);
+        apply<PPT>(x, y, pr, z);
     }
     static __device__ __forceinline__ int cell(Val v, int origin, int lo, int hi)
     {
@@ -367,8 +402,11 @@ struct ModeT<PF_F16> {
         }
     }
     template <int PPT>
-    static __device__ __forceinline__ void propagate(Val* x, Val* y, const Prop& pr, const StepArgs& a,
-                                                     int k0, uint32_t t)
+    struct Noise {
+        half2_t zx[PPT / 2], zy[PPT / 2];
+    };
+    template <int PPT>
+    static __device__ __forceinline__ void draw(Noise<PPT>& z, const StepArgs& a, int k0, uint32_t t)
     {
 #pragma unroll
         for (int i = 0; i < PPT; i += 2) {
@@ -377,15 +415,30 @@ struct ModeT<PF_F16> {
             float zx0, zy0, zx1, zy1;
             normal_pair_f32(w0, zx0, zy0);
             normal_pair_f32(w1, zx1, zy1);
-            const half2_t zx = __builtin_convertvector((float2_t){zx0, zx1}, half2_t);
-            const half2_t zy = __builtin_convertvector((float2_t){zy0, zy1}, half2_t);
+            z.zx[i / 2] = __builtin_convertvector((float2_t){zx0, zx1}, half2_t);
+            z.zy[i / 2] = __builtin_convertvector((float2_t){zy0, zy1}, half2_t);
+        }
+    }
+    template <int PPT>
+    static __device__ __forceinline__ void apply(Val* x, Val* y, const Prop& pr, const Noise<PPT>& z)
+    {
+#pragma unroll
+        for (int i = 0; i < PPT; i += 2) {
             half2_t xx = {x[i], x[i + 1]};
             half2_t yy = {y[i], y[i + 1]};
-            xx = xx + __builtin_elementwise_fma(pr.sx, zx, pr.dx);
-            yy = yy + __builtin_elementwise_fma(pr.sy, zy, pr.dy);
+            xx = xx + __builtin_elementwise_fma(pr.sx, z.zx[i / 2], pr.dx);
+            yy = yy + __builtin_elementwise_fma(pr.sy, z.zy[i / 2], pr.dy);
             x[i] = xx.x; x[i + 1] = xx.y;
             y[i] = yy.x; y[i + 1] = yy.y;
         }
+    }
+    template <int PPT>
+    static __device__ __forceinline__ void propagate(Val* x, Val* y, const Prop& pr, const StepArgs& a,
+                                                     int k0, uint32_t t)
+    {
+        Noise<PPT> z;
+        draw<PPT>(z, a, k0, t);
+        apply<PPT>(x, y, pr, z);
     }
     // The same propagation one particle at a time in scalar half arithmetic
     // (each normal cast to half on its own, then a scalar fused multiply-add
@@ -473,17 +526,34 @@ struct ModeT<PF_BF16> {
         }
     }
     template <int PPT>
-    static __device__ __forceinline__ void propagate(Val* x, Val* y, const Prop& pr, const StepArgs& a,
-                                                     int k0, uint32_t t)
+    struct Noise {
+        float zx[PPT], zy[PPT];
+    };
+    template <int PPT>
+    static __device__ __forceinline__ void draw(Noise<PPT>& z, const StepArgs& a, int k0, uint32_t t)
     {
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
             const u32x4 w = philox4x32_10((uint32_t)(k0 + i), t, a.stream_id, 0u, a.key0, a.key1);
-            float zx, zy;
-            normal_pair_f32(w, zx, zy);
-            x[i] = x[i] + __builtin_fmaf(pr.sx, zx, pr.dx);
-            y[i] = y[i] + __builtin_fmaf(pr.sy, zy, pr.dy);
+            normal_pair_f32(w, z.zx[i], z.zy[i]);
         }
+    }
+    template <int PPT>
+    static __device__ __forceinline__ void apply(Val* x, Val* y, const Prop& pr, const Noise<PPT>& z)
+    {
+#pragma unroll
+        for (int i = 0; i < PPT; ++i) {
+            x[i] = x[i] + __builtin_fmaf(pr.sx, z.zx[i], pr.dx);
+            y[i] = y[i] + __builtin_fmaf(pr.sy, z.zy[i], pr.dy);
+        }
+    }
+    template <int PPT>
+    static __device__ __forceinline__ void propagate(Val* x, Val* y, const Prop& pr, const StepArgs& a,
+                                                     int k0, uint32_t t)
+    {
+        Noise<PPT> z;
+        draw<PPT>(z, a, k0, t);
+        apply<PPT>(x, y, pr, z);
     }
     static __device__ __forceinline__ int cell(Val v, int origin, int lo, int hi)
     {
@@ -551,9 +621,9 @@ union PassAGatherLds {
     GatherLds<DT> g;
 };
 
-template <int DT, int PPT>
+template <int DT, int PPT, typename Pre>
 __device__ void gather_state(const StepArgs& a, int tile, bool prev_odd, GatherLds<DT>& lds, const int* ev,
-                             typename ModeT<DT>::Val* x, typename ModeT<DT>::Val* y);
+                             typename ModeT<DT>::Val* x, typename ModeT<DT>::Val* y, Pre&& pre);
 
 // Pass A of tile `tile` of the filter described by `a`, PPT particles per
 // thread (kTile / PPT threads).  GATHER: the filter defers its resampling
@@ -620,18 +690,37 @@ __device__ __forceinline__ void pass_a_tile(const StepArgs& a, int tile, PassALd
             for (int j = 0; j < kEv; ++j) __asm__ volatile("" ::"v"(ev[j]));
         }
         if (blk->pend) {  // uniform
-            gather_state<DT, PPT>(a, tile, !odd, *glds, ev, x, y);
-            __syncthreads();  // the gather's LDS is the pass's from here on
+            if constexpr (DT == PF_F64) {
+                // (drawn before, the double normals would hold 16 more
+                // registers through the gather: three workgroups per CU)
+                gather_state<DT, PPT>(a, tile, !odd, *glds, ev, x, y, []() {});
+                __syncthreads();  // the gather's LDS is the pass's from here on
+                M::template propagate<PPT>(x, y, pr, a, k0, tn);
+            } else {
+                // the normals are drawn while the candidates' loads are in
+                // flight (an empty use of each keeps the compiler from sinking
+                // the draws to their use after the gather)
+                typename M::template Noise<PPT> nz;
+                gather_state<DT, PPT>(a, tile, !odd, *glds, ev, x, y, [&]() {
+                    M::template draw<PPT>(nz, a, k0, tn);
+                    constexpr int kZ = (int)(sizeof(nz.zx) / sizeof(nz.zx[0]));
+#pragma unroll
+                    for (int i = 0; i < kZ; ++i) __asm__ volatile("" ::"v"(nz.zx[i]), "v"(nz.zy[i]));
+                });
+                __syncthreads();  // the gather's LDS is the pass's from here on
+                M::template apply<PPT>(x, y, pr, nz);
+            }
         } else {
             M::template load<PPT>(a.sx, k0, x);
             M::template load<PPT>(a.sy, k0, y);
+            M::template propagate<PPT>(x, y, pr, a, k0, tn);
         }
     } else {
         M::template load<PPT>(a.sx, k0, x);
         M::template load<PPT>(a.sy, k0, y);
+        if constexpr (SCALAR_HALF) M::template propagate_scalar<PPT>(x, y, pr, a, k0, tn);
+        else M::template propagate<PPT>(x, y, pr, a, k0, tn);
     }
-    if constexpr (SCALAR_HALF) M::template propagate_scalar<PPT>(x, y, pr, a, k0, tn);
-    else M::template propagate<PPT>(x, y, pr, a, k0, tn);
     M::template store<PPT, WT>(out_px, k0, x);
     M::template store<PPT, WT>(out_py, k0, y);
 
@@ -1050,9 +1139,9 @@ using TileSlotsT = TileSlots<DT == PF_F64 ? PF_F64 : PF_F32>;
 // inclusive maximum scan over the tile's slots gives every slot its owner
 // (pass C's fill, over output slots instead of one source tile's slots).
 // So the gathered state is bit for bit the state pass C would have written.
-template <int DT, int PPT>
+template <int DT, int PPT, typename Pre>
 __device__ void gather_state(const StepArgs& a, int tile, bool prev_odd, GatherLds<DT>& lds, const int* ev,
-                             typename ModeT<DT>::Val* x, typename ModeT<DT>::Val* y)
+                             typename ModeT<DT>::Val* x, typename ModeT<DT>::Val* y, Pre&& pre)
 {
     static_assert(PPT == 4 && kTile / PPT == 256, "gathered state: 256 threads, four slots each");
     using M = ModeT<DT>;
@@ -1097,52 +1186,40 @@ __device__ void gather_state(const StepArgs& a, int tile, bool prev_odd, GatherL
     // marked on its own, its owners' positions read from memory.
     constexpr int S = gather_stage(DT);
     const int k = PPT * tid;  // this thread's particles k .. k + 3, and k - 1
-    // A whole candidate tile is read with one vector load per array and
-    // thread (the particles k .. k + 3 are contiguous and aligned); particle
-    // k - 1's prefix sum then comes from the neighbouring lane, and lane 0
-    // loads its own.  (Element-wise loads issued several times the cache-line
-    // requests of pass A's state load and took three times as long.)  The
-    // last, partial tile is read element by element from clamped indices.
+    // A candidate tile is read with one vector load per array and thread
+    // (the particles k .. k + 3 are contiguous and aligned; the arrays are
+    // padded to whole tiles, so the last tile's loads stay inside them and
+    // its particles past N are never marked) and one load of particle k - 1's
+    // prefix sum.  Element-wise loads issued several times the cache-line
+    // requests of pass A's state load and took three times as long; a
+    // separate element-wise path for the last tile made the compiler wait
+    // for each candidate's loads before issuing the next one's.
     typedef Q Q4 __attribute__((ext_vector_type(4)));
     typedef Store S4 __attribute__((ext_vector_type(4)));
     struct Cand {
         typename TileSlotsT<DT>::Raw raw;
-        Q q[PPT + 1];  // q[0] of a whole tile: lane 0's own load of particle k - 1
+        Q q[PPT + 1];
         Store px[PPT], py[PPT];
     };
     auto load_cand = [&](int c, Cand& cd, bool pos) {
         cd.raw.load(a, c);
-        const int first = c * kTile, tt = min(kTile, n - first);
-        if (tt == kTile) {  // uniform
-            const Q4 qq = *reinterpret_cast<const gbl_t<Q4>*>(qin + first + k);
+        const int first = c * kTile;
+        const Q4 qq = *reinterpret_cast<const gbl_t<Q4>*>(qin + first + k);
+        cd.q[0] = qin[first + max(k - 1, 0)];
 #pragma unroll
-            for (int i = 0; i < PPT; ++i) cd.q[i + 1] = qq[i];
-            cd.q[0] = 0;
-            if (lane == 0 && k > 0) cd.q[0] = qin[first + k - 1];
-            if (pos) {
-                const S4 xx = *reinterpret_cast<const gbl_t<S4>*>(xin + first + k);
-                const S4 yy = *reinterpret_cast<const gbl_t<S4>*>(yin + first + k);
+        for (int i = 0; i < PPT; ++i) cd.q[i + 1] = qq[i];
+        if (pos) {
+            const S4 xx = *reinterpret_cast<const gbl_t<S4>*>(xin + first + k);
+            const S4 yy = *reinterpret_cast<const gbl_t<S4>*>(yin + first + k);
 #pragma unroll
-                for (int i = 0; i < PPT; ++i) {
-                    cd.px[i] = xx[i];
-                    cd.py[i] = yy[i];
-                }
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i <= PPT; ++i) cd.q[i] = qin[first + min(max(k - 1 + i, 0), tt - 1)];
-            if (pos) {
-#pragma unroll
-                for (int i = 0; i < PPT; ++i) {
-                    cd.px[i] = xin[first + min(k + i, tt - 1)];
-                    cd.py[i] = yin[first + min(k + i, tt - 1)];
-                }
+            for (int i = 0; i < PPT; ++i) {
+                cd.px[i] = xx[i];
+                cd.py[i] = yy[i];
             }
         }
     };
-    auto mark_cand = [&](int c, Cand& cd) {
+    auto mark_cand = [&](int c, const Cand& cd) {
         const int first = c * kTile, tt = min(kTile, n - first);
-        if (tt == kTile) cd.q[0] = wave_shift_up1(cd.q[PPT], cd.q[0]);  // particle k - 1 (uniform branch)
         const TileSlotsT<DT> ts(cd.raw);
         int e[PPT + 1];
 #pragma unroll
@@ -1160,6 +1237,7 @@ __device__ void gather_state(const StepArgs& a, int tile, bool prev_odd, GatherL
 #pragma unroll
     for (int j = 0; j < S; ++j)
         if (c0 + j <= c1) load_cand(c0 + j, cs[j], true);  // uniform
+    pre();  // the caller's work that needs no gathered value, while the loads are in flight
 #pragma unroll
     for (int j = 0; j < S; ++j) {
         if (c0 + j <= c1) {
