@@ -2,9 +2,11 @@
 it writes.
 
 Pass A (1024 particles per workgroup, 128/256/512 threads) and pass C (one
-tile per workgroup at a time, 64-1024 threads; timed together with the
-combine between them, which does not depend on pass C's size) are timed
-with the library's own per-kernel events, and the fastest sizes are kept.
+tile per workgroup at a time, 64-1024 threads) sizes are each timed as whole
+steps with the library's own per-kernel events (at the default sizes an FP32
+or FP64 filter of at most 2^20 particles resamples inside the next pass A
+instead of in pass C, so a size is worth what it does to the step), and the
+fastest sizes are kept.
 Results do not depend on pass C's size; pass A's size changes only the
 rounding order of the tile-local prefix sums.  This is the threads-per-block study of the paper
 (Sec. 5) turned into configuration: ``sweep`` measures every (dtype,
@@ -46,8 +48,8 @@ def bucket(n: int) -> int:
 
 def _time(params, frames, steps, warmup):
     """Mean microseconds per step of pass A and of the rest of the step (the
-    combine and pass C, or a pass C that combines for itself), from
-    dispatch-stamped events over `steps` steps after `warmup`, stepping
+    combine and pass C; no pass C for a filter that defers its resampling),
+    from dispatch-stamped events over `steps` steps after `warmup`, stepping
     through `frames`."""
     import ctypes
     f = Filter(params)
@@ -69,16 +71,22 @@ def autotune(n, width, height, frames, dtype="f16", radius=5, steps=20, warmup=5
     """Time every pass-A and pass-C size on `frames` ((T, H, W) uint8 device
     tensor, T >= 2) for a filter of n particles, `rounds` interleaved rounds
     (median per size); returns dict(threads_a, threads_c, flags, pass_a_us,
-    pass_c_us, table)."""
+    pass_c_us, table): table["pass_a"] / table["pass_c"] hold the step's
+    kernel time (us) per pass-A / pass-C size, the other size left at its
+    default (given as no size, so that a filter that defers its resampling
+    at the default sizes is timed that way), and pass_a_us / pass_c_us the
+    fastest of each."""
     times_a = {ta: [] for ta in PASS_A_THREADS}
     times_c = {tc: [] for tc in PASS_C_THREADS}
     for _ in range(rounds):
         for ta in PASS_A_THREADS:
-            p = make_params(n, width, height, dtype, radius=radius, threads_a=ta, **model)
-            times_a[ta].append(_time(p, frames, steps, warmup)[0])
+            p = make_params(n, width, height, dtype, radius=radius, threads_a=None if ta == DEFAULT_A else ta,
+                            **model)
+            times_a[ta].append(sum(_time(p, frames, steps, warmup)))
         for tc in PASS_C_THREADS:
-            p = make_params(n, width, height, dtype, radius=radius, threads_c=tc, **model)
-            times_c[tc].append(_time(p, frames, steps, warmup)[1])
+            p = make_params(n, width, height, dtype, radius=radius, threads_c=None if tc == DEFAULT_C else tc,
+                            **model)
+            times_c[tc].append(sum(_time(p, frames, steps, warmup)))
     table = {"pass_a": {k: statistics.median(v) for k, v in times_a.items()},
              "pass_c": {k: statistics.median(v) for k, v in times_c.items()}}
     ta = min(table["pass_a"], key=table["pass_a"].get)
@@ -120,8 +128,8 @@ def write_table(path, arch, rows, header=""):
     with open(path, "w") as f:
         for line in header.splitlines():
             f.write(f"# {line}\n")
-        f.write("# arch dtype bucket threads_a threads_c   (0: default size; measured pass A / pass C us "
-                "per size in the comment)\n")
+        f.write("# arch dtype bucket threads_a threads_c   (0: default size; in the comment, us per step by "
+                "pass-A size | by pass-C size)\n")
         for r in rows:
             t = r["result"]["table"]
             pa = " ".join(f"{k}:{v:.2f}" for k, v in t["pass_a"].items())
