@@ -294,7 +294,8 @@ int pf_export(pf_filter* h, double* x, double* y, double* w_norm, int32_t* anc, 
 int pf_export_step(pf_filter* h, double* x_prop, double* y_prop, int32_t* disk_sum);
 
 /* Replace the particle positions (host arrays of N doubles, absolute pixels)
- * and the step counter; weights become 1/N.  Used for checkpoint/resume and
+ * and the step counter; weights become 1/N (a pending resampling of the
+ * latest step, see pf_step, is discarded).  Used for checkpoint/resume and
  * teacher-forced comparisons.  Reduced-precision modes round each position
  * to the mode's storage precision.  Stream-ordered; waits for the copy. */
 int pf_import(pf_filter* h, const double* x, const double* y, uint32_t t);

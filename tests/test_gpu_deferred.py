@@ -147,3 +147,29 @@ def test_resume_from_a_checkpoint_of_a_deferring_filter():
         b.step(vid[t])
     assert _same_state(b.export(), want)
     b.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_import_over_a_pending_resampling(dtype):
+    # an import into a filter whose last resampling is pending replaces the
+    # state: the next steps equal those of a fresh filter given the same state
+    T = 8
+    n = 5000
+    s, vid, _ = _stream(n, T, seed=91)
+    p = _params(s, n, dtype)
+    rng = np.random.default_rng(5)
+    x = s.start[0] + rng.normal(0, 2, n)
+    y = s.start[1] + rng.normal(0, 2, n)
+    a = pf.Filter(p)
+    for t in range(1, 4):
+        a.step(vid[t])
+    a.load(x, y, 3)
+    b = pf.Filter(p)
+    b.load(x, y, 3)
+    for t in range(4, T):
+        a.step(vid[t])
+        b.step(vid[t])
+        assert np.array_equal(np.array(a.estimate()), np.array(b.estimate())), t
+    assert _same_state(a.export(), b.export())
+    a.close()
+    b.close()
