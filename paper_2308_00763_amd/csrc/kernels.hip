@@ -1341,6 +1341,18 @@ struct CombAcc<PF_F64> {
     static __device__ T min_(T a, T b) { return a < b ? a : b; }
     static __device__ T max_(T a, T b) { return a > b ? a : b; }
     static __device__ T sum_scan(T v) { return wave_incl_sum(v, 0); }
+    // the same scan on lanes 0 .. NW - 1 (NW <= 16: its steps inside the first
+    // row; the full scan's later steps add zero there)
+    template <int NW>
+    static __device__ T sum_scan_first(T v)
+    {
+        if constexpr (NW > 16) return sum_scan(v);
+        v = v + dpp<0x111>(v, 0.0);
+        if constexpr (NW > 2) v = v + dpp<0x112>(v, 0.0);
+        if constexpr (NW > 4) v = v + dpp<0x114>(v, 0.0);
+        if constexpr (NW > 8) v = v + dpp<0x118>(v, 0.0);
+        return v;
+    }
     static __device__ T last(T v) { return lane63(v); }
     static __device__ T up1(T v, T fill) { return wave_shift_up1(v, fill); }
 };
@@ -1353,6 +1365,16 @@ struct CombAcc<PF_F32> {
     static __device__ T min_(T a, T b) { return ff_min(a, b); }
     static __device__ T max_(T a, T b) { return ff_max(a, b); }
     static __device__ T sum_scan(T v) { return wave_incl_sum_ff(v); }
+    template <int NW>
+    static __device__ T sum_scan_first(T v)
+    {
+        if constexpr (NW > 16) return sum_scan(v);
+        v = ff_add(dpp_ff<0x111>(v, 0.f), v);
+        if constexpr (NW > 2) v = ff_add(dpp_ff<0x112>(v, 0.f), v);
+        if constexpr (NW > 4) v = ff_add(dpp_ff<0x114>(v, 0.f), v);
+        if constexpr (NW > 8) v = ff_add(dpp_ff<0x118>(v, 0.f), v);
+        return v;
+    }
     static __device__ T last(T v) { return ff{lane63(v.hi), lane63(v.lo)}; }
     static __device__ T up1(T v, T fill) { return ff{wave_shift_up1(v.hi, fill.hi), wave_shift_up1(v.lo, fill.lo)}; }
 };
@@ -1593,7 +1615,7 @@ __device__ __forceinline__ void combine_filter(const StepArgs& a)
         if (lane == 0) { red_x[wv] = wx; red_y[wv] = wy; }
         __syncthreads();
         T tv = lane < NW ? red_s[lane] : A::zero();
-        tv = A::sum_scan(tv);
+        tv = A::template sum_scan_first<NW>(tv);
         if (wv > 0) off = lane_at(tv, wv - 1);
         Z = lane_at(tv, NW - 1);
         sx = red_x[0];
@@ -1635,7 +1657,11 @@ __device__ __forceinline__ void combine_filter(const StepArgs& a)
         if (lane == 63) { red_e[wv] = sm; red_last[wv] = run; }
         __syncthreads();
         int tv = lane < NW ? red_e[lane] : 0;
-        tv = wave_incl_scan<OpMax>(tv);
+        tv = max(tv, dpp<0x111>(tv, 0));  // prefix maximum over lanes 0 .. NW - 1
+        if constexpr (NW > 2) tv = max(tv, dpp<0x112>(tv, 0));
+        if constexpr (NW > 4) tv = max(tv, dpp<0x114>(tv, 0));
+        if constexpr (NW > 8) tv = max(tv, dpp<0x118>(tv, 0));
+        static_assert(NW <= 16, "one combine workgroup holds at most 16 waves");
         if (wv > 0) {
             e_off = lane_at(tv, wv - 1);
             last_prev = red_last[wv - 1];
