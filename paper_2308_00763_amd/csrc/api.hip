@@ -389,12 +389,11 @@ void setup_filter(pf_filter* h, const pf_params& pr, uint8_t* ws, hipStream_t st
     h->scratch = nullptr;
     if (p->flags & PF_FLAG_STATE_ONLY) {
         // the step points these into the static scratch
-        a.rec = a.tab = a.grec = a.gtab = a.px = a.py = a.q = nullptr;
+        a.rec = a.tab = a.grec = a.px = a.py = a.q = nullptr;
     } else {
         a.rec = at(h, L.rec);
         a.tab = at(h, L.tab);
         a.grec = at(h, L.grec);
-        a.gtab = at(h, L.gtab);
         a.px = at(h, L.px);
         a.py = at(h, L.py);
         a.q = at(h, L.q);
@@ -662,7 +661,6 @@ int pf_step_static_scratch(pf_filter* h, const uint8_t* d_frame, int64_t row_pit
     a.rec = h->scratch + S.rec;
     a.tab = h->scratch + S.tab;
     a.grec = h->scratch + S.grec;
-    a.gtab = h->scratch + S.gtab;
     a.px = h->scratch + S.px;
     a.py = h->scratch + S.py;
     a.q = h->scratch + S.q;

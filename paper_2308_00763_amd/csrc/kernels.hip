@@ -1427,7 +1427,7 @@ struct SlotMap<false> {
 // block's origin cells as the step found them, read by the caller before its
 // first store, so that they come from a scalar load issued at the start and
 // not from a memory round trip at the end).  One thread.
-template <int DT>
+template <int DT, bool SET_T = true>
 __device__ __forceinline__ void write_block(const StepArgs& a,
                                            typename std::conditional<DT == PF_F64, double, ff>::type Z,
                                            typename std::conditional<DT == PF_F64, double, int>::type gm,
@@ -1436,7 +1436,7 @@ __device__ __forceinline__ void write_block(const StepArgs& a,
                                            const SlotMap<DT == PF_F64>& sm, uint32_t t, int cnx, int cny)
 {
     auto* b = gbl(a.blk);
-    b->t = t;
+    if constexpr (SET_T) b->t = t;
     b->pend = a.gather ? 1u : 0u;  // without pass C the resampling stays pending
     if constexpr (DT == PF_F64) {
         b->M = gm;
@@ -1711,23 +1711,30 @@ __global__ __launch_bounds__(NT) void combine_kernel(StepArgs a)
 
 // ---------------------------------------------------------------------------
 // Grouped combine for filters of more than 4096 tiles (combine class 3): the
-// tiles form groups of kGroupTiles, and three launches replace the single
+// tiles form groups of kGroupTiles, and two launches replace the single
 // workgroup.
 //   group:  one workgroup per group: the group maximum m_g, the tile factors
 //           f_t^g = e^{m_t - m_g}, the group-relative exclusive prefix W_t of
 //           f_t^g s_t (into the tile table), the group sum S_g and the group's
-//           estimate sums;
-//   top:    one workgroup over the groups: M = max m_g, c_g = e^{m_g - M},
-//           the group offsets O_g (exclusive scan of c_g S_g; Z is the total),
-//           the estimate, u0, R, and the groups' end slots EB_g (the end slot
-//           of O_{g+1}, made non-decreasing; the last group ends at N);
-//   finish: one workgroup per group: off_t = O_g + c_g W_t, f_t = c_g f_t^g,
-//           and the tiles' end slots from off_{t+1}, made non-decreasing from
-//           EB_{g-1} and capped at EB_g (the group's last tile ends at EB_g).
+//           estimate sums; the first workgroup advances the step count;
+//   finish: one workgroup per group.  Its first kTopThreads threads take the
+//           values over the groups from the group records: M = max m_g,
+//           c_g = e^{m_g - M}, the group offsets O_g (exclusive scan of
+//           c_g S_g; Z is the total), u0, R and the groups' end slots EB_g
+//           (the end slot of O_{g+1}, made non-decreasing; the last group
+//           ends at N).  Every workgroup computes them with the same
+//           operations on the same values, so they agree bit for bit, and
+//           the first one stores the block (estimate, Z, u0, R).  Then
+//           off_t = O_g + c_g W_t, f_t = c_g f_t^g, and the tiles' end slots
+//           from off_{t+1}, made non-decreasing from EB_{g-1} and capped at
+//           EB_g (the group's last tile ends at EB_g).
+// A separate launch for the values over the groups cost ~4.7 us per step
+// (2^24 particles: 16 groups), more than every finish workgroup spends
+// recomputing them while its tiles' entries load.
 
 constexpr int kGroupTiles = 1024;
 constexpr int kGroupWaves = kGroupTiles / 64;
-constexpr int kTopThreads = 256;  // groups of at most 2^28 / 2^20 filters' tiles
+constexpr int kTopThreads = 256;  // groups of at most 2^28 particles' tiles
 
 template <int DT>
 __global__ __launch_bounds__(kGroupTiles) void combine_group_kernel(StepArgs a)
@@ -1809,50 +1816,74 @@ __global__ __launch_bounds__(kGroupTiles) void combine_group_kernel(StepArgs a)
         gr.sx = sx;
         gr.sy = sy;
         static_cast<GRec*>(a.grec)[g] = gr;
+        // this step's count, read by every finish workgroup (nothing in this
+        // launch reads it)
+        if (g == 0) a.blk->t = a.blk->t + 1u;
     }
 }
 
 template <int DT>
-__global__ __launch_bounds__(kTopThreads) void combine_top_kernel(StepArgs a)
+__global__ __launch_bounds__(kGroupTiles) void combine_finish_kernel(StepArgs a)
 {
     constexpr bool F64 = DT == PF_F64;
-    constexpr int NW = kTopThreads / 64;
+    constexpr int NW = kTopThreads / 64;  // waves that take the values over the groups
     using A = CombAcc<F64 ? PF_F64 : PF_F32>;
     using T = typename A::T;
     using Tab = typename std::conditional<F64, TileTab64, TileTab32>::type;
     using GRec = typename std::conditional<F64, GroupRec64, GroupRec32>::type;
-    using GTab = typename std::conditional<F64, GroupTab64, GroupTab32>::type;
     using Fv = typename std::conditional<F64, double, float>::type;
     using Mx = typename std::conditional<F64, double, int>::type;
-    __shared__ Mx red_m[NW];
-    __shared__ T red_s[NW];
-    __shared__ T wave_off[NW + 1];
-    __shared__ Fv red_x[NW], red_y[NW];
-    __shared__ int red_e[NW];
+    __shared__ T s_off[kGroupTiles];
+    __shared__ int red_e[kGroupWaves];
+    __shared__ Mx top_m[NW];
+    __shared__ T top_s[NW];
+    __shared__ T top_off[NW + 1];
+    __shared__ Fv top_x[NW], top_y[NW];
+    __shared__ int top_e[NW];
+    __shared__ T g_off;     // this group's offset O_g
+    __shared__ Fv g_c;      // its factor c_g
+    __shared__ int g_e[2];  // EB_{g-1}, EB_g
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int n = (int)a.n;
+    const int g = blockIdx.x, t0 = g * kGroupTiles, t = t0 + tid;
     const int ng = (a.ntiles + kGroupTiles - 1) / kGroupTiles;
-    const bool valid = tid < ng;
-    int cnx, cny;
-    read_cells<F64>(a, cnx, cny);
-    const uint32_t tn = a.blk->t + 1u;  // this step (thread 0 advances the count at the end)
-    GRec gr{};
-    if (valid) gr = static_cast<const GRec*>(a.grec)[tid];
-    Mx m = F64 ? (Mx)-INFINITY : (Mx)INT32_MIN;
+    const int mt = min(kGroupTiles, a.ntiles - t0);
+    const bool valid = tid < mt;
+    Tab* tab = static_cast<Tab*>(a.tab);
+    // this tile's group-relative entry: its load is in flight while the
+    // values over the groups are computed
+    T W = A::zero();
+    Fv fg = 0;
     if (valid) {
+        if constexpr (F64) W = tab[t].off; else W = ff{tab[t].off_hi, tab[t].off_lo};
+        fg = tab[t].f;
+    }
+    const uint32_t tn = a.blk->t;  // this step (the group launch advanced the count)
+    int cnx = 0, cny = 0;
+    if (g == 0) read_cells<F64>(a, cnx, cny);  // the first workgroup stores the block
+
+    // values over the groups, on threads 0 .. kTopThreads - 1 (thread i: group i)
+    const bool top = tid < kTopThreads;  // whole waves
+    const bool gv = tid < ng;
+    GRec gr{};
+    if (gv) gr = static_cast<const GRec*>(a.grec)[tid];
+    Mx m = F64 ? (Mx)-INFINITY : (Mx)INT32_MIN;
+    if (gv) {
         if constexpr (F64) m = gr.m; else m = gr.smax;
     }
-    m = wave_max(m);
-    if (lane == 0) red_m[wv] = m;
+    if (top) {
+        m = wave_max(m);
+        if (lane == 0) top_m[wv] = m;
+    }
     __syncthreads();
-    Mx gm = red_m[0];
+    Mx gm = top_m[0];
 #pragma unroll
-    for (int w = 1; w < NW; ++w) gm = red_m[w] > gm ? red_m[w] : gm;
+    for (int w = 1; w < NW; ++w) gm = top_m[w] > gm ? top_m[w] : gm;
 
     Fv c = 0, ex = 0, ey = 0;
-    T v = A::zero();
-    if (valid) {
+    T v = A::zero(), sw = A::zero();
+    if (gv) {
         if constexpr (F64) {
             c = exp(gr.m - gm);
             v = c * gr.s;
@@ -1863,114 +1894,85 @@ __global__ __launch_bounds__(kTopThreads) void combine_top_kernel(StepArgs a)
         ex = c * gr.sx;
         ey = c * gr.sy;
     }
-    const T sw = A::sum_scan(v);
-    if (lane == 63) red_s[wv] = sw;
+    if (top) {
+        sw = A::sum_scan(v);
+        if (lane == 63) top_s[wv] = sw;
+    }
     __syncthreads();
     if (wv == 0) {
-        T tv = lane < NW ? red_s[lane] : A::zero();
+        T tv = lane < NW ? top_s[lane] : A::zero();
         tv = A::sum_scan(tv);
-        if (lane < NW) wave_off[lane + 1] = tv;
-        if (lane == 0) wave_off[0] = A::zero();
+        if (lane < NW) top_off[lane + 1] = tv;
+        if (lane == 0) top_off[0] = A::zero();
     }
     __syncthreads();
-    const T off = wave_off[wv];
-    const T incl = A::add(off, sw);
-    const T excl = A::up1(incl, off);
-    const T Z = wave_off[NW];
+    const T Z = top_off[NW];
     const SlotMap<F64> smap(a, Z, tn);
-    // end slot of every group (from the next group's offset), made
-    // non-decreasing; the last group ends at N
-    int e = 0;
-    if (valid) e = tid == ng - 1 ? n : smap.end_of(incl, n);
-    int sm = wave_incl_scan<OpMax>(e);
-    if (lane == 63) red_e[wv] = sm;
-    ex = wave_sum(ex);
-    ey = wave_sum(ey);
-    if (lane == 0) { red_x[wv] = ex; red_y[wv] = ey; }
-    __syncthreads();
-    int carry = 0;  // end slot of the previous waves' groups
-    for (int w = 0; w < wv; ++w) carry = max(carry, red_e[w]);
-    sm = max(sm, carry);
-    const int ep = wave_shift_up1(sm, carry);  // end slot of the previous group
-    if (valid) {
-        GTab gt{};
-        if constexpr (F64) gt.off = excl;
-        else { gt.off_hi = excl.hi; gt.off_lo = excl.lo; }
-        gt.c = c;
-        gt.Eprev = ep;
-        gt.E = sm;
-        static_cast<GTab*>(a.gtab)[tid] = gt;
+    T excl = A::zero();
+    int sm = 0;
+    if (top) {
+        const T off = top_off[wv];
+        const T incl = A::add(off, sw);
+        excl = A::up1(incl, off);
+        // end slot of every group (from the next group's offset), made
+        // non-decreasing; the last group ends at N
+        int e = 0;
+        if (gv) e = tid == ng - 1 ? n : smap.end_of(incl, n);
+        sm = wave_incl_scan<OpMax>(e);
+        if (lane == 63) top_e[wv] = sm;
+        ex = wave_sum(ex);
+        ey = wave_sum(ey);
+        if (lane == 0) { top_x[wv] = ex; top_y[wv] = ey; }
     }
-    if (tid == 0) {
-        Fv sx = red_x[0], sy = red_y[0];
-        for (int w = 1; w < NW; ++w) { sx = sx + red_x[w]; sy = sy + red_y[w]; }
-        Tab* tab = static_cast<Tab*>(a.tab);
+    __syncthreads();
+    if (top) {
+        int carry = 0;  // end slot of the previous waves' groups
+        for (int w = 0; w < wv; ++w) carry = max(carry, top_e[w]);
+        sm = max(sm, carry);
+        const int ep = wave_shift_up1(sm, carry);  // end slot of the previous group
+        if (tid == g) {
+            g_off = excl;
+            g_c = c;
+            g_e[0] = ep;
+            g_e[1] = sm;
+        }
+    }
+    if (g == 0 && tid == 0) {
+        Fv sx = top_x[0], sy = top_y[0];
+        for (int w = 1; w < NW; ++w) { sx = sx + top_x[w]; sy = sy + top_y[w]; }
         if constexpr (F64) tab[a.ntiles].off = Z;
         else { tab[a.ntiles].off_hi = Z.hi; tab[a.ntiles].off_lo = Z.lo; }
-        write_block<DT>(a, Z, gm, sx, sy, smap, tn, cnx, cny);
+        write_block<DT, false>(a, Z, gm, sx, sy, smap, tn, cnx, cny);
     }
-}
+    __syncthreads();
 
-template <int DT>
-__global__ __launch_bounds__(kGroupTiles) void combine_finish_kernel(StepArgs a)
-{
-    constexpr bool F64 = DT == PF_F64;
-    using A = CombAcc<F64 ? PF_F64 : PF_F32>;
-    using T = typename A::T;
-    using Tab = typename std::conditional<F64, TileTab64, TileTab32>::type;
-    using GTab = typename std::conditional<F64, GroupTab64, GroupTab32>::type;
-    using Fv = typename std::conditional<F64, double, float>::type;
-    __shared__ T s_off[kGroupTiles];
-    __shared__ int red_e[kGroupWaves];
-
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int n = (int)a.n;
-    const int g = blockIdx.x, t0 = g * kGroupTiles, t = t0 + tid;
-    const int mt = min(kGroupTiles, a.ntiles - t0);
-    const bool valid = tid < mt;
-    const GTab gt = static_cast<const GTab*>(a.gtab)[g];
-    Tab* tab = static_cast<Tab*>(a.tab);
-    T W = A::zero();
-    Fv fg = 0;
-    if (valid) {
-        if constexpr (F64) W = tab[t].off; else W = ff{tab[t].off_hi, tab[t].off_lo};
-        fg = tab[t].f;
-    }
+    const Fv gc = g_c;
+    const int Eprev = g_e[0], E = g_e[1];
     T off;
     Fv f;
     if constexpr (F64) {
-        off = gt.off + gt.c * W;
-        f = gt.c * fg;
+        off = g_off + gc * W;
+        f = gc * fg;
     } else {
-        off = ff_add(ff{gt.off_hi, gt.off_lo}, ff_mul_f(W, gt.c));
-        f = gt.c * fg;
+        off = ff_add(g_off, ff_mul_f(W, gc));
+        f = gc * fg;
     }
     s_off[tid] = off;
     __syncthreads();
     // the end slot of tile t comes from off_{t+1}; the group's last tile
     // ends where the group does
-    const DevBlock* b = a.blk;
     int e = 0;
     if (valid) {
-        if (tid == mt - 1) {
-            e = gt.E;
-        } else {
-            if constexpr (F64) {
-                e = slot_end_of(b->R * s_off[tid + 1] + (-b->u0), n);
-            } else {
-                const ff R{b->R_hi, b->R_lo}, mu0{-b->u0_hi, -b->u0_lo};
-                e = slot_end_of(ff_add(ff_mul(R, s_off[tid + 1]), mu0), n);
-            }
-        }
-        e = min(max(e, gt.Eprev), gt.E);
+        e = tid == mt - 1 ? E : smap.end_of(s_off[tid + 1], n);
+        e = min(max(e, Eprev), E);
     }
-    int sm = wave_incl_scan<OpMax>(e);
-    if (lane == 63) red_e[wv] = sm;
+    int se = wave_incl_scan<OpMax>(e);
+    if (lane == 63) red_e[wv] = se;
     __syncthreads();
-    for (int w = 0; w < wv; ++w) sm = max(sm, red_e[w]);
+    for (int w = 0; w < wv; ++w) se = max(se, red_e[w]);
     if (valid) {
         tab[t].f = f;
-        tab[t].E = sm;
+        tab[t].E = se;
         if constexpr (F64) tab[t].off = off;
         else { tab[t].off_hi = off.hi; tab[t].off_lo = off.lo; }
     }
@@ -2736,7 +2738,6 @@ static hipError_t launch_combine_grouped(const StepArgs& a, hipStream_t s, const
     t0.start = tm.start;
     t2.stop = tm.stop;
     hipError_t e = launch1(combine_group_kernel<DT>, gg, dim3(kGroupTiles), s, t0, a);
-    if (e == hipSuccess) e = launch1(combine_top_kernel<DT>, dim3(1), dim3(kTopThreads), s, KTiming(), a);
     if (e == hipSuccess) e = launch1(combine_finish_kernel<DT>, gg, dim3(kGroupTiles), s, t2, a);
     return e;
 }
@@ -2895,7 +2896,7 @@ hipError_t launch_fill(int dtype, const StepArgs& a, double vx, double vy, hipSt
 
 // ---------------------------------------------------------------------------
 // Static step scratch of the filters created with PF_FLAG_STATE_ONLY: the
-// tile records and table, group records and table, propagated positions and
+// tile records and table, group records, propagated positions and
 // tile prefix sums of one step, for callers that cannot allocate.  Each
 // device holds its own copy at its own address; the array's name is only a
 // host-side stand-in, so host code uses the address that

@@ -92,8 +92,7 @@ struct TileTab32 {
 };
 
 // Grouped combine (filters of more than 4096 tiles, groups of 1024 tiles):
-// per group, its maximum and sums relative to it, then its carried offset,
-// factor e^{m_g - M} and end slots.
+// per group, its maximum and sums relative to it.
 struct GroupRec64 {
     double m, s, sx, sy;
 };
@@ -102,22 +101,12 @@ struct GroupRec32 {
     float s_hi, s_lo, sx, sy;
     int32_t pad[3];
 };
-struct GroupTab64 {
-    double off, c;
-    int32_t Eprev, E;
-    int32_t pad[2];
-};
-struct GroupTab32 {
-    float off_hi, off_lo, c;
-    int32_t Eprev, E;
-    int32_t pad[3];
-};
 
 // Workspace layout; offsets in bytes from the workspace base.
 struct Layout {
     int64_t n, n_pad;
     int tile, ntiles;
-    size_t blk, rec, tab, grec, gtab, sx, sy, px, py, q, dg_s, dg_w, dg_anc, cdf, s_all, px2, py2, q2, ecol, total;
+    size_t blk, rec, tab, grec, sx, sy, px, py, q, dg_s, dg_w, dg_anc, cdf, s_all, px2, py2, q2, ecol, total;
 };
 
 // Whether a filter with parameters p defers its resampling into the next
@@ -138,10 +127,10 @@ inline bool gather_eligible(const pf_params& p, int ntiles)
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // Step scratch of a filter: the sections one step writes before it reads
-// them (tile records and table, group records and table, propagated
+// them (tile records and table, group records, propagated
 // positions, tile prefix sums); offsets relative to the scratch's base.
 struct ScratchLayout {
-    size_t rec, tab, grec, gtab, px, py, q, total;
+    size_t rec, tab, grec, px, py, q, total;
 };
 
 inline ScratchLayout make_scratch_layout(const pf_params& p, int ntiles, int64_t n_pad)
@@ -156,7 +145,6 @@ inline ScratchLayout make_scratch_layout(const pf_params& p, int ntiles, int64_t
     S.rec = o; o = align256(o + rec * (size_t)ntiles);
     S.tab = o; o = align256(o + tab * (size_t)(ntiles + 1));
     S.grec = o; o = align256(o + 32 * ngroups);
-    S.gtab = o; o = align256(o + 32 * ngroups);
     S.px = o; o = align256(o + elt * (size_t)n_pad);
     S.py = o; o = align256(o + elt * (size_t)n_pad);
     S.q = o; o = align256(o + qel * (size_t)n_pad);
@@ -184,13 +172,12 @@ inline Layout make_layout(const pf_params& p, bool single = false)
     L.sx = o; o = align256(o + elt * (size_t)L.n_pad);
     L.sy = o; o = align256(o + elt * (size_t)L.n_pad);
     if (p.flags & PF_FLAG_STATE_ONLY) {
-        L.rec = L.tab = L.grec = L.gtab = L.px = L.py = L.q = 0;
+        L.rec = L.tab = L.grec = L.px = L.py = L.q = 0;
     } else {
         const ScratchLayout S = make_scratch_layout(p, L.ntiles, L.n_pad);
         L.rec = o + S.rec;
         L.tab = o + S.tab;
         L.grec = o + S.grec;
-        L.gtab = o + S.gtab;
         L.px = o + S.px;
         L.py = o + S.py;
         L.q = o + S.q;
@@ -240,8 +227,7 @@ struct StepArgs {
     DevBlock* blk;
     void* rec;
     void* tab;
-    void* grec;         // grouped combine: per-group records and table
-    void* gtab;
+    void* grec;         // grouped combine: per-group records
     void* sx;
     void* sy;
     void* px;
