@@ -2521,9 +2521,13 @@ __device__ __forceinline__ StepArgs batch_args_of(const BatchArgs& b, int fid)
 // complete since the last tile), and so are the arguments of t + 2G, the
 // entry of t + 3G and the map word of t + 4G -- one round trip, not three,
 // in front of each tile.  A tile past its filter's tiles (a plan captured
-// before a smaller re-initialisation) is skipped.
+// before a smaller re-initialisation) is skipped.  The pipelined arguments
+// live in scalar registers; left to itself the compiler takes 100 of them,
+// which allows 7 waves per SIMD, so at least 8 workgroups per CU are asked
+// for (72 SGPRs in the 16-bit modes, which then run 9 per CU, as many as
+// their VGPRs and LDS allow).
 template <int DT>
-__global__ __launch_bounds__(pass_c_threads(DT, 1 << 30), 6) void pass_c_batch_kernel(BatchArgs b)
+__global__ __launch_bounds__(pass_c_threads(DT, 1 << 30), 8) void pass_c_batch_kernel(BatchArgs b)
 {
     constexpr int BC = pass_c_threads(DT, 1 << 30);
     __shared__ PassCLds<DT> lds;
